@@ -1,0 +1,209 @@
+/*
+ * sem.h -- C ABI of an MI355X (gfx950) engine for the data-parallel hot path
+ * of a spectral-element incompressible-flow solver: the matrix-free local
+ * Poisson/Helmholtz operator on order-N hexahedra, the direct-stiffness
+ * gather-scatter Q Q^T, and a Jacobi-preconditioned conjugate-gradient solve.
+ *
+ * Paper: "Strong Scaling of OpenACC enabled Nek5000 on several GPU based HPC
+ * systems" (arXiv 2109.03592).  Section 2 defines the spectral element
+ * discretisation (GLL tensor-product basis, global face exchange versus local
+ * matrix-free work) and the pressure Poisson problem (Eq. 5); Algorithm 1
+ * (axhelm) defines the local operator.
+ *
+ * Conventions for every entry point:
+ *  - Returns SEM_OK (0) or a nonzero sem_status; sem_last_error() gives a
+ *    thread-local message.  No C++ exception or abort crosses the ABI.
+ *  - "E-vector" = one value per local node, layout [E][(N+1)^3] with the node
+ *    index i + (N+1) j + (N+1)^2 k (i fastest), element e = ex + nx (ey + ny ez).
+ *    This is Algorithm 1's u(lx1,ly1,lz1,e).
+ *  - Pointers named "device" are HIP device pointers owned by the caller; the
+ *    library never frees them.  "host" pointers are ordinary host memory.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Operators are
+ *    enqueued asynchronously; entry points that return host data synchronise
+ *    the stream first.
+ *  - Everything runs in HIP kernels on the GPU; there is no CPU fallback.  A
+ *    machine without a usable gfx950 device gets SEM_EHIP from sem_setup.
+ */
+#ifndef SEM_H
+#define SEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int sem_status;
+enum {
+    SEM_OK = 0,
+    SEM_EINVAL = 1,      /* bad argument or descriptor                        */
+    SEM_ENOMEM = 2,      /* device or host allocation failed                  */
+    SEM_EHIP = 3,        /* a HIP runtime call failed                         */
+    SEM_ENOCONV = 4,     /* solve hit max_iter; x holds the last iterate      */
+    SEM_EBREAKDOWN = 5,  /* CG breakdown: p.Ap <= 0 or not finite             */
+    SEM_EBUDGET = 6,     /* request exceeds a memory budget or slot limit     */
+    SEM_EUNSUPPORTED = 7 /* valid request the library was not built for       */
+};
+
+enum { SEM_MAP_BOX = 0, SEM_MAP_PIPE_SQ2DISK = 1 };
+enum { SEM_FP64 = 0, SEM_FP32 = 1 };          /* element type of E-vectors       */
+enum { SEM_PREC_FP64 = 0, SEM_PREC_MIXED = 1 }; /* solve precision               */
+enum { SEM_WITH_FP32 = 1 };                   /* sem_mesh_desc.precision_flags  */
+enum { SEM_MAX_ORDER = 12 };                  /* largest N with built kernels   */
+
+typedef struct sem_mesh sem_mesh;
+
+/* Mesh descriptor: an nel[0] x nel[1] x nel[2] lattice of hexahedra of order N.
+ *  mapping SEM_MAP_BOX: each element is the trilinear image of its 8 vertices,
+ *    taken from `vertices` when non-NULL ((nx+1)(ny+1)(nz+1) x 3 doubles, x
+ *    fastest, host memory, read during sem_setup only) or else from the uniform
+ *    lattice on [lo, hi].
+ *  mapping SEM_MAP_PIPE_SQ2DISK: the square [lo0,hi0] x [lo1,hi1] (normally
+ *    [-1,1]^2) is mapped to the unit disk by (X sqrt(1-Y^2/2), Y sqrt(1-X^2/2));
+ *    z is uniform.  The map is singular where the square's corners are; the
+ *    quadrature points there are dropped (geometric factors and mass set to 0).
+ *  periodic[d]: identify the last node layer with the first along axis d.
+ *  dirichlet_faces: bit 2d (2d+1) = homogeneous Dirichlet on the low (high)
+ *    face of axis d; -1 = every non-periodic face.
+ *  precision_flags: SEM_WITH_FP32 also builds FP32 copies of the geometric
+ *    factors and the Jacobi diagonal (needed for SEM_FP32 operators and mixed
+ *    solves). */
+typedef struct {
+    int N;
+    int nel[3];
+    int periodic[3];
+    double lo[3], hi[3];
+    int mapping;
+    const double *vertices;
+    int dirichlet_faces;
+    int precision_flags;
+} sem_mesh_desc;
+
+typedef struct {
+    int N;
+    int64_t E;
+    int64_t n_local;          /* E (N+1)^3                                   */
+    int64_t n_global;         /* unique global nodes                          */
+    int64_t n_shared_local;   /* local nodes whose global node has mult >= 2  */
+    int64_t n_shared_global;  /* global nodes with mult >= 2                  */
+    int64_t n_masked_global;  /* global nodes on Dirichlet faces              */
+    int64_t n_unmasked_global;
+    int64_t gs_plan_ids;      /* global ids the gather-scatter visits         */
+    int64_t gs_plan_sum_ids;  /* the first gs_plan_sum_ids of them are summed, the
+                                 rest (Dirichlet ids) are zeroed               */
+    int64_t gs_plan_len;      /* local entries listed by the plan             */
+    size_t device_bytes;      /* device memory held by the handle             */
+} sem_mesh_info;
+
+const char *sem_last_error(void);
+const char *sem_version(void);
+
+/* Build a mesh on the current HIP device (section 2: GLL rule, element
+ * geometry, global numbering, gather-scatter plan, Jacobi diagonal) and
+ * upload it.  The handle owns every device buffer it allocates.
+ * Errors: SEM_EINVAL (N outside 1..SEM_MAX_ORDER, non-positive element counts,
+ * degenerate geometry), SEM_ENOMEM, SEM_EHIP. */
+sem_status sem_setup(const sem_mesh_desc *desc, void *stream, sem_mesh **out);
+sem_status sem_free(sem_mesh *mesh);
+sem_status sem_info(const sem_mesh *mesh, sem_mesh_info *info);
+
+/* Host copies of set-up data, for checking.
+ *  sem_export_gll: GLL nodes xi[N+1], weights w[N+1], D[(N+1)^2] with
+ *    D[i*(N+1)+l] = derivative of the l-th Lagrange interpolant at xi_i.
+ *  sem_export_maps: per local node (n_local entries each; NULL skips):
+ *    glob_id (lexicographic: a + gx (b + gy c) with lattice indices
+ *    a = ex N + i etc., reduced on periodic axes), mult (copies of that
+ *    global node), mask (1 on Dirichlet faces).
+ *  sem_export_geom: G[6][n_local] (g1..g6 = G_rr, G_ss, G_tt, G_rs, G_rt, G_st,
+ *    Algorithm 1's factors with W det J folded in), B[n_local] (W det J),
+ *    invdiag[n_local] (inverse assembled diagonal, 0 on masked nodes).
+ *  sem_export_coords: xyz[3][n_local] node coordinates. */
+sem_status sem_export_gll(int N, double *xi, double *w, double *D);
+sem_status sem_export_maps(const sem_mesh *mesh, int64_t *glob_id, uint8_t *mult, uint8_t *mask);
+sem_status sem_export_geom(const sem_mesh *mesh, double *G, double *B, double *invdiag);
+sem_status sem_export_coords(const sem_mesh *mesh, double *xyz);
+
+/* Host-only set-up, for checking on machines without a GPU: runs the host
+ * part of sem_setup (GLL rule, coordinates, geometric factors, numbering,
+ * gather-scatter plan, Jacobi diagonal) without touching any device, and
+ * copies its products out.  info receives the sizes (device_bytes = 0).
+ * Arrays as in the exports above; gs_off[gs_plan_ids + 1] and
+ * gs_idx[gs_plan_len] receive the plan (global ids in ascending order, summed
+ * ids first; each id's local copies in ascending local index).  Any array
+ * pointer may be NULL. */
+sem_status sem_host_setup(const sem_mesh_desc *desc, sem_mesh_info *info, int64_t *glob_id, uint8_t *mult,
+                          uint8_t *mask, double *G, double *B, double *invdiag, int32_t *gs_off,
+                          int32_t *gs_idx);
+
+/* Local operator, Algorithm 1: w = A_L u element by element (no
+ * gather-scatter).  u, w: device E-vectors of `dtype` (SEM_FP64 or SEM_FP32;
+ * FP32 needs SEM_WITH_FP32).  opt_dot (device double, may be NULL) receives
+ * sum_local u.w, which equals u^T A u when u is continuous.  u and w must not
+ * overlap. */
+sem_status sem_ax(sem_mesh *mesh, int dtype, const void *u, void *w, double *opt_dot, void *stream);
+
+/* Direct-stiffness summation and Dirichlet mask, in place (section 2, the
+ * global exchange of element face values): every copy of a global node gets
+ * the sum of all its copies, summed in ascending local index; nodes on
+ * Dirichlet faces get 0.  v: device E-vector of `dtype`. */
+sem_status sem_gs(sem_mesh *mesh, int dtype, void *v, void *stream);
+
+/* w = mask(Q Q^T A_L u): sem_ax followed by sem_gs. */
+sem_status sem_axgs(sem_mesh *mesh, int dtype, const void *u, void *w, void *stream);
+
+/* b = mask(Q Q^T (B f)): weak-form right-hand side of a forcing f (device
+ * FP64 E-vectors). */
+sem_status sem_mass(sem_mesh *mesh, const double *f, double *b, void *stream);
+
+/* u_local = mask(Q v): copy one value per global node (device FP64, n_global,
+ * indexed by the glob_id of sem_export_maps) to every local copy. */
+sem_status sem_scatter(sem_mesh *mesh, const double *v_global, double *u_local, void *stream);
+
+/* Solve options.  sem_solve_opts_default fills tol=1e-10, max_iter=5000,
+ * precision=SEM_PREC_FP64, inner_tol=1e-4, inner_max_iter=max_iter,
+ * poll_every=16, use_graph=1, fixed_iters=0, x0_given=0. */
+typedef struct {
+    double tol;          /* stop when ||b - A x|| <= tol ||b|| (unique-dof 2-norm) */
+    int max_iter;        /* limit on PCG iterations (inner ones for mixed)         */
+    int precision;       /* SEM_PREC_FP64 or SEM_PREC_MIXED                        */
+    double inner_tol;    /* mixed: relative tolerance of each FP32 inner solve     */
+    int inner_max_iter;  /* mixed: limit per inner solve                           */
+    int poll_every;      /* iterations between host convergence checks            */
+    int use_graph;       /* replay poll_every iterations as one hipGraph           */
+    int fixed_iters;     /* > 0: run exactly this many FP64 iterations, no polling,
+                            no final residual (throughput measurement)           */
+    int x0_given;        /* 1: x holds the initial guess; 0: start from x = 0      */
+} sem_solve_opts;
+
+typedef struct {
+    int status;               /* same value the call returns                  */
+    int iterations;           /* PCG iterations (FP64, or FP32 inner total)    */
+    int outer_iterations;     /* mixed: refinement steps; FP64: restarts + 1   */
+    double rel_residual;      /* true ||b - A x|| / ||b|| at exit (FP64)        */
+    double bnorm;             /* ||b||                                         */
+    double seconds;           /* wall time of the call                         */
+} sem_solve_stats;
+
+void sem_solve_opts_default(sem_solve_opts *opts);
+
+/* Jacobi-PCG on the masked assembled system A x = b (section 2 Eq. 5 solved
+ * by a preconditioned Krylov method; the preconditioner is the inverse
+ * assembled diagonal).  b: device FP64 E-vector, continuous (all copies of a
+ * global node equal) and masked.  x: device FP64 E-vector, in/out.
+ * FP64: dot products, alpha and beta stay on the device; the host reads the
+ * residual every poll_every iterations.  When the recursive residual meets
+ * tol the true residual b - A x is recomputed; if it does not, CG restarts
+ * from x (at most 3 times).
+ * SEM_PREC_MIXED: defect correction -- r = b - A x in FP64, an FP32 PCG solves
+ * A d = r/||r|| to inner_tol, x += ||r|| d in FP64, until the FP64 true
+ * residual meets tol.  Needs SEM_WITH_FP32.
+ * Synchronises `stream` before returning.  Errors: SEM_ENOCONV (x holds the
+ * last iterate), SEM_EBREAKDOWN, SEM_EINVAL, SEM_EHIP. */
+sem_status sem_pcg_solve(sem_mesh *mesh, const double *b, double *x, const sem_solve_opts *opts,
+                         sem_solve_stats *stats, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SEM_H */

@@ -1,0 +1,236 @@
+"""MI355X (gfx950) spectral-element Poisson engine: Python binding.
+
+Thin marshalling over the C ABI of ``include/sem.h``: every step of the path
+(operator, gather-scatter, dot products, CG updates) runs in the HIP kernels
+of ``libsem.so``.  PyTorch provides device memory and streams only.  The
+binding checks tensor device, dtype, contiguity and length before passing raw
+pointers, because the C ABI cannot.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from ._lib import (SEM_FP32, SEM_FP64, SEM_MAP_BOX, SEM_MAP_PIPE_SQ2DISK, SEM_MAX_ORDER,
+                   SEM_PREC_FP64, SEM_PREC_MIXED, SemError)
+
+__all__ = ["Mesh", "SolveResult", "SemError", "box_mesh", "pipe_mesh", "export_gll", "version",
+           "SEM_FP64", "SEM_FP32", "SEM_MAP_BOX", "SEM_MAP_PIPE_SQ2DISK", "SEM_MAX_ORDER"]
+
+
+def version() -> str:
+    return L.load().sem_version().decode()
+
+
+def _stream_handle(stream) -> Optional[int]:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+def export_gll(N: int):
+    """(xi, w, D) of the library's own GLL rule and derivative matrix."""
+    xi, w, D = np.zeros(N + 1), np.zeros(N + 1), np.zeros((N + 1, N + 1))
+    L.check(L.load().sem_export_gll(N, xi.ctypes.data, w.ctypes.data, D.ctypes.data), "sem_export_gll")
+    return xi, w, D
+
+
+@dataclass
+class SolveResult:
+    status: int
+    iterations: int
+    outer_iterations: int
+    rel_residual: float
+    bnorm: float
+    seconds: float
+
+    @property
+    def ok(self) -> bool:
+        return self.status == L.SEM_OK
+
+
+class Mesh:
+    """A structured hexahedral mesh of order N resident on the current GPU."""
+
+    def __init__(self, N: int, nel: Sequence[int], periodic=(0, 0, 0), lo=(0.0, 0.0, 0.0),
+                 hi=(1.0, 1.0, 1.0), mapping: int = SEM_MAP_BOX, vertices: Optional[np.ndarray] = None,
+                 dirichlet_faces: int = -1, with_fp32: bool = False, stream=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("paper_2109_03592_amd needs a ROCm GPU (gfx950); none is visible")
+        self._lib = L.load()
+        d = L.MeshDesc()
+        d.N = int(N)
+        d.nel[:] = [int(v) for v in nel]
+        d.periodic[:] = [int(v) for v in periodic]
+        d.lo[:] = [float(v) for v in lo]
+        d.hi[:] = [float(v) for v in hi]
+        d.mapping = int(mapping)
+        self._vert = None
+        if vertices is not None:
+            v = np.ascontiguousarray(vertices, dtype=np.float64).reshape(-1)
+            need = (d.nel[0] + 1) * (d.nel[1] + 1) * (d.nel[2] + 1) * 3
+            if v.size != need:
+                raise ValueError(f"vertices: expected {need} doubles, got {v.size}")
+            self._vert = v
+            d.vertices = v.ctypes.data_as(C.POINTER(C.c_double))
+        d.dirichlet_faces = int(dirichlet_faces)
+        d.precision_flags = L.SEM_WITH_FP32 if with_fp32 else 0
+        self.desc = d
+        self.with_fp32 = bool(with_fp32)
+        h = C.c_void_p()
+        L.check(self._lib.sem_setup(C.byref(d), _stream_handle(stream), C.byref(h)), "sem_setup")
+        self._h = h
+        info = L.MeshInfo()
+        L.check(self._lib.sem_info(h, C.byref(info)), "sem_info")
+        self.info = info
+        self.N = info.N
+        self.P = self.N + 1
+        self.E = int(info.E)
+        self.n_local = int(info.n_local)
+        self.n_global = int(info.n_global)
+        self.device = torch.device("cuda", torch.cuda.current_device())
+
+    # -- lifetime ------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.sem_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- argument checks -----------------------------------------------------
+    def _vec(self, t: torch.Tensor, name: str, dtype=None, n=None) -> int:
+        n = self.n_local if n is None else n
+        if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+            raise TypeError(f"{name}: expected a CUDA tensor")
+        if dtype is not None and t.dtype != dtype:
+            raise TypeError(f"{name}: expected {dtype}, got {t.dtype}")
+        if t.dtype not in (torch.float64, torch.float32):
+            raise TypeError(f"{name}: expected float64 or float32")
+        if not t.is_contiguous() or t.numel() != n:
+            raise ValueError(f"{name}: expected a contiguous tensor of {n} elements")
+        if t.device.index != self.device.index:
+            raise ValueError(f"{name}: tensor is on another device")
+        return t.data_ptr()
+
+    @staticmethod
+    def _dt(t: torch.Tensor) -> int:
+        if t.dtype == torch.float32:
+            return SEM_FP32
+        return SEM_FP64
+
+    def empty(self, dtype=torch.float64) -> torch.Tensor:
+        return torch.empty(self.n_local, dtype=dtype, device=self.device)
+
+    def zeros(self, dtype=torch.float64) -> torch.Tensor:
+        return torch.zeros(self.n_local, dtype=dtype, device=self.device)
+
+    # -- operators -----------------------------------------------------------
+    def ax(self, u: torch.Tensor, w: Optional[torch.Tensor] = None, dot: bool = False, stream=None):
+        """w = A_L u (no gather-scatter); with dot=True also returns sum u.w (device scalar)."""
+        w = torch.empty_like(u) if w is None else w
+        pu, pw = self._vec(u, "u"), self._vec(w, "w", dtype=u.dtype)
+        if pu == pw:
+            raise ValueError("ax: u and w must be distinct")
+        dt = torch.zeros(1, dtype=torch.float64, device=self.device) if dot else None
+        L.check(self._lib.sem_ax(self._h, self._dt(u), pu, pw, None if dt is None else dt.data_ptr(),
+                                 _stream_handle(stream)), "sem_ax")
+        return (w, dt) if dot else w
+
+    def gs(self, v: torch.Tensor, stream=None) -> torch.Tensor:
+        """In-place Q Q^T and Dirichlet mask."""
+        L.check(self._lib.sem_gs(self._h, self._dt(v), self._vec(v, "v"), _stream_handle(stream)), "sem_gs")
+        return v
+
+    def axgs(self, u: torch.Tensor, w: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """w = mask(Q Q^T A_L u)."""
+        w = torch.empty_like(u) if w is None else w
+        pu, pw = self._vec(u, "u"), self._vec(w, "w", dtype=u.dtype)
+        if pu == pw:
+            raise ValueError("axgs: u and w must be distinct")
+        L.check(self._lib.sem_axgs(self._h, self._dt(u), pu, pw, _stream_handle(stream)), "sem_axgs")
+        return w
+
+    def mass(self, f: torch.Tensor, b: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """b = mask(Q Q^T (B f))."""
+        b = torch.empty_like(f) if b is None else b
+        L.check(self._lib.sem_mass(self._h, self._vec(f, "f", torch.float64), self._vec(b, "b", torch.float64),
+                                   _stream_handle(stream)), "sem_mass")
+        return b
+
+    def scatter(self, v_global: torch.Tensor, u: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """u = mask(Q v_global)."""
+        u = self.empty() if u is None else u
+        pv = self._vec(v_global, "v_global", torch.float64, n=self.n_global)
+        L.check(self._lib.sem_scatter(self._h, pv, self._vec(u, "u", torch.float64), _stream_handle(stream)),
+                "sem_scatter")
+        return u
+
+    # -- solve -----------------------------------------------------------------
+    def solve(self, b: torch.Tensor, x: Optional[torch.Tensor] = None, tol: float = 1e-10,
+              max_iter: int = 5000, precision: str = "fp64", inner_tol: float = 1e-4,
+              inner_max_iter: int = 0, poll_every: int = 16, use_graph: bool = True,
+              fixed_iters: int = 0, stream=None, raise_on_error: bool = True) -> Tuple[torch.Tensor, SolveResult]:
+        """Jacobi-PCG for A x = b; x (if given) is the initial guess and is overwritten."""
+        o = L.SolveOpts()
+        self._lib.sem_solve_opts_default(C.byref(o))
+        o.tol, o.max_iter = float(tol), int(max_iter)
+        o.precision = SEM_PREC_MIXED if precision == "mixed" else SEM_PREC_FP64
+        o.inner_tol, o.inner_max_iter = float(inner_tol), int(inner_max_iter)
+        o.poll_every, o.use_graph, o.fixed_iters = int(poll_every), int(bool(use_graph)), int(fixed_iters)
+        o.x0_given = 0 if x is None else 1
+        x = self.zeros() if x is None else x
+        st = L.SolveStats()
+        status = self._lib.sem_pcg_solve(self._h, self._vec(b, "b", torch.float64), self._vec(x, "x", torch.float64),
+                                         C.byref(o), C.byref(st), _stream_handle(stream))
+        res = SolveResult(st.status, st.iterations, st.outer_iterations, st.rel_residual, st.bnorm, st.seconds)
+        if raise_on_error and status != L.SEM_OK:
+            raise SemError(status, "sem_pcg_solve")
+        return x, res
+
+    # -- exports ---------------------------------------------------------------
+    def export_maps(self):
+        gid = np.zeros(self.n_local, dtype=np.int64)
+        mult = np.zeros(self.n_local, dtype=np.uint8)
+        mask = np.zeros(self.n_local, dtype=np.uint8)
+        L.check(self._lib.sem_export_maps(self._h, gid.ctypes.data, mult.ctypes.data, mask.ctypes.data),
+                "sem_export_maps")
+        return gid, mult, mask
+
+    def export_geom(self):
+        G = np.zeros((6, self.n_local))
+        B = np.zeros(self.n_local)
+        inv = np.zeros(self.n_local)
+        L.check(self._lib.sem_export_geom(self._h, G.ctypes.data, B.ctypes.data, inv.ctypes.data), "sem_export_geom")
+        return G, B, inv
+
+    def export_coords(self):
+        xyz = np.zeros((3, self.n_local))
+        L.check(self._lib.sem_export_coords(self._h, xyz.ctypes.data), "sem_export_coords")
+        return xyz
+
+
+def box_mesh(N: int, nel: Sequence[int], vertices=None, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0),
+             periodic=(0, 0, 0), **kw) -> Mesh:
+    return Mesh(N, nel, periodic=periodic, lo=lo, hi=hi, mapping=SEM_MAP_BOX, vertices=vertices, **kw)
+
+
+def pipe_mesh(nx: int = 48, ny: int = 48, nz: int = 96, N: int = 7, length: float = 10.0, **kw) -> Mesh:
+    """Square [-1,1]^2 x [0,length] mapped to a circular pipe; periodic in z,
+    Dirichlet on the wall."""
+    return Mesh(N, (nx, ny, nz), periodic=(0, 0, 1), lo=(-1.0, -1.0, 0.0), hi=(1.0, 1.0, length),
+                mapping=SEM_MAP_PIPE_SQ2DISK, **kw)

@@ -1,0 +1,714 @@
+// api.cpp -- the C ABI (include/sem.h): mesh set-up and upload, operators,
+// and the Jacobi-PCG drivers (FP64, and FP32-inner / FP64-outer defect
+// correction).  All arithmetic of the path runs in the kernels of
+// kernels.hip; this file only allocates, uploads and sequences launches.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "kernels.hpp"
+#include "sem_internal.hpp"
+
+namespace sem {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+void fail(sem_status st, const std::string &msg)
+{
+    set_error(msg);
+    throw Failure{st};
+}
+
+void check_hip(hipError_t e, const char *what)
+{
+    if (e != hipSuccess) {
+        const sem_status st = (e == hipErrorOutOfMemory) ? SEM_ENOMEM : SEM_EHIP;
+        fail(st, std::string(what) + ": " + hipGetErrorString(e));
+    }
+}
+
+template <typename F>
+static sem_status guarded(F &&f)
+{
+    try {
+        return f();
+    } catch (const Failure &x) {
+        return x.status;
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return SEM_ENOMEM;
+    } catch (const std::exception &x) {
+        set_error(x.what());
+        return SEM_EINVAL;
+    } catch (...) {
+        set_error("unknown internal error");
+        return SEM_EINVAL;
+    }
+}
+
+template <typename T>
+static T *dalloc(sem_mesh *m, size_t count)
+{
+    void *p = nullptr;
+    const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    SEM_HIP(hipMalloc(&p, bytes));
+    m->allocations.push_back(p);
+    m->device_bytes += bytes;
+    return static_cast<T *>(p);
+}
+
+static void upload(void *dst, const void *src, size_t bytes, hipStream_t s)
+{
+    SEM_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
+}
+
+// Elements per workgroup of the operator: the smallest count that keeps the
+// 64-wide waves at least ~94% populated, within 256 lanes.
+static int default_epw(int N)
+{
+    const int P2 = (N + 1) * (N + 1);
+    int best = 1;
+    double best_fill = 0.0;
+    for (int epw = 1; epw * P2 <= 256; ++epw) {
+        const int t = epw * P2, tr = (t + 63) / 64 * 64;
+        const double fill = (double)t / tr;
+        if (fill > best_fill + 0.06) {
+            best_fill = fill;
+            best = epw;
+        }
+    }
+    return best;
+}
+
+static void require_device_gfx950()
+{
+    int dev = 0;
+    SEM_HIP(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    SEM_HIP(hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        fail(SEM_EHIP, std::string("kernels are built for gfx950, device is ") + prop.gcnArchName);
+}
+
+static void ensure_solve_space(sem_mesh *m, bool need32)
+{
+    const int64_t nL = m->h.nL;
+    if (!m->r64) {
+        m->r64 = dalloc<double>(m, nL);
+        m->p64 = dalloc<double>(m, nL);
+        m->w64 = dalloc<double>(m, nL);
+        m->x64 = dalloc<double>(m, nL);
+    }
+    if (need32 && !m->r32) {
+        m->x32 = dalloc<float>(m, nL);
+        m->r32 = dalloc<float>(m, nL);
+        m->p32 = dalloc<float>(m, nL);
+        m->w32 = dalloc<float>(m, nL);
+    }
+}
+
+static hipStream_t cap_stream(sem_mesh *m)
+{
+    if (!m->capture_stream) SEM_HIP(hipStreamCreateWithFlags(&m->capture_stream, hipStreamNonBlocking));
+    return m->capture_stream;
+}
+
+// --- building blocks --------------------------------------------------------
+template <typename T>
+struct Prec;
+template <>
+struct Prec<double> {
+    static const double *D(sem_mesh *m) { return m->D64; }
+    static const double *G(sem_mesh *m) { return m->G64; }
+    static const double *inv(sem_mesh *m) { return m->inv64; }
+    static double *x(sem_mesh *m) { return m->x64; }
+    static double *r(sem_mesh *m) { return m->r64; }
+    static double *p(sem_mesh *m) { return m->p64; }
+    static double *w(sem_mesh *m) { return m->w64; }
+    static PcgState *st(sem_mesh *m) { return m->state; }
+};
+template <>
+struct Prec<float> {
+    static const float *D(sem_mesh *m) { return m->D32; }
+    static const float *G(sem_mesh *m) { return m->G32; }
+    static const float *inv(sem_mesh *m) { return m->inv32; }
+    static float *x(sem_mesh *m) { return m->x32; }
+    static float *r(sem_mesh *m) { return m->r32; }
+    static float *p(sem_mesh *m) { return m->p32; }
+    static float *w(sem_mesh *m) { return m->w32; }
+    static PcgState *st(sem_mesh *m) { return m->state + 1; }
+};
+
+template <typename T>
+static void enqueue_ax(sem_mesh *m, int mode, const T *in, T *out, hipStream_t s)
+{
+    AxParams<T> a{};
+    a.E = m->h.E;
+    a.epw = m->ax_epw;
+    a.D = Prec<T>::D(m);
+    a.G = Prec<T>::G(m);
+    a.in = in;
+    a.out = out;
+    a.partial = m->partials;
+    if (mode == 2) {
+        a.invdiag = Prec<T>::inv(m);
+        a.p = Prec<T>::p(m);
+        a.st = Prec<T>::st(m);
+    }
+    SEM_HIP(launch_ax<T>(m->h.N, mode, a, s));
+}
+
+template <typename T>
+static void enqueue_gs(sem_mesh *m, T *v, const PcgState *st, hipStream_t s)
+{
+    SEM_HIP(launch_gs<T>(0, m->h.gs_n_sum, m->h.gs_n_ids, m->gs_off, m->gs_idx, v, st, s));
+}
+
+// one CG iteration: w = A p (p updated from z and beta first), gs, alpha,
+// x/r update with <r,z>, <r,r>, beta
+template <typename T>
+static void enqueue_iterations(sem_mesh *m, int k, hipStream_t s)
+{
+    PcgState *st = Prec<T>::st(m);
+    const int64_t axb = ax_blocks(m->h.E, m->ax_epw);
+    const int64_t nL = m->h.nL;
+    for (int it = 0; it < k; ++it) {
+        enqueue_ax<T>(m, 2, Prec<T>::r(m), Prec<T>::w(m), s);
+        enqueue_gs<T>(m, Prec<T>::w(m), st, s);
+        SEM_HIP(launch_reduce_sigma(m->partials, axb, st, s));
+        SEM_HIP(launch_pcg_update<T>(nL, st, Prec<T>::x(m), Prec<T>::r(m), Prec<T>::p(m), Prec<T>::w(m),
+                                     Prec<T>::inv(m), m->mult, m->partials, s));
+        SEM_HIP(launch_reduce_rho(m->partials, vec_blocks(nL), st, s));
+    }
+}
+
+template <typename T>
+static void run_iterations(sem_mesh *m, int k, bool use_graph, hipStream_t s)
+{
+    if (!use_graph) {
+        enqueue_iterations<T>(m, k, s);
+        return;
+    }
+    const int slot = sizeof(T) == 8 ? 0 : 1;
+    if (!m->graph[slot] || m->graph_k[slot] != k || m->graph_epw[slot] != m->ax_epw) {
+        if (m->graph[slot]) {
+            SEM_HIP(hipGraphExecDestroy(m->graph[slot]));
+            m->graph[slot] = nullptr;
+        }
+        hipStream_t cs = cap_stream(m);
+        hipGraph_t g = nullptr;
+        SEM_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        try {
+            enqueue_iterations<T>(m, k, cs);
+        } catch (...) {
+            hipStreamEndCapture(cs, &g);
+            if (g) hipGraphDestroy(g);
+            throw;
+        }
+        SEM_HIP(hipStreamEndCapture(cs, &g));
+        hipGraphExec_t ex = nullptr;
+        const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        SEM_HIP(e);
+        m->graph[slot] = ex;
+        m->graph_k[slot] = k;
+        m->graph_epw[slot] = m->ax_epw;
+    }
+    SEM_HIP(hipGraphLaunch(m->graph[slot], s));
+}
+
+static PcgState read_state(const PcgState *st, hipStream_t s)
+{
+    PcgState h;
+    SEM_HIP(hipMemcpyAsync(&h, st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
+    SEM_HIP(hipStreamSynchronize(s));
+    return h;
+}
+
+static double read_scalar(const double *d, hipStream_t s)
+{
+    double h = 0.0;
+    SEM_HIP(hipMemcpyAsync(&h, d, sizeof(double), hipMemcpyDeviceToHost, s));
+    SEM_HIP(hipStreamSynchronize(s));
+    return h;
+}
+
+// r = b - A x (FP64), then rr = <r, r> into scal[slot]
+static void true_residual(sem_mesh *m, const double *b, hipStream_t s, int slot)
+{
+    enqueue_ax<double>(m, 0, m->x64, m->w64, s);
+    enqueue_gs<double>(m, m->w64, nullptr, s);
+    SEM_HIP(launch_residual(m->h.nL, b, m->w64, m->r64, s));
+    SEM_HIP(launch_dot_unique<double>(m->h.nL, m->r64, m->r64, m->mult, m->partials, m->scal + slot, s));
+}
+
+// Plain CG loop on precision T from the current r (x, p set by the caller);
+// returns the final device state.
+template <typename T>
+static PcgState cg_loop(sem_mesh *m, double stop2, int limit, int poll, bool graph, hipStream_t s)
+{
+    SEM_HIP(launch_pcg_init<T>(m->h.nL, Prec<T>::r(m), Prec<T>::inv(m), m->mult, m->partials, Prec<T>::st(m), stop2,
+                               limit, s));
+    SEM_HIP(hipMemsetAsync(Prec<T>::p(m), 0, sizeof(T) * m->h.nL, s));
+    PcgState hs = read_state(Prec<T>::st(m), s);
+    while (!hs.done) {
+        run_iterations<T>(m, poll, graph, s);
+        hs = read_state(Prec<T>::st(m), s);
+    }
+    return hs;
+}
+
+static sem_status solve_fp64(sem_mesh *m, const double *b, double *x, const sem_solve_opts &o, sem_solve_stats &out,
+                             hipStream_t s)
+{
+    const int64_t nL = m->h.nL;
+    ensure_solve_space(m, false);
+    SEM_HIP(launch_dot_unique<double>(nL, b, b, m->mult, m->partials, m->scal, s));
+    const double bb = read_scalar(m->scal, s);
+    out.bnorm = std::sqrt(bb);
+    if (o.x0_given) SEM_HIP(hipMemcpyAsync(m->x64, x, sizeof(double) * nL, hipMemcpyDeviceToDevice, s));
+    else SEM_HIP(hipMemsetAsync(m->x64, 0, sizeof(double) * nL, s));
+    const int poll = std::max(1, o.poll_every);
+
+    if (o.fixed_iters > 0) {
+        // throughput mode: exactly fixed_iters iterations from the current x
+        if (o.x0_given) true_residual(m, b, s, 1);
+        else SEM_HIP(hipMemcpyAsync(m->r64, b, sizeof(double) * nL, hipMemcpyDeviceToDevice, s));
+        SEM_HIP(launch_pcg_init<double>(nL, m->r64, m->inv64, m->mult, m->partials, m->state, -1.0, o.fixed_iters, s));
+        SEM_HIP(hipMemsetAsync(m->p64, 0, sizeof(double) * nL, s));
+        int left = o.fixed_iters;
+        while (left > 0) {
+            const int k = std::min(left, poll);
+            run_iterations<double>(m, k, o.use_graph != 0, s);
+            left -= k;
+        }
+        const PcgState hs = read_state(m->state, s);
+        SEM_HIP(hipMemcpyAsync(x, m->x64, sizeof(double) * nL, hipMemcpyDeviceToDevice, s));
+        SEM_HIP(hipStreamSynchronize(s));
+        out.iterations = hs.iters;
+        out.outer_iterations = 1;
+        out.rel_residual = bb > 0 ? std::sqrt(hs.rr / bb) : 0.0;
+        return hs.done == 2 ? SEM_EBREAKDOWN : SEM_OK;
+    }
+
+    sem_status status = SEM_OK;
+    if (bb == 0.0) {
+        SEM_HIP(hipMemsetAsync(x, 0, sizeof(double) * nL, s));
+        SEM_HIP(hipStreamSynchronize(s));
+        out.iterations = 0;
+        out.outer_iterations = 1;
+        out.rel_residual = 0.0;
+        return SEM_OK;
+    }
+    const double stop2 = o.tol * o.tol * bb;
+    int total = 0, restarts = 0;
+    bool have_x = o.x0_given != 0;
+    double rel = 0.0;
+    for (;;) {
+        if (have_x) true_residual(m, b, s, 1);
+        else SEM_HIP(hipMemcpyAsync(m->r64, b, sizeof(double) * nL, hipMemcpyDeviceToDevice, s));
+        const PcgState hs = cg_loop<double>(m, stop2, o.max_iter - total, poll, o.use_graph != 0, s);
+        total += hs.iters;
+        have_x = true;
+        if (hs.done == 2) {
+            true_residual(m, b, s, 1);
+            rel = std::sqrt(read_scalar(m->scal + 1, s) / bb);
+            status = SEM_EBREAKDOWN;
+            set_error("sem_pcg_solve: CG breakdown (p.Ap <= 0 or not finite)");
+            break;
+        }
+        true_residual(m, b, s, 1);
+        rel = std::sqrt(read_scalar(m->scal + 1, s) / bb);
+        if (rel <= o.tol) break;
+        if (total >= o.max_iter || restarts == 3) {
+            status = SEM_ENOCONV;
+            set_error("sem_pcg_solve: no convergence within max_iter");
+            break;
+        }
+        restarts++;
+    }
+    SEM_HIP(hipMemcpyAsync(x, m->x64, sizeof(double) * nL, hipMemcpyDeviceToDevice, s));
+    SEM_HIP(hipStreamSynchronize(s));
+    out.iterations = total;
+    out.outer_iterations = restarts + 1;
+    out.rel_residual = rel;
+    return status;
+}
+
+static sem_status solve_mixed(sem_mesh *m, const double *b, double *x, const sem_solve_opts &o, sem_solve_stats &out,
+                              hipStream_t s)
+{
+    if (!m->with_fp32) fail(SEM_EINVAL, "sem_pcg_solve: mixed precision needs SEM_WITH_FP32 at set-up");
+    const int64_t nL = m->h.nL;
+    ensure_solve_space(m, true);
+    SEM_HIP(launch_dot_unique<double>(nL, b, b, m->mult, m->partials, m->scal, s));
+    const double bb = read_scalar(m->scal, s);
+    out.bnorm = std::sqrt(bb);
+    if (o.x0_given) SEM_HIP(hipMemcpyAsync(m->x64, x, sizeof(double) * nL, hipMemcpyDeviceToDevice, s));
+    else SEM_HIP(hipMemsetAsync(m->x64, 0, sizeof(double) * nL, s));
+    const int poll = std::max(1, o.poll_every);
+    const int inner_max = o.inner_max_iter > 0 ? o.inner_max_iter : o.max_iter;
+    sem_status status = SEM_OK;
+    int total = 0, outer = 0;
+    double rel = 0.0;
+    if (bb == 0.0) {
+        SEM_HIP(hipMemsetAsync(x, 0, sizeof(double) * nL, s));
+        SEM_HIP(hipStreamSynchronize(s));
+        out.iterations = 0;
+        out.outer_iterations = 0;
+        out.rel_residual = 0.0;
+        return SEM_OK;
+    }
+    for (;;) {
+        // FP64: r = b - A x, rr -> scal[1]
+        true_residual(m, b, s, 1);
+        const double rr = read_scalar(m->scal + 1, s);
+        rel = std::sqrt(rr / bb);
+        if (rel <= o.tol) break;
+        if (total >= o.max_iter || outer >= 100) {
+            status = SEM_ENOCONV;
+            set_error("sem_pcg_solve: mixed refinement did not converge within max_iter");
+            break;
+        }
+        // FP32 inner solve of A d = r / ||r|| from d = 0
+        SEM_HIP(launch_to_fp32_scaled(nL, m->r64, m->scal + 1, m->r32, s));
+        SEM_HIP(hipMemsetAsync(m->x32, 0, sizeof(float) * nL, s));
+        const int limit = std::min(inner_max, o.max_iter - total);
+        const PcgState hs = cg_loop<float>(m, o.inner_tol * o.inner_tol, limit, poll, o.use_graph != 0, s);
+        total += hs.iters;
+        outer++;
+        if (hs.iters == 0 && hs.done == 2) {
+            status = SEM_EBREAKDOWN;
+            set_error("sem_pcg_solve: FP32 inner CG broke down at its first step");
+            break;
+        }
+        // FP64: x += ||r|| d
+        SEM_HIP(launch_axpy_fp32(nL, m->x32, m->scal + 1, m->x64, s));
+    }
+    SEM_HIP(hipMemcpyAsync(x, m->x64, sizeof(double) * nL, hipMemcpyDeviceToDevice, s));
+    SEM_HIP(hipStreamSynchronize(s));
+    out.iterations = total;
+    out.outer_iterations = outer;
+    out.rel_residual = rel;
+    return status;
+}
+
+}  // namespace sem
+
+using namespace sem;
+
+extern "C" {
+
+const char *sem_last_error(void) { return g_err.c_str(); }
+const char *sem_version(void) { return "sem-mi355x 0.1 (gfx950)"; }
+
+sem_status sem_setup(const sem_mesh_desc *desc, void *stream, sem_mesh **out)
+{
+    return guarded([&]() -> sem_status {
+        if (!desc || !out) fail(SEM_EINVAL, "sem_setup: null argument");
+        *out = nullptr;
+        require_device_gfx950();
+        hipStream_t s = (hipStream_t)stream;
+        sem_mesh *m = new sem_mesh();
+        try {
+            HostMesh &h = m->h;
+            build_host_mesh(*desc, h);
+            h.desc = *desc;
+            if (desc->vertices) {
+                const size_t nv = (size_t)(desc->nel[0] + 1) * (desc->nel[1] + 1) * (desc->nel[2] + 1) * 3;
+                h.vertices.assign(desc->vertices, desc->vertices + nv);
+            }
+            h.desc.vertices = nullptr;
+            SEM_HIP(hipGetDevice(&m->device));
+            m->with_fp32 = (desc->precision_flags & SEM_WITH_FP32) ? 1 : 0;
+            m->ax_epw = default_epw(h.N);
+            const int64_t nL = h.nL, P2 = (int64_t)h.P * h.P;
+            m->D64 = dalloc<double>(m, P2);
+            m->G64 = dalloc<double>(m, 6 * nL);
+            m->B64 = dalloc<double>(m, nL);
+            m->inv64 = dalloc<double>(m, nL);
+            m->mult = dalloc<uint8_t>(m, nL);
+            m->gid = dalloc<int32_t>(m, nL);
+            m->gs_off = dalloc<int32_t>(m, h.gs_n_ids + 1);
+            m->gs_idx = dalloc<int32_t>(m, h.gs_idx.size());
+            const int64_t np = std::max<int64_t>(ax_blocks(h.E, 1), 2 * (int64_t)vec_blocks(nL)) + 64;
+            m->partials = dalloc<double>(m, np);
+            m->n_partials = np;
+            m->state = dalloc<PcgState>(m, 2);
+            m->scal = dalloc<double>(m, 8);
+            std::vector<uint8_t> lmult((size_t)nL);
+            for (int64_t l = 0; l < nL; ++l) lmult[l] = h.gmult[h.gid[l]];
+            upload(m->D64, h.D.data(), sizeof(double) * P2, s);
+            upload(m->G64, h.G.data(), sizeof(double) * 6 * nL, s);
+            upload(m->B64, h.B.data(), sizeof(double) * nL, s);
+            upload(m->inv64, h.invdiag.data(), sizeof(double) * nL, s);
+            upload(m->mult, lmult.data(), nL, s);
+            upload(m->gid, h.gid.data(), sizeof(int32_t) * nL, s);
+            upload(m->gs_off, h.gs_off.data(), sizeof(int32_t) * (h.gs_n_ids + 1), s);
+            upload(m->gs_idx, h.gs_idx.data(), sizeof(int32_t) * h.gs_idx.size(), s);
+            if (m->with_fp32) {
+                m->D32 = dalloc<float>(m, P2);
+                m->G32 = dalloc<float>(m, 6 * nL);
+                m->inv32 = dalloc<float>(m, nL);
+                SEM_HIP(launch_fp64_to_fp32(P2, m->D64, m->D32, s));
+                SEM_HIP(launch_fp64_to_fp32(6 * nL, m->G64, m->G32, s));
+                SEM_HIP(launch_fp64_to_fp32(nL, m->inv64, m->inv32, s));
+            }
+            SEM_HIP(hipMemsetAsync(m->state, 0, 2 * sizeof(PcgState), s));
+            SEM_HIP(hipStreamSynchronize(s));
+            // the device holds these now; keep only what exports need
+            std::vector<double>().swap(h.G);
+            std::vector<double>().swap(h.B);
+            std::vector<double>().swap(h.invdiag);
+            std::vector<double>().swap(h.xyz);
+            std::vector<int32_t>().swap(h.gs_idx);
+            std::vector<int32_t>().swap(h.gs_off);
+        } catch (...) {
+            sem_free(m);
+            throw;
+        }
+        *out = m;
+        return SEM_OK;
+    });
+}
+
+sem_status sem_free(sem_mesh *m)
+{
+    if (!m) return SEM_OK;
+    for (int q = 0; q < 2; ++q)
+        if (m->graph[q]) hipGraphExecDestroy(m->graph[q]);
+    if (m->capture_stream) hipStreamDestroy(m->capture_stream);
+    for (void *p : m->allocations) hipFree(p);
+    delete m;
+    return SEM_OK;
+}
+
+sem_status sem_info(const sem_mesh *m, sem_mesh_info *info)
+{
+    return guarded([&]() -> sem_status {
+        if (!m || !info) fail(SEM_EINVAL, "sem_info: null argument");
+        const HostMesh &h = m->h;
+        info->N = h.N;
+        info->E = h.E;
+        info->n_local = h.nL;
+        info->n_global = h.nG;
+        info->n_shared_local = h.n_shared_local;
+        info->n_shared_global = h.n_shared_global;
+        info->n_masked_global = h.n_masked_global;
+        info->n_unmasked_global = h.nG - h.n_masked_global;
+        info->gs_plan_ids = h.gs_n_ids;
+        info->gs_plan_sum_ids = h.gs_n_sum;
+        info->gs_plan_len = h.gs_plan_len;
+        info->device_bytes = m->device_bytes;
+        return SEM_OK;
+    });
+}
+
+sem_status sem_export_gll(int N, double *xi, double *w, double *D)
+{
+    return guarded([&]() -> sem_status {
+        if (N < 1 || N > SEM_MAX_ORDER) fail(SEM_EINVAL, "sem_export_gll: N out of range");
+        std::vector<double> x, wt, d;
+        gll_rule(N, x, wt);
+        lagrange_derivative(x, d);
+        if (xi) std::copy(x.begin(), x.end(), xi);
+        if (w) std::copy(wt.begin(), wt.end(), w);
+        if (D) std::copy(d.begin(), d.end(), D);
+        return SEM_OK;
+    });
+}
+
+sem_status sem_export_maps(const sem_mesh *m, int64_t *glob_id, uint8_t *mult, uint8_t *mask)
+{
+    return guarded([&]() -> sem_status {
+        if (!m) fail(SEM_EINVAL, "sem_export_maps: null mesh");
+        const HostMesh &h = m->h;
+        for (int64_t l = 0; l < h.nL; ++l) {
+            const int32_t g = h.gid[l];
+            if (glob_id) glob_id[l] = g;
+            if (mult) mult[l] = h.gmult[g];
+            if (mask) mask[l] = h.gmask[g];
+        }
+        return SEM_OK;
+    });
+}
+
+sem_status sem_export_geom(const sem_mesh *m, double *G, double *B, double *invdiag)
+{
+    return guarded([&]() -> sem_status {
+        if (!m) fail(SEM_EINVAL, "sem_export_geom: null mesh");
+        const HostMesh &h = m->h;
+        const int64_t nL = h.nL, P3 = (int64_t)h.P * h.P * h.P;
+        if (G) {
+            std::vector<double> tmp((size_t)6 * nL);
+            SEM_HIP(hipMemcpy(tmp.data(), m->G64, sizeof(double) * 6 * nL, hipMemcpyDeviceToHost));
+            for (int64_t e = 0; e < h.E; ++e)
+                for (int c = 0; c < 6; ++c)
+                    std::memcpy(G + c * nL + e * P3, tmp.data() + (e * 6 + c) * P3, sizeof(double) * P3);
+        }
+        if (B) SEM_HIP(hipMemcpy(B, m->B64, sizeof(double) * nL, hipMemcpyDeviceToHost));
+        if (invdiag) SEM_HIP(hipMemcpy(invdiag, m->inv64, sizeof(double) * nL, hipMemcpyDeviceToHost));
+        return SEM_OK;
+    });
+}
+
+sem_status sem_export_coords(const sem_mesh *m, double *xyz)
+{
+    return guarded([&]() -> sem_status {
+        if (!m || !xyz) fail(SEM_EINVAL, "sem_export_coords: null argument");
+        HostMesh tmp;
+        sem_mesh_desc d = m->h.desc;
+        d.vertices = m->h.vertices.empty() ? nullptr : m->h.vertices.data();
+        build_host_coords(d, tmp);
+        std::memcpy(xyz, tmp.xyz.data(), sizeof(double) * 3 * tmp.nL);
+        return SEM_OK;
+    });
+}
+
+sem_status sem_host_setup(const sem_mesh_desc *desc, sem_mesh_info *info, int64_t *glob_id, uint8_t *mult,
+                          uint8_t *mask, double *G, double *B, double *invdiag, int32_t *gs_off, int32_t *gs_idx)
+{
+    return guarded([&]() -> sem_status {
+        if (!desc) fail(SEM_EINVAL, "sem_host_setup: null descriptor");
+        HostMesh h;
+        build_host_mesh(*desc, h);
+        const int64_t nL = h.nL, P3 = (int64_t)h.P * h.P * h.P;
+        if (info) {
+            info->N = h.N;
+            info->E = h.E;
+            info->n_local = nL;
+            info->n_global = h.nG;
+            info->n_shared_local = h.n_shared_local;
+            info->n_shared_global = h.n_shared_global;
+            info->n_masked_global = h.n_masked_global;
+            info->n_unmasked_global = h.nG - h.n_masked_global;
+            info->gs_plan_ids = h.gs_n_ids;
+            info->gs_plan_sum_ids = h.gs_n_sum;
+            info->gs_plan_len = h.gs_plan_len;
+            info->device_bytes = 0;
+        }
+        for (int64_t l = 0; l < nL; ++l) {
+            const int32_t g = h.gid[l];
+            if (glob_id) glob_id[l] = g;
+            if (mult) mult[l] = h.gmult[g];
+            if (mask) mask[l] = h.gmask[g];
+        }
+        if (G)
+            for (int64_t e = 0; e < h.E; ++e)
+                for (int c = 0; c < 6; ++c)
+                    std::memcpy(G + c * nL + e * P3, h.G.data() + (e * 6 + c) * P3, sizeof(double) * P3);
+        if (B) std::memcpy(B, h.B.data(), sizeof(double) * nL);
+        if (invdiag) std::memcpy(invdiag, h.invdiag.data(), sizeof(double) * nL);
+        if (gs_off) std::memcpy(gs_off, h.gs_off.data(), sizeof(int32_t) * h.gs_off.size());
+        if (gs_idx) std::memcpy(gs_idx, h.gs_idx.data(), sizeof(int32_t) * h.gs_idx.size());
+        return SEM_OK;
+    });
+}
+
+static void check_dtype(const sem_mesh *m, int dtype)
+{
+    if (dtype != SEM_FP64 && dtype != SEM_FP32) fail(SEM_EINVAL, "unknown dtype");
+    if (dtype == SEM_FP32 && !m->with_fp32) fail(SEM_EINVAL, "FP32 operators need SEM_WITH_FP32 at set-up");
+}
+
+sem_status sem_ax(sem_mesh *m, int dtype, const void *u, void *w, double *opt_dot, void *stream)
+{
+    return guarded([&]() -> sem_status {
+        if (!m || !u || !w) fail(SEM_EINVAL, "sem_ax: null argument");
+        if (u == w) fail(SEM_EINVAL, "sem_ax: u and w must not overlap");
+        check_dtype(m, dtype);
+        hipStream_t s = (hipStream_t)stream;
+        const int mode = opt_dot ? 1 : 0;
+        if (dtype == SEM_FP64) enqueue_ax<double>(m, mode, (const double *)u, (double *)w, s);
+        else enqueue_ax<float>(m, mode, (const float *)u, (float *)w, s);
+        if (opt_dot) SEM_HIP(launch_reduce_scalar(m->partials, ax_blocks(m->h.E, m->ax_epw), opt_dot, s));
+        return SEM_OK;
+    });
+}
+
+sem_status sem_gs(sem_mesh *m, int dtype, void *v, void *stream)
+{
+    return guarded([&]() -> sem_status {
+        if (!m || !v) fail(SEM_EINVAL, "sem_gs: null argument");
+        check_dtype(m, dtype);
+        hipStream_t s = (hipStream_t)stream;
+        if (dtype == SEM_FP64) enqueue_gs<double>(m, (double *)v, nullptr, s);
+        else enqueue_gs<float>(m, (float *)v, nullptr, s);
+        return SEM_OK;
+    });
+}
+
+sem_status sem_axgs(sem_mesh *m, int dtype, const void *u, void *w, void *stream)
+{
+    sem_status st = sem_ax(m, dtype, u, w, nullptr, stream);
+    if (st != SEM_OK) return st;
+    return sem_gs(m, dtype, w, stream);
+}
+
+sem_status sem_mass(sem_mesh *m, const double *f, double *b, void *stream)
+{
+    return guarded([&]() -> sem_status {
+        if (!m || !f || !b) fail(SEM_EINVAL, "sem_mass: null argument");
+        hipStream_t s = (hipStream_t)stream;
+        SEM_HIP(launch_scale(m->h.nL, m->B64, f, b, s));
+        enqueue_gs<double>(m, b, nullptr, s);
+        return SEM_OK;
+    });
+}
+
+sem_status sem_scatter(sem_mesh *m, const double *v_global, double *u_local, void *stream)
+{
+    return guarded([&]() -> sem_status {
+        if (!m || !v_global || !u_local) fail(SEM_EINVAL, "sem_scatter: null argument");
+        hipStream_t s = (hipStream_t)stream;
+        SEM_HIP(launch_scatter(m->h.nL, m->gid, v_global, u_local, s));
+        // masked ids only: every copy set to 0
+        SEM_HIP(launch_gs<double>(m->h.gs_n_sum, m->h.gs_n_sum, m->h.gs_n_ids, m->gs_off, m->gs_idx, u_local,
+                                  nullptr, s));
+        return SEM_OK;
+    });
+}
+
+void sem_solve_opts_default(sem_solve_opts *o)
+{
+    if (!o) return;
+    o->tol = 1e-10;
+    o->max_iter = 5000;
+    o->precision = SEM_PREC_FP64;
+    o->inner_tol = 1e-4;
+    o->inner_max_iter = 0;
+    o->poll_every = 16;
+    o->use_graph = 1;
+    o->fixed_iters = 0;
+    o->x0_given = 0;
+}
+
+sem_status sem_pcg_solve(sem_mesh *m, const double *b, double *x, const sem_solve_opts *opts, sem_solve_stats *stats,
+                         void *stream)
+{
+    sem_solve_stats local{};
+    sem_solve_stats &out = stats ? *stats : local;
+    std::memset(&out, 0, sizeof(out));
+    const auto t0 = std::chrono::steady_clock::now();
+    const sem_status st = guarded([&]() -> sem_status {
+        if (!m || !b || !x) fail(SEM_EINVAL, "sem_pcg_solve: null argument");
+        sem_solve_opts o;
+        sem_solve_opts_default(&o);
+        if (opts) o = *opts;
+        if (!(o.tol > 0.0) && o.fixed_iters <= 0) fail(SEM_EINVAL, "sem_pcg_solve: tol must be positive");
+        if (o.max_iter < 0) fail(SEM_EINVAL, "sem_pcg_solve: negative max_iter");
+        hipStream_t s = (hipStream_t)stream;
+        if (o.precision == SEM_PREC_MIXED) return solve_mixed(m, b, x, o, out, s);
+        if (o.precision != SEM_PREC_FP64) fail(SEM_EINVAL, "sem_pcg_solve: unknown precision");
+        return solve_fp64(m, b, x, o, out, s);
+    });
+    out.status = st;
+    out.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return st;
+}
+
+}  // extern "C"

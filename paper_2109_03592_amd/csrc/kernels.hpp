@@ -1,0 +1,55 @@
+// kernels.hpp -- launch wrappers of the gfx950 kernels (kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "sem_internal.hpp"
+
+namespace sem {
+
+template <typename T>
+struct AxParams {
+    int64_t E;             // elements
+    int epw;               // elements per workgroup
+    const T *D;            // D[i*P+l], P*P entries
+    const T *G;            // [E][6][P^3]
+    const T *in;           // u (modes 0/1) or r (mode 2)
+    T *out;                // w
+    double *partial;       // per-workgroup dot partials (modes 1/2)
+    const T *invdiag;      // mode 2
+    T *p;                  // mode 2: search direction, updated in place
+    const PcgState *st;    // mode 2: beta and the done flag
+};
+
+int ax_block_threads(int N, int epw);
+size_t ax_lds_bytes(int N, int epw, size_t elem);
+int64_t ax_blocks(int64_t E, int epw);
+int vec_blocks(int64_t n);
+
+template <typename T>
+hipError_t launch_ax(int N, int mode, const AxParams<T> &a, hipStream_t s);
+template <typename T>
+hipError_t launch_gs(int64_t first, int64_t n_sum, int64_t n_ids, const int32_t *off, const int32_t *idx, T *v,
+                     const PcgState *st, hipStream_t s);
+hipError_t launch_scale(int64_t n, const double *a, const double *b, double *out, hipStream_t s);
+hipError_t launch_scatter(int64_t n, const int32_t *gid, const double *vg, double *out, hipStream_t s);
+hipError_t launch_residual(int64_t n, const double *b, const double *w, double *r, hipStream_t s);
+hipError_t launch_to_fp32_scaled(int64_t n, const double *r, const double *scal, float *out, hipStream_t s);
+hipError_t launch_axpy_fp32(int64_t n, const float *d, const double *scal, double *x, hipStream_t s);
+hipError_t launch_fp64_to_fp32(int64_t n, const double *a, float *out, hipStream_t s);
+template <typename T>
+hipError_t launch_dot_unique(int64_t n, const T *a, const T *b, const uint8_t *mult, double *partial,
+                             double *out, hipStream_t s);
+template <typename T>
+hipError_t launch_pcg_init(int64_t n, const T *r, const T *inv, const uint8_t *mult, double *partial,
+                           PcgState *st, double stop2, int limit, hipStream_t s);
+template <typename T>
+hipError_t launch_pcg_update(int64_t n, const PcgState *st, T *x, T *r, const T *p, const T *w, const T *inv,
+                             const uint8_t *mult, double *partial, hipStream_t s);
+hipError_t launch_reduce_sigma(const double *partial, int64_t n, PcgState *st, hipStream_t s);
+hipError_t launch_reduce_rho(const double *partial, int64_t n, PcgState *st, hipStream_t s);
+hipError_t launch_reduce_scalar(const double *partial, int64_t n, double *out, hipStream_t s);
+
+}  // namespace sem

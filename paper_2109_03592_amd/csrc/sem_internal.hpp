@@ -1,0 +1,109 @@
+// sem_internal.hpp -- types shared by the host set-up, the kernels and the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <functional>
+#include <string>
+#include <vector>
+
+#include "../../include/sem.h"
+
+namespace sem {
+
+// ---------------------------------------------------------------------------
+// error plumbing: every internal failure becomes a status + thread-local text
+void set_error(const std::string &msg);
+struct Failure {
+    sem_status status;
+};
+[[noreturn]] void fail(sem_status st, const std::string &msg);
+void check_hip(hipError_t e, const char *what);
+#define SEM_HIP(call) ::sem::check_hip((call), #call)
+
+// ---------------------------------------------------------------------------
+// Host set-up products (section 2: GLL basis, element geometry, numbering).
+struct HostMesh {
+    int N = 0, P = 0;
+    int nel[3] = {0, 0, 0};
+    int periodic[3] = {0, 0, 0};
+    int64_t E = 0, nL = 0, nG = 0;
+    int64_t ext[3] = {0, 0, 0};          // global lattice extent per axis
+    std::vector<double> xi, w, D;         // GLL nodes, weights, D[i*P+l]
+    std::vector<double> xyz;              // [3][nL]
+    std::vector<double> G;                // [E][6][P^3] element-blocked
+    std::vector<double> B;                // [nL]
+    std::vector<int32_t> gid;             // [nL]
+    std::vector<uint8_t> gmask;           // [nG]
+    std::vector<uint8_t> gmult;           // [nG]
+    // gather-scatter plan: ids [0, n_sum) are summed, [n_sum, n_ids) zeroed
+    int64_t gs_n_sum = 0, gs_n_ids = 0, gs_plan_len = 0;
+    std::vector<int32_t> gs_off;          // [n_ids + 1]
+    std::vector<int32_t> gs_idx;          // local ids, ascending within an id
+    int64_t n_shared_local = 0, n_shared_global = 0, n_masked_global = 0;
+    std::vector<double> invdiag;          // [nL]
+    sem_mesh_desc desc{};                 // copy of the descriptor (vertices below)
+    std::vector<double> vertices;
+};
+
+void gll_rule(int N, std::vector<double> &xi, std::vector<double> &w);
+void lagrange_derivative(const std::vector<double> &xi, std::vector<double> &D);
+void build_host_mesh(const sem_mesh_desc &d, HostMesh &h);
+void build_host_coords(const sem_mesh_desc &d, HostMesh &h);
+void host_parallel_for(int64_t n, const std::function<void(int64_t, int64_t)> &body);
+
+// ---------------------------------------------------------------------------
+// Device-side PCG scalars (one block per solve, device memory).
+struct PcgState {
+    double rho;        // <r, z>
+    double rho_new;
+    double sigma;      // <p, A p>
+    double alpha, beta;
+    double rr;         // <r, r>
+    double stop2;      // stop when rr <= stop2
+    int iters;         // iterations performed
+    int done;          // 1 = converged, 2 = breakdown
+    int limit;         // iteration limit
+    int pad;
+};
+
+// ---------------------------------------------------------------------------
+struct DeviceBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace sem
+
+struct sem_mesh {
+    sem::HostMesh h;
+    int device = 0;
+    int with_fp32 = 0;
+    // device arrays
+    double *D64 = nullptr;
+    float *D32 = nullptr;
+    double *G64 = nullptr;     // [E][6][P^3]
+    float *G32 = nullptr;
+    double *B64 = nullptr;     // [nL]
+    double *inv64 = nullptr;   // [nL]
+    float *inv32 = nullptr;
+    uint8_t *mult = nullptr;   // [nL] multiplicity per local node
+    int32_t *gid = nullptr;    // [nL]
+    int32_t *gs_off = nullptr;
+    int32_t *gs_idx = nullptr;
+    // Krylov work space, allocated on the first solve
+    double *x64 = nullptr, *r64 = nullptr, *p64 = nullptr, *w64 = nullptr;
+    float *x32 = nullptr, *r32 = nullptr, *p32 = nullptr, *w32 = nullptr;
+    double *partials = nullptr;   // reduction partials
+    int64_t n_partials = 0;
+    sem::PcgState *state = nullptr;  // [2]: FP64 solve, FP32 inner solve
+    double *scal = nullptr;          // small device scratch for norms
+    int ax_epw = 1;                  // elements per workgroup of the operator
+    hipStream_t capture_stream = nullptr;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};  // CG iteration blocks, FP64 / FP32
+    int graph_k[2] = {0, 0};
+    int graph_epw[2] = {0, 0};
+    size_t device_bytes = 0;
+    std::vector<void *> allocations;
+};
