@@ -1,0 +1,251 @@
+#!/usr/bin/env python3
+"""Benchmark of the SEM Poisson hot path on one MI355X.
+
+Workload: the pipe-like mesh at one GPU's real share -- the square
+[-1,1]^2 x [0,10] with 48 x 48 x 96 = 221,184 hexahedra of order N=7 mapped to
+a circular pipe, periodic in z, Dirichlet wall, seeded uniform-random
+right-hand side (one U[-1,1) value per global node, mean removed).  The
+paper's own pipe meshes are not available; this synthetic mesh stands in.
+
+A step is one Jacobi-PCG iteration in FP64: the local operator with the fused
+search-direction update and p.Ap partials, the gather-scatter, alpha, the x/r
+update with the Jacobi-weighted dot products, beta -- every row of the hot
+path, one Ax+gs apply per step.  `value` = unique global nodes x steps /
+seconds (GDOF/s).  Beside it the line reports the stand-alone Ax+gs apply rate
+(FP64 and FP32), full FP64 and mixed-precision solves to a 1e-10 relative
+residual, the roofline of the dominant kernel (measured with HIP events on the
+launch stream inside the timed region) and the CPU oracle on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+if HERE not in sys.path:
+    sys.path.insert(0, HERE)
+
+METRIC = "SEM Ax+gs GDOF/s & HBM % (FP64 vs mixed, 1e-10) + solves/s, p99 latency"
+HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def bytes_per_point(N: int, kind: str, dtype_bytes: int = 8) -> float:
+    """Algorithmic HBM bytes per local point of one kernel launch."""
+    if kind == "ax":          # read u, 6 geometric factors; write w
+        return dtype_bytes * (1 + 6 + 1)
+    if kind == "ax_pcg":      # read r, invdiag, p, 6 factors; write p, w
+        return dtype_bytes * (3 + 6 + 2)
+    if kind == "update":      # read x, r, p, w, invdiag, mult(1 B); write x, r
+        return dtype_bytes * 7 + 1
+    raise ValueError(kind)
+
+
+def flops_per_point(N: int) -> int:
+    """Operator flops per local point: 6 contractions of length N+1 (2 flops
+    each) plus the 15-flop geometric combine."""
+    return 12 * (N + 1) + 15
+
+
+def gs_bytes(info, dtype_bytes: int = 8) -> float:
+    """Gather-scatter: per shared local copy read index + read + write value;
+    per shared global id one offset."""
+    return info.n_shared_local * (4 + 2 * dtype_bytes) + info.n_shared_global * 4
+
+
+def cpu_baseline(seconds_target: float = 15.0):
+    """The oracle, as it stands, on a bounded slab of the same pipe."""
+    from oracle import oracle as O
+    import seeded_inputs as SI
+    nz = 8
+    om = O.pipe_mesh(48, 48, nz, N=7)
+    gid = om.numbering()
+    b = SI.uniform_global_values(om.nglob, 2)[gid]
+    b[om.local_mask() == 1] = 0.0
+    om.geom()
+    om.jacobi()
+    # probe one iteration's cost, then size the run to the target
+    t0 = time.perf_counter()
+    om.pcg(b, tol=1e-30, max_iter=1)
+    t1 = time.perf_counter() - t0
+    iters = int(max(3, min(200, seconds_target / max(t1 / 3.0, 1e-3))))
+    t0 = time.perf_counter()
+    _, res = om.pcg(b, tol=1e-30, max_iter=iters)
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {
+        "value": om.nglob * res.iterations / dt / 1e9,
+        "unit": "GDOF/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": (f"pipe 48x48x{nz} N=7 ({om.E} elements, {om.nglob} global nodes), "
+                   f"{res.iterations} FP64 Jacobi-PCG iterations in {dt:.2f} s (plus 2 residual applies); "
+                   f"OpenMP over elements, gather-scatter and dots sequential"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--nel", type=int, nargs=3, default=(48, 48, 96))
+    ap.add_argument("--order", type=int, default=7)
+    ap.add_argument("--applies", type=int, default=100, help="stand-alone Ax+gs applies")
+    ap.add_argument("--no-solve", action="store_true", help="skip the full FP64 / mixed solves")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-axgs", action="store_true", help="skip the stand-alone Ax+gs timing")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: this engine has no multi-GPU path (one GPU's share of the "
+              "pipe is the workload); run it with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2109_03592_amd as sem
+    import seeded_inputs as SI
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a ROCm GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    nx, ny, nz = args.nel
+    N = args.order
+    t0 = time.perf_counter()
+    mesh = sem.pipe_mesh(nx, ny, nz, N=N, with_fp32=True)
+    info = mesh.info
+    log(f"setup: E={mesh.E} N={N} n_local={mesh.n_local} n_global={mesh.n_global} "
+        f"({time.perf_counter() - t0:.1f} s, {info.device_bytes / 2**30:.1f} GiB on device)")
+    vg = torch.from_numpy(SI.uniform_global_values(mesh.n_global, 2)).cuda()
+    b = mesh.scatter(vg)
+    del vg
+    nL, nG = mesh.n_local, mesh.n_global
+
+    # ---- K timed PCG iterations (the steps) --------------------------------
+    x = mesh.zeros()
+    mesh.solve(b, x, fixed_iters=max(1, args.warmup), profile=True, initial_guess=False)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    _, res = mesh.solve(b, x, fixed_iters=args.steps, profile=True, initial_guess=False)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t_steps = ev0.elapsed_time(ev1) / 1e3
+    value = nG * args.steps / t_steps / 1e9
+    ax_ms = res.ms_operator / max(1, res.operator_launches)
+    gs_ms = res.ms_gather_scatter / max(1, res.operator_launches)
+    up_ms = res.ms_update / max(1, res.operator_launches)
+    log(f"pcg steps: {args.steps} in {t_steps * 1e3:.1f} ms -> {value:.2f} GDOF/s; per iteration "
+        f"operator {ax_ms:.3f} ms, gs {gs_ms:.3f} ms, update {up_ms:.3f} ms")
+    # graph-replayed iterations (no per-kernel events)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    mesh.solve(b, x, fixed_iters=args.steps, use_graph=True, poll_every=25, initial_guess=False)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t_graph = ev0.elapsed_time(ev1) / 1e3
+
+    ax_bytes = bytes_per_point(N, "ax_pcg") * nL
+    roof = {"bound": "hbm", "kernel": f"ax_kernel<double,{N},pcg>",
+            "achieved": ax_bytes / (ax_ms / 1e3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "traffic": None}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    step_bytes = ax_bytes + gs_bytes(info) + bytes_per_point(N, "update") * nL
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "GDOF/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": t_steps / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"pipe {nx}x{ny}x{nz} N={N} FP64 Jacobi-PCG iteration (one Ax+gs apply each)",
+                   "E": mesh.E, "N": N, "n_local": nL, "n_global": nG},
+        "roofline": roof,
+        "step": {"ms_operator": ax_ms, "ms_gather_scatter": gs_ms, "ms_update_reduce": up_ms,
+                 "hbm_frac_step": step_bytes / (t_steps / args.steps) / 1e9 / HBM_PEAK_GBS,
+                 "algorithmic_bytes_per_step": step_bytes,
+                 "ms_per_step_graph": t_graph / args.steps * 1e3,
+                 "gdofs_graph": nG * args.steps / t_graph / 1e9},
+    }
+
+    # ---- stand-alone Ax+gs applies (FP64 and FP32) ---------------------------
+    if not args.no_axgs:
+        axgs = {}
+        for name, dt, eb in (("fp64", torch.float64, 8), ("fp32", torch.float32, 4)):
+            u = torch.from_numpy(SI.random_local(nL, 3)).to(device="cuda", dtype=dt)
+            w = torch.empty_like(u)
+            for _ in range(3):
+                mesh.ax(u, w)
+                mesh.gs(w)
+            evs = [torch.cuda.Event(enable_timing=True) for _ in range(3 * args.applies)]
+            torch.cuda.synchronize()
+            tA = time.perf_counter()
+            for q in range(args.applies):
+                evs[3 * q].record(stream)
+                mesh.ax(u, w)
+                evs[3 * q + 1].record(stream)
+                mesh.gs(w)
+                evs[3 * q + 2].record(stream)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - tA
+            t_ax = np.mean([evs[3 * q].elapsed_time(evs[3 * q + 1]) for q in range(args.applies)]) / 1e3
+            t_gs = np.mean([evs[3 * q + 1].elapsed_time(evs[3 * q + 2]) for q in range(args.applies)]) / 1e3
+            tot = evs[0].elapsed_time(evs[-1]) / 1e3 / args.applies
+            byt = bytes_per_point(N, "ax", eb) * nL + gs_bytes(info, eb)
+            axgs[name] = {"gdofs": nG / tot / 1e9, "ms_per_apply": tot * 1e3, "ms_ax": t_ax * 1e3,
+                          "ms_gs": t_gs * 1e3, "ax_gbs": bytes_per_point(N, "ax", eb) * nL / t_ax / 1e9,
+                          "gs_gbs": gs_bytes(info, eb) / t_gs / 1e9,
+                          "hbm_frac": byt / tot / 1e9 / HBM_PEAK_GBS,
+                          "ax_tflops": flops_per_point(N) * nL / t_ax / 1e12,
+                          "algorithmic_bytes": byt, "applies": args.applies, "wall_s": wall}
+            log(f"ax+gs {name}: {axgs[name]['gdofs']:.2f} GDOF/s, {axgs[name]['ms_per_apply']:.3f} ms/apply, "
+                f"ax {t_ax * 1e3:.3f} ms ({axgs[name]['ax_gbs']:.0f} GB/s), gs {t_gs * 1e3:.3f} ms, "
+                f"HBM {axgs[name]['hbm_frac'] * 100:.1f}%")
+            del u, w
+        out["ax_gs"] = axgs
+
+    # ---- full solves to 1e-10: FP64 and mixed --------------------------------
+    if not args.no_solve:
+        sol = {}
+        for prec in ("fp64", "mixed"):
+            x = mesh.zeros()
+            torch.cuda.synchronize()
+            tS = time.perf_counter()
+            _, r = mesh.solve(b, x, tol=1e-10, max_iter=40000, precision=prec, inner_tol=1e-4,
+                              poll_every=50, initial_guess=False, raise_on_error=False)
+            torch.cuda.synchronize()
+            ts = time.perf_counter() - tS
+            sol[prec] = {"status": r.status, "iterations": r.iterations, "outer": r.outer_iterations,
+                         "rel_residual": r.rel_residual, "seconds": ts, "solves_per_s": 1.0 / ts}
+            log(f"solve {prec}: status={r.status} iters={r.iterations} outer={r.outer_iterations} "
+                f"rel_res={r.rel_residual:.2e} {ts:.2f} s")
+            if prec == "fp64":
+                x64 = x.clone()
+            else:
+                d = (x - x64)
+                err = float(torch.linalg.norm(d) / torch.linalg.norm(x64))
+                sol[prec]["rel_diff_vs_fp64"] = err
+        sol["mixed_speedup"] = sol["fp64"]["seconds"] / sol["mixed"]["seconds"]
+        out["solve"] = sol
+
+    # ---- CPU oracle on a bounded sample ---------------------------------------
+    if not args.no_cpu:
+        log("cpu baseline: oracle on a pipe slab ...")
+        out["cpu_baseline"] = cpu_baseline()
+        log(f"cpu baseline: {out['cpu_baseline']['value']:.4f} GDOF/s on {out['cpu_baseline']['cores']} threads")
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -136,6 +136,13 @@ sem_status sem_host_setup(const sem_mesh_desc *desc, sem_mesh_info *info, int64_
                           uint8_t *mask, double *G, double *B, double *invdiag, int32_t *gs_off,
                           int32_t *gs_idx);
 
+/* Replace the geometric factors and lumped mass of a mesh with caller-supplied
+ * ones (host arrays in the sem_export_geom layout: G[6][n_local], B[n_local]),
+ * e.g. factors computed by another code for the same element layout.  The
+ * Jacobi diagonal and the FP32 copies are rebuilt; graphs stay valid.
+ * Errors: SEM_EINVAL (null pointers, non-positive assembled diagonal). */
+sem_status sem_load_geometry(sem_mesh *mesh, const double *G, const double *B, void *stream);
+
 /* Local operator, Algorithm 1: w = A_L u element by element (no
  * gather-scatter).  u, w: device E-vectors of `dtype` (SEM_FP64 or SEM_FP32;
  * FP32 needs SEM_WITH_FP32).  opt_dot (device double, may be NULL) receives
@@ -162,7 +169,7 @@ sem_status sem_scatter(sem_mesh *mesh, const double *v_global, double *u_local, 
 
 /* Solve options.  sem_solve_opts_default fills tol=1e-10, max_iter=5000,
  * precision=SEM_PREC_FP64, inner_tol=1e-4, inner_max_iter=max_iter,
- * poll_every=16, use_graph=1, fixed_iters=0, x0_given=0. */
+ * poll_every=16, use_graph=1, fixed_iters=0, x0_given=0, profile=0. */
 typedef struct {
     double tol;          /* stop when ||b - A x|| <= tol ||b|| (unique-dof 2-norm) */
     int max_iter;        /* limit on PCG iterations (inner ones for mixed)         */
@@ -174,6 +181,9 @@ typedef struct {
     int fixed_iters;     /* > 0: run exactly this many FP64 iterations, no polling,
                             no final residual (throughput measurement)           */
     int x0_given;        /* 1: x holds the initial guess; 0: start from x = 0      */
+    int profile;         /* 1: time each kernel class with HIP events recorded on
+                            `stream` around every launch (iterations then run
+                            without graphs); results in sem_solve_stats            */
 } sem_solve_opts;
 
 typedef struct {
@@ -183,6 +193,12 @@ typedef struct {
     double rel_residual;      /* true ||b - A x|| / ||b|| at exit (FP64)        */
     double bnorm;             /* ||b||                                         */
     double seconds;           /* wall time of the call                         */
+    /* with opts.profile: summed device time per kernel class over all CG
+     * iterations, and the number of operator launches timed */
+    double ms_operator;       /* local operator (with the fused p update)      */
+    double ms_gather_scatter;
+    double ms_update;         /* x/r update, dot products, alpha/beta          */
+    int operator_launches;
 } sem_solve_stats;
 
 void sem_solve_opts_default(sem_solve_opts *opts);

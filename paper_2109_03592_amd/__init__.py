@@ -47,6 +47,10 @@ class SolveResult:
     rel_residual: float
     bnorm: float
     seconds: float
+    ms_operator: float = 0.0
+    ms_gather_scatter: float = 0.0
+    ms_update: float = 0.0
+    operator_launches: int = 0
 
     @property
     def ok(self) -> bool:
@@ -184,20 +188,26 @@ class Mesh:
     def solve(self, b: torch.Tensor, x: Optional[torch.Tensor] = None, tol: float = 1e-10,
               max_iter: int = 5000, precision: str = "fp64", inner_tol: float = 1e-4,
               inner_max_iter: int = 0, poll_every: int = 16, use_graph: bool = True,
-              fixed_iters: int = 0, stream=None, raise_on_error: bool = True) -> Tuple[torch.Tensor, SolveResult]:
-        """Jacobi-PCG for A x = b; x (if given) is the initial guess and is overwritten."""
+              fixed_iters: int = 0, profile: bool = False, initial_guess: Optional[bool] = None,
+              stream=None, raise_on_error: bool = True) -> Tuple[torch.Tensor, SolveResult]:
+        """Jacobi-PCG for A x = b.  x receives the solution; it is also the initial
+        guess when initial_guess is True (default: whenever x is given)."""
         o = L.SolveOpts()
         self._lib.sem_solve_opts_default(C.byref(o))
         o.tol, o.max_iter = float(tol), int(max_iter)
         o.precision = SEM_PREC_MIXED if precision == "mixed" else SEM_PREC_FP64
         o.inner_tol, o.inner_max_iter = float(inner_tol), int(inner_max_iter)
         o.poll_every, o.use_graph, o.fixed_iters = int(poll_every), int(bool(use_graph)), int(fixed_iters)
-        o.x0_given = 0 if x is None else 1
+        if initial_guess is None:
+            initial_guess = x is not None
+        o.x0_given = int(bool(initial_guess) and x is not None)
+        o.profile = int(bool(profile))
         x = self.zeros() if x is None else x
         st = L.SolveStats()
         status = self._lib.sem_pcg_solve(self._h, self._vec(b, "b", torch.float64), self._vec(x, "x", torch.float64),
                                          C.byref(o), C.byref(st), _stream_handle(stream))
-        res = SolveResult(st.status, st.iterations, st.outer_iterations, st.rel_residual, st.bnorm, st.seconds)
+        res = SolveResult(st.status, st.iterations, st.outer_iterations, st.rel_residual, st.bnorm, st.seconds,
+                          st.ms_operator, st.ms_gather_scatter, st.ms_update, st.operator_launches)
         if raise_on_error and status != L.SEM_OK:
             raise SemError(status, "sem_pcg_solve")
         return x, res
@@ -217,6 +227,15 @@ class Mesh:
         inv = np.zeros(self.n_local)
         L.check(self._lib.sem_export_geom(self._h, G.ctypes.data, B.ctypes.data, inv.ctypes.data), "sem_export_geom")
         return G, B, inv
+
+    def load_geometry(self, G: np.ndarray, B: np.ndarray, stream=None):
+        """Replace the geometric factors G[6, n_local] and mass B[n_local] (host arrays)."""
+        G = np.ascontiguousarray(G, dtype=np.float64)
+        B = np.ascontiguousarray(B, dtype=np.float64)
+        if G.shape != (6, self.n_local) or B.shape != (self.n_local,):
+            raise ValueError("load_geometry: expected G[6, n_local] and B[n_local]")
+        L.check(self._lib.sem_load_geometry(self._h, G.ctypes.data, B.ctypes.data, _stream_handle(stream)),
+                "sem_load_geometry")
 
     def export_coords(self):
         xyz = np.zeros((3, self.n_local))

@@ -39,12 +39,15 @@ class MeshInfo(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("precision", C.c_int),
                 ("inner_tol", C.c_double), ("inner_max_iter", C.c_int), ("poll_every", C.c_int),
-                ("use_graph", C.c_int), ("fixed_iters", C.c_int), ("x0_given", C.c_int)]
+                ("use_graph", C.c_int), ("fixed_iters", C.c_int), ("x0_given", C.c_int),
+                ("profile", C.c_int)]
 
 
 class SolveStats(C.Structure):
     _fields_ = [("status", C.c_int), ("iterations", C.c_int), ("outer_iterations", C.c_int),
-                ("rel_residual", C.c_double), ("bnorm", C.c_double), ("seconds", C.c_double)]
+                ("rel_residual", C.c_double), ("bnorm", C.c_double), ("seconds", C.c_double),
+                ("ms_operator", C.c_double), ("ms_gather_scatter", C.c_double), ("ms_update", C.c_double),
+                ("operator_launches", C.c_int)]
 
 
 # name -> (restype, argtypes); kept in step with include/sem.h
@@ -60,6 +63,7 @@ SIGNATURES = {
     "sem_export_geom": (_i, [_vp, _vp, _vp, _vp]),
     "sem_export_coords": (_i, [_vp, _vp]),
     "sem_host_setup": (_i, [C.POINTER(MeshDesc), C.POINTER(MeshInfo), _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "sem_load_geometry": (_i, [_vp, _vp, _vp, _vp]),
     "sem_ax": (_i, [_vp, _i, _vp, _vp, _vp, _vp]),
     "sem_gs": (_i, [_vp, _i, _vp, _vp]),
     "sem_axgs": (_i, [_vp, _i, _vp, _vp, _vp]),

@@ -168,29 +168,70 @@ static void enqueue_gs(sem_mesh *m, T *v, const PcgState *st, hipStream_t s)
     SEM_HIP(launch_gs<T>(0, m->h.gs_n_sum, m->h.gs_n_ids, m->gs_off, m->gs_idx, v, st, s));
 }
 
+// Per-kernel-class timing with HIP events recorded on the launch stream.
+struct Profiler {
+    sem_mesh *m = nullptr;
+    size_t used = 0;
+    std::vector<hipEvent_t> marks;  // 4 per iteration
+    double ms_op = 0, ms_gs = 0, ms_up = 0;
+    int launches = 0;
+    hipEvent_t mark(hipStream_t s)
+    {
+        if (used == m->events.size()) {
+            hipEvent_t e;
+            SEM_HIP(hipEventCreate(&e));
+            m->events.push_back(e);
+        }
+        hipEvent_t e = m->events[used++];
+        SEM_HIP(hipEventRecord(e, s));
+        marks.push_back(e);
+        return e;
+    }
+    void flush(hipStream_t s)
+    {
+        if (marks.empty()) return;
+        SEM_HIP(hipStreamSynchronize(s));
+        for (size_t q = 0; q + 3 < marks.size(); q += 4) {
+            float a = 0, b = 0, c = 0;
+            SEM_HIP(hipEventElapsedTime(&a, marks[q], marks[q + 1]));
+            SEM_HIP(hipEventElapsedTime(&b, marks[q + 1], marks[q + 2]));
+            SEM_HIP(hipEventElapsedTime(&c, marks[q + 2], marks[q + 3]));
+            ms_op += a; ms_gs += b; ms_up += c;
+            launches++;
+        }
+        marks.clear();
+        used = 0;
+    }
+};
+
 // one CG iteration: w = A p (p updated from z and beta first), gs, alpha,
 // x/r update with <r,z>, <r,r>, beta
 template <typename T>
-static void enqueue_iterations(sem_mesh *m, int k, hipStream_t s)
+static void enqueue_iterations(sem_mesh *m, int k, hipStream_t s, Profiler *prof = nullptr)
 {
     PcgState *st = Prec<T>::st(m);
     const int64_t axb = ax_blocks(m->h.E, m->ax_epw);
     const int64_t nL = m->h.nL;
     for (int it = 0; it < k; ++it) {
+        if (prof) prof->mark(s);
         enqueue_ax<T>(m, 2, Prec<T>::r(m), Prec<T>::w(m), s);
+        if (prof) prof->mark(s);
         enqueue_gs<T>(m, Prec<T>::w(m), st, s);
+        if (prof) prof->mark(s);
         SEM_HIP(launch_reduce_sigma(m->partials, axb, st, s));
         SEM_HIP(launch_pcg_update<T>(nL, st, Prec<T>::x(m), Prec<T>::r(m), Prec<T>::p(m), Prec<T>::w(m),
                                      Prec<T>::inv(m), m->mult, m->partials, s));
         SEM_HIP(launch_reduce_rho(m->partials, vec_blocks(nL), st, s));
+        if (prof) prof->mark(s);
     }
+    if (prof) prof->flush(s);
 }
 
 template <typename T>
-static void run_iterations(sem_mesh *m, int k, bool use_graph, hipStream_t s)
+static void run_iterations(sem_mesh *m, int k, bool use_graph, hipStream_t s, Profiler *prof = nullptr)
 {
-    if (!use_graph) {
-        enqueue_iterations<T>(m, k, s);
+    if (prof || !use_graph) {
+        enqueue_iterations<T>(m, k, s, prof);
         return;
     }
     const int slot = sizeof(T) == 8 ? 0 : 1;
@@ -249,14 +290,15 @@ static void true_residual(sem_mesh *m, const double *b, hipStream_t s, int slot)
 // Plain CG loop on precision T from the current r (x, p set by the caller);
 // returns the final device state.
 template <typename T>
-static PcgState cg_loop(sem_mesh *m, double stop2, int limit, int poll, bool graph, hipStream_t s)
+static PcgState cg_loop(sem_mesh *m, double stop2, int limit, int poll, bool graph, hipStream_t s,
+                        Profiler *prof = nullptr)
 {
     SEM_HIP(launch_pcg_init<T>(m->h.nL, Prec<T>::r(m), Prec<T>::inv(m), m->mult, m->partials, Prec<T>::st(m), stop2,
                                limit, s));
     SEM_HIP(hipMemsetAsync(Prec<T>::p(m), 0, sizeof(T) * m->h.nL, s));
     PcgState hs = read_state(Prec<T>::st(m), s);
     while (!hs.done) {
-        run_iterations<T>(m, poll, graph, s);
+        run_iterations<T>(m, poll, graph, s, prof);
         hs = read_state(Prec<T>::st(m), s);
     }
     return hs;
@@ -281,11 +323,17 @@ static sem_status solve_fp64(sem_mesh *m, const double *b, double *x, const sem_
         SEM_HIP(launch_pcg_init<double>(nL, m->r64, m->inv64, m->mult, m->partials, m->state, -1.0, o.fixed_iters, s));
         SEM_HIP(hipMemsetAsync(m->p64, 0, sizeof(double) * nL, s));
         int left = o.fixed_iters;
+        Profiler prof;
+        prof.m = m;
         while (left > 0) {
             const int k = std::min(left, poll);
-            run_iterations<double>(m, k, o.use_graph != 0, s);
+            run_iterations<double>(m, k, o.use_graph != 0, s, o.profile ? &prof : nullptr);
             left -= k;
         }
+        out.ms_operator = prof.ms_op;
+        out.ms_gather_scatter = prof.ms_gs;
+        out.ms_update = prof.ms_up;
+        out.operator_launches = prof.launches;
         const PcgState hs = read_state(m->state, s);
         SEM_HIP(hipMemcpyAsync(x, m->x64, sizeof(double) * nL, hipMemcpyDeviceToDevice, s));
         SEM_HIP(hipStreamSynchronize(s));
@@ -305,13 +353,16 @@ static sem_status solve_fp64(sem_mesh *m, const double *b, double *x, const sem_
         return SEM_OK;
     }
     const double stop2 = o.tol * o.tol * bb;
+    Profiler prof;
+    prof.m = m;
+    Profiler *pp = o.profile ? &prof : nullptr;
     int total = 0, restarts = 0;
     bool have_x = o.x0_given != 0;
     double rel = 0.0;
     for (;;) {
         if (have_x) true_residual(m, b, s, 1);
         else SEM_HIP(hipMemcpyAsync(m->r64, b, sizeof(double) * nL, hipMemcpyDeviceToDevice, s));
-        const PcgState hs = cg_loop<double>(m, stop2, o.max_iter - total, poll, o.use_graph != 0, s);
+        const PcgState hs = cg_loop<double>(m, stop2, o.max_iter - total, poll, o.use_graph != 0, s, pp);
         total += hs.iters;
         have_x = true;
         if (hs.done == 2) {
@@ -336,6 +387,10 @@ static sem_status solve_fp64(sem_mesh *m, const double *b, double *x, const sem_
     out.iterations = total;
     out.outer_iterations = restarts + 1;
     out.rel_residual = rel;
+    out.ms_operator = prof.ms_op;
+    out.ms_gather_scatter = prof.ms_gs;
+    out.ms_update = prof.ms_up;
+    out.operator_launches = prof.launches;
     return status;
 }
 
@@ -355,6 +410,9 @@ static sem_status solve_mixed(sem_mesh *m, const double *b, double *x, const sem
     sem_status status = SEM_OK;
     int total = 0, outer = 0;
     double rel = 0.0;
+    Profiler prof;
+    prof.m = m;
+    Profiler *pp = o.profile ? &prof : nullptr;
     if (bb == 0.0) {
         SEM_HIP(hipMemsetAsync(x, 0, sizeof(double) * nL, s));
         SEM_HIP(hipStreamSynchronize(s));
@@ -378,7 +436,7 @@ static sem_status solve_mixed(sem_mesh *m, const double *b, double *x, const sem
         SEM_HIP(launch_to_fp32_scaled(nL, m->r64, m->scal + 1, m->r32, s));
         SEM_HIP(hipMemsetAsync(m->x32, 0, sizeof(float) * nL, s));
         const int limit = std::min(inner_max, o.max_iter - total);
-        const PcgState hs = cg_loop<float>(m, o.inner_tol * o.inner_tol, limit, poll, o.use_graph != 0, s);
+        const PcgState hs = cg_loop<float>(m, o.inner_tol * o.inner_tol, limit, poll, o.use_graph != 0, s, pp);
         total += hs.iters;
         outer++;
         if (hs.iters == 0 && hs.done == 2) {
@@ -394,6 +452,10 @@ static sem_status solve_mixed(sem_mesh *m, const double *b, double *x, const sem
     out.iterations = total;
     out.outer_iterations = outer;
     out.rel_residual = rel;
+    out.ms_operator = prof.ms_op;
+    out.ms_gather_scatter = prof.ms_gs;
+    out.ms_update = prof.ms_up;
+    out.operator_launches = prof.launches;
     return status;
 }
 
@@ -465,8 +527,6 @@ sem_status sem_setup(const sem_mesh_desc *desc, void *stream, sem_mesh **out)
             std::vector<double>().swap(h.B);
             std::vector<double>().swap(h.invdiag);
             std::vector<double>().swap(h.xyz);
-            std::vector<int32_t>().swap(h.gs_idx);
-            std::vector<int32_t>().swap(h.gs_off);
         } catch (...) {
             sem_free(m);
             throw;
@@ -482,6 +542,7 @@ sem_status sem_free(sem_mesh *m)
     for (int q = 0; q < 2; ++q)
         if (m->graph[q]) hipGraphExecDestroy(m->graph[q]);
     if (m->capture_stream) hipStreamDestroy(m->capture_stream);
+    for (hipEvent_t e : m->events) hipEventDestroy(e);
     for (void *p : m->allocations) hipFree(p);
     delete m;
     return SEM_OK;
@@ -609,6 +670,38 @@ sem_status sem_host_setup(const sem_mesh_desc *desc, sem_mesh_info *info, int64_
     });
 }
 
+sem_status sem_load_geometry(sem_mesh *m, const double *G, const double *B, void *stream)
+{
+    return guarded([&]() -> sem_status {
+        if (!m || !G || !B) fail(SEM_EINVAL, "sem_load_geometry: null argument");
+        hipStream_t s = (hipStream_t)stream;
+        HostMesh &h = m->h;
+        const int64_t nL = h.nL, P3 = (int64_t)h.P * h.P * h.P;
+        try {
+            h.G.assign((size_t)6 * nL, 0.0);
+            for (int64_t e = 0; e < h.E; ++e)
+                for (int c = 0; c < 6; ++c)
+                    std::memcpy(h.G.data() + (e * 6 + c) * P3, G + c * nL + e * P3, sizeof(double) * P3);
+            build_jacobi(h);
+            upload(m->G64, h.G.data(), sizeof(double) * 6 * nL, s);
+            upload(m->B64, B, sizeof(double) * nL, s);
+            upload(m->inv64, h.invdiag.data(), sizeof(double) * nL, s);
+            if (m->with_fp32) {
+                SEM_HIP(launch_fp64_to_fp32(6 * nL, m->G64, m->G32, s));
+                SEM_HIP(launch_fp64_to_fp32(nL, m->inv64, m->inv32, s));
+            }
+            SEM_HIP(hipStreamSynchronize(s));
+        } catch (...) {
+            std::vector<double>().swap(h.G);
+            std::vector<double>().swap(h.invdiag);
+            throw;
+        }
+        std::vector<double>().swap(h.G);
+        std::vector<double>().swap(h.invdiag);
+        return SEM_OK;
+    });
+}
+
 static void check_dtype(const sem_mesh *m, int dtype)
 {
     if (dtype != SEM_FP64 && dtype != SEM_FP32) fail(SEM_EINVAL, "unknown dtype");
@@ -685,6 +778,7 @@ void sem_solve_opts_default(sem_solve_opts *o)
     o->use_graph = 1;
     o->fixed_iters = 0;
     o->x0_given = 0;
+    o->profile = 0;
 }
 
 sem_status sem_pcg_solve(sem_mesh *m, const double *b, double *x, const sem_solve_opts *opts, sem_solve_stats *stats,

@@ -51,6 +51,7 @@ void gll_rule(int N, std::vector<double> &xi, std::vector<double> &w);
 void lagrange_derivative(const std::vector<double> &xi, std::vector<double> &D);
 void build_host_mesh(const sem_mesh_desc &d, HostMesh &h);
 void build_host_coords(const sem_mesh_desc &d, HostMesh &h);
+void build_jacobi(HostMesh &h);  // from h.G (element-blocked), h.gs plan, h.gid, h.gmask
 void host_parallel_for(int64_t n, const std::function<void(int64_t, int64_t)> &body);
 
 // ---------------------------------------------------------------------------
@@ -100,6 +101,7 @@ struct sem_mesh {
     sem::PcgState *state = nullptr;  // [2]: FP64 solve, FP32 inner solve
     double *scal = nullptr;          // small device scratch for norms
     int ax_epw = 1;                  // elements per workgroup of the operator
+    std::vector<hipEvent_t> events;  // profiling event pool
     hipStream_t capture_stream = nullptr;
     hipGraphExec_t graph[2] = {nullptr, nullptr};  // CG iteration blocks, FP64 / FP32
     int graph_k[2] = {0, 0};

@@ -341,6 +341,8 @@ void build_gs_plan(HostMesh &h)
     h.gs_plan_len = pos;
 }
 
+}  // namespace
+
 // Local diagonal of Algorithm 1's operator at (i,j,k), obtained by applying
 // it to the unit vector of that node:
 //   sum_l D[l][i]^2 g1(l,j,k) + sum_l D[l][j]^2 g2(i,l,k) + sum_l D[l][k]^2 g3(i,j,l)
@@ -392,10 +394,8 @@ void build_jacobi(HostMesh &h)
             h.invdiag[l] = 1.0 / h.invdiag[l];
         }
     }
-    if (bad) fail(SEM_EINVAL, "sem_setup: non-positive assembled diagonal (degenerate mesh)");
+    if (bad) fail(SEM_EINVAL, "non-positive assembled diagonal (degenerate mesh)");
 }
-
-}  // namespace
 
 void build_host_coords(const sem_mesh_desc &d, HostMesh &h)
 {
