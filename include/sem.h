@@ -143,6 +143,15 @@ sem_status sem_host_setup(const sem_mesh_desc *desc, sem_mesh_info *info, int64_
  * Errors: SEM_EINVAL (null pointers, non-positive assembled diagonal). */
 sem_status sem_load_geometry(sem_mesh *mesh, const double *G, const double *B, void *stream);
 
+/* Launch configuration of the local operator on this mesh: elements per
+ * workgroup (1 <= epw, epw (N+1)^2 <= 256) and the number of persistent
+ * workgroups (grid > 0; 0 keeps the default of 16 per compute unit).  Results
+ * of sem_ax / sem_axgs do not depend on it; CG dot products do at rounding
+ * level (their partial sums follow the workgroups).  The autotuner sets it;
+ * sem_get_operator_config reads it. */
+sem_status sem_set_operator_config(sem_mesh *mesh, int epw, int grid);
+sem_status sem_get_operator_config(const sem_mesh *mesh, int *epw, int *grid);
+
 /* Local operator, Algorithm 1: w = A_L u element by element (no
  * gather-scatter).  u, w: device E-vectors of `dtype` (SEM_FP64 or SEM_FP32;
  * FP32 needs SEM_WITH_FP32).  opt_dot (device double, may be NULL) receives
@@ -218,6 +227,50 @@ void sem_solve_opts_default(sem_solve_opts *opts);
  * last iterate), SEM_EBREAKDOWN, SEM_EINVAL, SEM_EHIP. */
 sem_status sem_pcg_solve(sem_mesh *mesh, const double *b, double *x, const sem_solve_opts *opts,
                          sem_solve_stats *stats, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Batched and continuous solves.  A batch holds up to max_slots concurrent
+ * solves ("slots"), each on any mesh (orders 2..10, any size) with its own
+ * right-hand side, solution and precision.  Every CG phase of all slots runs
+ * as one persistent launch over a table of (slot, element tile) work items --
+ * the paper moves loops of small kernels inside the kernel (section 3) -- and
+ * poll_every iterations are replayed as one hipGraph.  Each slot's dot
+ * products are summed from its own items in a fixed order, so a slot's result
+ * does not depend on which other slots share the launches.
+ *
+ * Ownership: the batch owns its slot vectors (allocated within
+ * device_budget bytes, 0 = unlimited, reused after retirement); meshes, b and
+ * x stay the caller's and must outlive the slots that use them.
+ */
+typedef struct sem_batch sem_batch;
+
+sem_status sem_batch_create(int max_slots, size_t device_budget, void *stream, sem_batch **out);
+sem_status sem_batch_free(sem_batch *batch);
+
+/* Autotuner: for every order among `meshes`, time the batched operator for
+ * each candidate elements-per-workgroup and keep the fastest; then choose the
+ * persistent grid size.  The batch must have no admitted slots. */
+sem_status sem_batch_tune(sem_batch *batch, sem_mesh *const *meshes, int n, void *stream);
+sem_status sem_batch_set_epw(sem_batch *batch, int N, int epw);  /* 0 restores the default */
+sem_status sem_batch_get_epw(const sem_batch *batch, int N, int *epw);
+
+/* One-shot: solve A_i x_i = b_i for i < n together (b_i, x_i device FP64
+ * E-vectors of mesh i; opts as for sem_pcg_solve, shared by all; stats: n
+ * entries or NULL).  Returns SEM_OK when every system converged, else the
+ * first failing status. */
+sem_status sem_batch_solve(sem_batch *batch, sem_mesh *const *meshes, int n, const double *const *b,
+                           double *const *x, const sem_solve_opts *opts, sem_solve_stats *stats, void *stream);
+
+/* Continuous batching: admit a solve into a free slot (SEM_EBUDGET when no
+ * slot or no memory within the budget is left), advance all admitted slots by
+ * `iterations` CG iterations (serving phase changes -- residual checks,
+ * restarts, mixed-precision refinement steps -- at the step boundary), list
+ * finished slots, and retire a slot (its stats; the slot becomes free). */
+sem_status sem_batch_admit(sem_batch *batch, sem_mesh *mesh, const double *b, double *x,
+                           const sem_solve_opts *opts, int *slot, void *stream);
+sem_status sem_batch_step(sem_batch *batch, int iterations, int use_graph, void *stream, int *n_active);
+sem_status sem_batch_finished(const sem_batch *batch, int *slots, int capacity, int *n);
+sem_status sem_batch_retire(sem_batch *batch, int slot, sem_solve_stats *stats);
 
 #ifdef __cplusplus
 }

@@ -19,7 +19,7 @@ from . import _lib as L
 from ._lib import (SEM_FP32, SEM_FP64, SEM_MAP_BOX, SEM_MAP_PIPE_SQ2DISK, SEM_MAX_ORDER,
                    SEM_PREC_FP64, SEM_PREC_MIXED, SemError)
 
-__all__ = ["Mesh", "SolveResult", "SemError", "box_mesh", "pipe_mesh", "export_gll", "version",
+__all__ = ["Mesh", "Batch", "SolveResult", "SemError", "box_mesh", "pipe_mesh", "export_gll", "version",
            "SEM_FP64", "SEM_FP32", "SEM_MAP_BOX", "SEM_MAP_PIPE_SQ2DISK", "SEM_MAX_ORDER"]
 
 
@@ -143,6 +143,16 @@ class Mesh:
     def zeros(self, dtype=torch.float64) -> torch.Tensor:
         return torch.zeros(self.n_local, dtype=dtype, device=self.device)
 
+    # -- launch configuration -------------------------------------------------
+    def set_operator_config(self, epw: int, grid: int = 0):
+        """Elements per workgroup and persistent grid size of the operator (0 = default)."""
+        L.check(self._lib.sem_set_operator_config(self._h, int(epw), int(grid)), "sem_set_operator_config")
+
+    def operator_config(self):
+        e, g = C.c_int(), C.c_int()
+        L.check(self._lib.sem_get_operator_config(self._h, C.byref(e), C.byref(g)), "sem_get_operator_config")
+        return e.value, g.value
+
     # -- operators -----------------------------------------------------------
     def ax(self, u: torch.Tensor, w: Optional[torch.Tensor] = None, dot: bool = False, stream=None):
         """w = A_L u (no gather-scatter); with dot=True also returns sum u.w (device scalar)."""
@@ -241,6 +251,114 @@ class Mesh:
         xyz = np.zeros((3, self.n_local))
         L.check(self._lib.sem_export_coords(self._h, xyz.ctypes.data), "sem_export_coords")
         return xyz
+
+
+def _opts(lib, tol=1e-10, max_iter=5000, precision="fp64", inner_tol=1e-4, inner_max_iter=0,
+          poll_every=16, use_graph=True):
+    o = L.SolveOpts()
+    lib.sem_solve_opts_default(C.byref(o))
+    o.tol, o.max_iter = float(tol), int(max_iter)
+    o.precision = SEM_PREC_MIXED if precision == "mixed" else SEM_PREC_FP64
+    o.inner_tol, o.inner_max_iter = float(inner_tol), int(inner_max_iter)
+    o.poll_every, o.use_graph = int(poll_every), int(bool(use_graph))
+    return o
+
+
+def _result(st) -> SolveResult:
+    return SolveResult(st.status, st.iterations, st.outer_iterations, st.rel_residual, st.bnorm, st.seconds,
+                       st.ms_operator, st.ms_gather_scatter, st.ms_update, st.operator_launches)
+
+
+class Batch:
+    """Many concurrent solves advanced by persistent batched kernels (C ABI
+    sem_batch_*).  Meshes, right-hand sides and solutions passed in are kept
+    referenced here until their slot is retired."""
+
+    def __init__(self, max_slots: int = 64, budget_bytes: int = 0, stream=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("paper_2109_03592_amd needs a ROCm GPU (gfx950); none is visible")
+        self._lib = L.load()
+        h = C.c_void_p()
+        L.check(self._lib.sem_batch_create(int(max_slots), C.c_size_t(int(budget_bytes)), _stream_handle(stream),
+                                           C.byref(h)), "sem_batch_create")
+        self._h = h
+        self.max_slots = int(max_slots)
+        self._held = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.sem_batch_free(self._h)
+            self._h = None
+            self._held.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def tune(self, meshes, stream=None):
+        """Autotune elements per workgroup per order (and the operator grid) on these meshes."""
+        arr = (C.c_void_p * len(meshes))(*[m._h.value for m in meshes])
+        L.check(self._lib.sem_batch_tune(self._h, arr, len(meshes), _stream_handle(stream)), "sem_batch_tune")
+
+    def set_epw(self, N: int, epw: int):
+        L.check(self._lib.sem_batch_set_epw(self._h, int(N), int(epw)), "sem_batch_set_epw")
+
+    def epw(self, N: int) -> int:
+        e = C.c_int()
+        L.check(self._lib.sem_batch_get_epw(self._h, int(N), C.byref(e)), "sem_batch_get_epw")
+        return e.value
+
+    def solve(self, meshes, bs, xs=None, stream=None, raise_on_error: bool = True, **kw):
+        """Solve A_i x_i = b_i together; returns (xs, [SolveResult])."""
+        n = len(meshes)
+        xs = [m.zeros() for m in meshes] if xs is None else list(xs)
+        for m, b, x in zip(meshes, bs, xs):
+            m._vec(b, "b", torch.float64)
+            m._vec(x, "x", torch.float64)
+        o = _opts(self._lib, **kw)
+        harr = (C.c_void_p * n)(*[m._h.value for m in meshes])
+        barr = (C.c_void_p * n)(*[b.data_ptr() for b in bs])
+        xarr = (C.c_void_p * n)(*[x.data_ptr() for x in xs])
+        stats = (L.SolveStats * n)()
+        status = self._lib.sem_batch_solve(self._h, harr, n, barr, xarr, C.byref(o), stats, _stream_handle(stream))
+        res = [_result(stats[i]) for i in range(n)]
+        if raise_on_error and status != L.SEM_OK:
+            raise SemError(status, "sem_batch_solve")
+        return xs, res
+
+    def admit(self, mesh, b, x=None, stream=None, **kw) -> int:
+        """Admit one solve (x: solution, zero initial guess); returns its slot."""
+        x = mesh.zeros() if x is None else x
+        mesh._vec(b, "b", torch.float64)
+        mesh._vec(x, "x", torch.float64)
+        o = _opts(self._lib, **kw)
+        slot = C.c_int()
+        L.check(self._lib.sem_batch_admit(self._h, mesh._h, b.data_ptr(), x.data_ptr(), C.byref(o), C.byref(slot),
+                                          _stream_handle(stream)), "sem_batch_admit")
+        self._held[slot.value] = (mesh, b, x)
+        return slot.value
+
+    def step(self, iterations: int = 16, use_graph: bool = True, stream=None) -> int:
+        n = C.c_int()
+        L.check(self._lib.sem_batch_step(self._h, int(iterations), int(bool(use_graph)), _stream_handle(stream),
+                                         C.byref(n)), "sem_batch_step")
+        return n.value
+
+    def finished(self):
+        cap = self.max_slots
+        arr = (C.c_int * cap)()
+        n = C.c_int()
+        L.check(self._lib.sem_batch_finished(self._h, arr, cap, C.byref(n)), "sem_batch_finished")
+        return [arr[i] for i in range(min(n.value, cap))]
+
+    def retire(self, slot: int):
+        """Free a slot; returns (x, SolveResult)."""
+        st = L.SolveStats()
+        L.check(self._lib.sem_batch_retire(self._h, int(slot), C.byref(st)), "sem_batch_retire")
+        _, _, x = self._held.pop(slot, (None, None, None))
+        return x, _result(st)
 
 
 def box_mesh(N: int, nel: Sequence[int], vertices=None, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0),

@@ -64,11 +64,24 @@ SIGNATURES = {
     "sem_export_coords": (_i, [_vp, _vp]),
     "sem_host_setup": (_i, [C.POINTER(MeshDesc), C.POINTER(MeshInfo), _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "sem_load_geometry": (_i, [_vp, _vp, _vp, _vp]),
+    "sem_set_operator_config": (_i, [_vp, _i, _i]),
+    "sem_get_operator_config": (_i, [_vp, C.POINTER(_i), C.POINTER(_i)]),
     "sem_ax": (_i, [_vp, _i, _vp, _vp, _vp, _vp]),
     "sem_gs": (_i, [_vp, _i, _vp, _vp]),
     "sem_axgs": (_i, [_vp, _i, _vp, _vp, _vp]),
     "sem_mass": (_i, [_vp, _vp, _vp, _vp]),
     "sem_scatter": (_i, [_vp, _vp, _vp, _vp]),
+    "sem_batch_create": (_i, [_i, C.c_size_t, _vp, C.POINTER(_vp)]),
+    "sem_batch_free": (_i, [_vp]),
+    "sem_batch_tune": (_i, [_vp, C.POINTER(_vp), _i, _vp]),
+    "sem_batch_set_epw": (_i, [_vp, _i, _i]),
+    "sem_batch_get_epw": (_i, [_vp, _i, C.POINTER(_i)]),
+    "sem_batch_solve": (_i, [_vp, C.POINTER(_vp), _i, C.POINTER(_vp), C.POINTER(_vp), C.POINTER(SolveOpts),
+                             _vp, _vp]),
+    "sem_batch_admit": (_i, [_vp, _vp, _vp, _vp, C.POINTER(SolveOpts), C.POINTER(_i), _vp]),
+    "sem_batch_step": (_i, [_vp, _i, _i, _vp, C.POINTER(_i)]),
+    "sem_batch_finished": (_i, [_vp, C.POINTER(_i), _i, C.POINTER(_i)]),
+    "sem_batch_retire": (_i, [_vp, _i, C.POINTER(SolveStats)]),
     "sem_solve_opts_default": (None, [C.POINTER(SolveOpts)]),
     "sem_pcg_solve": (_i, [_vp, _vp, _vp, C.POINTER(SolveOpts), C.POINTER(SolveStats), _vp]),
 }

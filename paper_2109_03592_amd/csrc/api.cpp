@@ -6,12 +6,15 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "kernels.hpp"
 #include "sem_internal.hpp"
 
 namespace sem {
+
+hipError_t upload_batch_dtables(const double *d64, const float *d32, hipStream_t s);
 
 static thread_local std::string g_err;
 
@@ -84,6 +87,47 @@ static int default_epw(int N)
     return best;
 }
 
+// Derivative matrices of every order in the kernels' constant table, once
+// per device.
+static void ensure_dtables(hipStream_t s)
+{
+    static std::mutex mu;
+    static std::vector<int> done;
+    int dev = 0;
+    SEM_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(mu);
+    if ((int)done.size() <= dev) done.resize(dev + 1, 0);
+    if (done[dev]) return;
+    std::vector<double> d64;
+    for (int N = 1; N <= SEM_MAX_ORDER; ++N) {
+        std::vector<double> xi, w, D;
+        gll_rule(N, xi, w);
+        lagrange_derivative(xi, D);
+        if ((int)d64.size() != dtable_offset_host(N)) fail(SEM_EINVAL, "derivative table layout");
+        d64.insert(d64.end(), D.begin(), D.end());
+    }
+    std::vector<float> d32(d64.begin(), d64.end());
+    SEM_HIP(upload_dtables(d64.data(), d32.data(), s));
+    SEM_HIP(upload_batch_dtables(d64.data(), d32.data(), s));
+    SEM_HIP(hipStreamSynchronize(s));
+    done[dev] = 1;
+}
+
+void ensure_dtables_all(hipStream_t s) { ensure_dtables(s); }
+int persistent_grid_cap_public();
+
+// Persistent operator grid: a few resident workgroups per compute unit.
+static int persistent_grid_cap()
+{
+    int dev = 0;
+    SEM_HIP(hipGetDevice(&dev));
+    int cus = 0;
+    SEM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    return std::max(64, cus * 16);
+}
+
+int persistent_grid_cap_public() { return persistent_grid_cap(); }
+
 static void require_device_gfx950()
 {
     int dev = 0;
@@ -122,7 +166,6 @@ template <typename T>
 struct Prec;
 template <>
 struct Prec<double> {
-    static const double *D(sem_mesh *m) { return m->D64; }
     static const double *G(sem_mesh *m) { return m->G64; }
     static const double *inv(sem_mesh *m) { return m->inv64; }
     static double *x(sem_mesh *m) { return m->x64; }
@@ -133,7 +176,6 @@ struct Prec<double> {
 };
 template <>
 struct Prec<float> {
-    static const float *D(sem_mesh *m) { return m->D32; }
     static const float *G(sem_mesh *m) { return m->G32; }
     static const float *inv(sem_mesh *m) { return m->inv32; }
     static float *x(sem_mesh *m) { return m->x32; }
@@ -149,7 +191,7 @@ static void enqueue_ax(sem_mesh *m, int mode, const T *in, T *out, hipStream_t s
     AxParams<T> a{};
     a.E = m->h.E;
     a.epw = m->ax_epw;
-    a.D = Prec<T>::D(m);
+    a.grid_cap = m->ax_grid_cap;
     a.G = Prec<T>::G(m);
     a.in = in;
     a.out = out;
@@ -165,7 +207,7 @@ static void enqueue_ax(sem_mesh *m, int mode, const T *in, T *out, hipStream_t s
 template <typename T>
 static void enqueue_gs(sem_mesh *m, T *v, const PcgState *st, hipStream_t s)
 {
-    SEM_HIP(launch_gs<T>(0, m->h.gs_n_sum, m->h.gs_n_ids, m->gs_off, m->gs_idx, v, st, s));
+    SEM_HIP(launch_gs<T>(m->gsplan, m->gs_off, m->gs_idx, v, false, st, s));
 }
 
 // Per-kernel-class timing with HIP events recorded on the launch stream.
@@ -210,7 +252,7 @@ template <typename T>
 static void enqueue_iterations(sem_mesh *m, int k, hipStream_t s, Profiler *prof = nullptr)
 {
     PcgState *st = Prec<T>::st(m);
-    const int64_t axb = ax_blocks(m->h.E, m->ax_epw);
+    const int64_t axb = ax_grid(m->h.E, m->ax_epw, m->ax_grid_cap);
     const int64_t nL = m->h.nL;
     for (int it = 0; it < k; ++it) {
         if (prof) prof->mark(s);
@@ -235,7 +277,8 @@ static void run_iterations(sem_mesh *m, int k, bool use_graph, hipStream_t s, Pr
         return;
     }
     const int slot = sizeof(T) == 8 ? 0 : 1;
-    if (!m->graph[slot] || m->graph_k[slot] != k || m->graph_epw[slot] != m->ax_epw) {
+    if (!m->graph[slot] || m->graph_k[slot] != k || m->graph_epw[slot] != m->ax_epw ||
+        m->graph_grid[slot] != m->ax_grid_cap) {
         if (m->graph[slot]) {
             SEM_HIP(hipGraphExecDestroy(m->graph[slot]));
             m->graph[slot] = nullptr;
@@ -258,6 +301,7 @@ static void run_iterations(sem_mesh *m, int k, bool use_graph, hipStream_t s, Pr
         m->graph[slot] = ex;
         m->graph_k[slot] = k;
         m->graph_epw[slot] = m->ax_epw;
+        m->graph_grid[slot] = m->ax_grid_cap;
     }
     SEM_HIP(hipGraphLaunch(m->graph[slot], s));
 }
@@ -488,35 +532,35 @@ sem_status sem_setup(const sem_mesh_desc *desc, void *stream, sem_mesh **out)
             SEM_HIP(hipGetDevice(&m->device));
             m->with_fp32 = (desc->precision_flags & SEM_WITH_FP32) ? 1 : 0;
             m->ax_epw = default_epw(h.N);
-            const int64_t nL = h.nL, P2 = (int64_t)h.P * h.P;
-            m->D64 = dalloc<double>(m, P2);
+            const int64_t nL = h.nL;
+            ensure_dtables(s);
             m->G64 = dalloc<double>(m, 6 * nL);
             m->B64 = dalloc<double>(m, nL);
             m->inv64 = dalloc<double>(m, nL);
             m->mult = dalloc<uint8_t>(m, nL);
             m->gid = dalloc<int32_t>(m, nL);
-            m->gs_off = dalloc<int32_t>(m, h.gs_n_ids + 1);
+            m->gsplan.n_sum = h.gs_n_sum;
+            m->gsplan.n_ids = h.gs_n_ids;
+            m->gs_off = dalloc<int32_t>(m, h.gs_off.size());
             m->gs_idx = dalloc<int32_t>(m, h.gs_idx.size());
-            const int64_t np = std::max<int64_t>(ax_blocks(h.E, 1), 2 * (int64_t)vec_blocks(nL)) + 64;
+            m->ax_grid_cap = persistent_grid_cap();
+            const int64_t np = std::max<int64_t>(std::max<int64_t>(m->ax_grid_cap, 65536), 2 * (int64_t)vec_blocks(nL)) + 64;
             m->partials = dalloc<double>(m, np);
             m->n_partials = np;
             m->state = dalloc<PcgState>(m, 2);
             m->scal = dalloc<double>(m, 8);
             std::vector<uint8_t> lmult((size_t)nL);
             for (int64_t l = 0; l < nL; ++l) lmult[l] = h.gmult[h.gid[l]];
-            upload(m->D64, h.D.data(), sizeof(double) * P2, s);
             upload(m->G64, h.G.data(), sizeof(double) * 6 * nL, s);
             upload(m->B64, h.B.data(), sizeof(double) * nL, s);
             upload(m->inv64, h.invdiag.data(), sizeof(double) * nL, s);
             upload(m->mult, lmult.data(), nL, s);
             upload(m->gid, h.gid.data(), sizeof(int32_t) * nL, s);
-            upload(m->gs_off, h.gs_off.data(), sizeof(int32_t) * (h.gs_n_ids + 1), s);
+            upload(m->gs_off, h.gs_off.data(), sizeof(int32_t) * h.gs_off.size(), s);
             upload(m->gs_idx, h.gs_idx.data(), sizeof(int32_t) * h.gs_idx.size(), s);
             if (m->with_fp32) {
-                m->D32 = dalloc<float>(m, P2);
                 m->G32 = dalloc<float>(m, 6 * nL);
                 m->inv32 = dalloc<float>(m, nL);
-                SEM_HIP(launch_fp64_to_fp32(P2, m->D64, m->D32, s));
                 SEM_HIP(launch_fp64_to_fp32(6 * nL, m->G64, m->G32, s));
                 SEM_HIP(launch_fp64_to_fp32(nL, m->inv64, m->inv32, s));
             }
@@ -702,6 +746,31 @@ sem_status sem_load_geometry(sem_mesh *m, const double *G, const double *B, void
     });
 }
 
+sem_status sem_set_operator_config(sem_mesh *m, int epw, int grid)
+{
+    return guarded([&]() -> sem_status {
+        if (!m) fail(SEM_EINVAL, "sem_set_operator_config: null mesh");
+        const int P2 = m->h.P * m->h.P;
+        if (epw < 1 || epw * P2 > 256) fail(SEM_EINVAL, "sem_set_operator_config: epw out of range");
+        if (grid < 0) fail(SEM_EINVAL, "sem_set_operator_config: negative grid");
+        const int cap = grid > 0 ? grid : persistent_grid_cap();
+        if (cap > m->n_partials - 64) fail(SEM_EINVAL, "sem_set_operator_config: grid larger than the partials buffer");
+        m->ax_epw = epw;
+        m->ax_grid_cap = cap;
+        return SEM_OK;
+    });
+}
+
+sem_status sem_get_operator_config(const sem_mesh *m, int *epw, int *grid)
+{
+    return guarded([&]() -> sem_status {
+        if (!m) fail(SEM_EINVAL, "sem_get_operator_config: null mesh");
+        if (epw) *epw = m->ax_epw;
+        if (grid) *grid = m->ax_grid_cap;
+        return SEM_OK;
+    });
+}
+
 static void check_dtype(const sem_mesh *m, int dtype)
 {
     if (dtype != SEM_FP64 && dtype != SEM_FP32) fail(SEM_EINVAL, "unknown dtype");
@@ -718,7 +787,7 @@ sem_status sem_ax(sem_mesh *m, int dtype, const void *u, void *w, double *opt_do
         const int mode = opt_dot ? 1 : 0;
         if (dtype == SEM_FP64) enqueue_ax<double>(m, mode, (const double *)u, (double *)w, s);
         else enqueue_ax<float>(m, mode, (const float *)u, (float *)w, s);
-        if (opt_dot) SEM_HIP(launch_reduce_scalar(m->partials, ax_blocks(m->h.E, m->ax_epw), opt_dot, s));
+        if (opt_dot) SEM_HIP(launch_reduce_scalar(m->partials, ax_grid(m->h.E, m->ax_epw, m->ax_grid_cap), opt_dot, s));
         return SEM_OK;
     });
 }
@@ -760,8 +829,7 @@ sem_status sem_scatter(sem_mesh *m, const double *v_global, double *u_local, voi
         hipStream_t s = (hipStream_t)stream;
         SEM_HIP(launch_scatter(m->h.nL, m->gid, v_global, u_local, s));
         // masked ids only: every copy set to 0
-        SEM_HIP(launch_gs<double>(m->h.gs_n_sum, m->h.gs_n_sum, m->h.gs_n_ids, m->gs_off, m->gs_idx, u_local,
-                                  nullptr, s));
+        SEM_HIP(launch_gs<double>(m->gsplan, m->gs_off, m->gs_idx, u_local, true, nullptr, s));
         return SEM_OK;
     });
 }

@@ -1,0 +1,855 @@
+// batch.cpp -- host side of batched CG: slots, groups, phase transitions,
+// the autotuner and the C ABI of sem_batch_*.
+//
+// Each slot walks a small state machine:
+//   FP64 : START -> CG64 -> CHECK -> DONE   (CHECK restarts CG64 at most 3x)
+//   mixed: RESID -> CG32 -> RESID -> ... -> DONE
+// START/CHECK/RESID are served together by one batched FP64 residual
+// (operator, gather-scatter, r = b - A x, <r,r>); CG64 and CG32 slots are
+// advanced by replaying one hipGraph per precision whose kernels read the
+// group's work tables from fixed device addresses, so membership changes only
+// rewrite table contents.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+
+#include "batch.hpp"
+#include "kernels.hpp"
+
+namespace sem {
+
+hipError_t upload_batch_dtables(const double *d64, const float *d32, hipStream_t s);
+void ensure_dtables_all(hipStream_t s);
+int persistent_grid_cap_public();
+
+enum Phase { PH_FREE = 0, PH_START, PH_CG64, PH_CHECK, PH_RESID, PH_CG32, PH_DONE };
+
+struct HostSlot {
+    int phase = PH_FREE;
+    sem_mesh *mesh = nullptr;
+    sem_solve_opts opts{};
+    const double *b = nullptr;
+    double *x = nullptr;
+    int iters = 0, outer = 0, restarts = 0;
+    double bb = -1.0, rel = 0.0;
+    sem_status status = SEM_OK;
+    void *buf = nullptr;     // slot-owned device vectors
+    size_t buf_bytes = 0;
+    std::chrono::steady_clock::time_point t0;
+    double seconds = 0.0;
+};
+
+struct Group {
+    // device
+    int32_t *slots = nullptr;
+    int64_t *counts = nullptr;
+    Item *ax_items = nullptr, *gs_items = nullptr, *vec_items = nullptr;
+    int64_t *ax_first = nullptr, *ax_count = nullptr, *vec_first = nullptr, *vec_count = nullptr;
+    double *ax_partial = nullptr, *vec_partial = nullptr;
+    // capacities
+    int64_t cap_ax = 0, cap_gs = 0, cap_vec = 0;
+    // host mirror
+    std::vector<int32_t> h_slots;
+    std::vector<Item> h_ax, h_gs, h_vec;
+    std::vector<int64_t> h_axf, h_axc, h_vf, h_vc;
+    size_t lds = 0;
+    hipGraphExec_t graph = nullptr;
+    int graph_k = 0;
+    size_t graph_lds = 0;
+    GroupDev dev() const
+    {
+        GroupDev g;
+        g.slots = slots;
+        g.counts = counts;
+        g.ax_items = ax_items;
+        g.gs_items = gs_items;
+        g.vec_items = vec_items;
+        g.ax_first = ax_first;
+        g.ax_count = ax_count;
+        g.vec_first = vec_first;
+        g.vec_count = vec_count;
+        g.ax_partial = ax_partial;
+        g.vec_partial = vec_partial;
+        return g;
+    }
+};
+
+}  // namespace sem
+
+struct sem_batch {
+    int max_slots = 0;
+    size_t budget = 0, used = 0;
+    int device = 0;
+    std::vector<sem::HostSlot> slots;
+    std::vector<sem::SlotDesc> h_desc;
+    sem::SlotDesc *d_desc = nullptr;
+    sem::PcgState *d_state = nullptr;   // 2 per slot
+    double *d_scal = nullptr;           // 2 per slot
+    sem::Group g64, g32, gres;          // CG64, CG32, residual
+    int epw[SEM_MAX_ORDER + 1] = {0};   // elements per operator tile, per order
+    sem::BatchLaunch L{};
+    hipStream_t capture = nullptr;
+    std::vector<void *> allocations;
+    std::multimap<size_t, void *> free_bufs;
+    std::vector<sem::PcgState> h_state;
+};
+
+namespace sem {
+
+template <typename F>
+static sem_status bguard(F &&f)
+{
+    try {
+        return f();
+    } catch (const Failure &x) {
+        return x.status;
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return SEM_ENOMEM;
+    } catch (const std::exception &x) {
+        set_error(x.what());
+        return SEM_EINVAL;
+    }
+}
+
+static void *balloc(sem_batch *B, size_t bytes)
+{
+    void *p = nullptr;
+    SEM_HIP(hipMalloc(&p, std::max<size_t>(bytes, 16)));
+    B->allocations.push_back(p);
+    return p;
+}
+
+static int default_batch_epw(int N)
+{
+    const int P2 = (N + 1) * (N + 1);
+    int best = 1;
+    double best_fill = 0.0;
+    for (int e = 1; e * P2 <= kBatchBlock; ++e) {
+        const double fill = (double)(e * P2) / kBatchBlock;
+        if (fill > best_fill + 1e-9) {
+            best_fill = fill;
+            best = e;
+        }
+    }
+    return best;
+}
+
+static void group_alloc(sem_batch *B, Group &g)
+{
+    const int ms = B->max_slots;
+    g.slots = (int32_t *)balloc(B, sizeof(int32_t) * ms);
+    g.counts = (int64_t *)balloc(B, sizeof(int64_t) * 4);
+    g.ax_first = (int64_t *)balloc(B, sizeof(int64_t) * ms);
+    g.ax_count = (int64_t *)balloc(B, sizeof(int64_t) * ms);
+    g.vec_first = (int64_t *)balloc(B, sizeof(int64_t) * ms);
+    g.vec_count = (int64_t *)balloc(B, sizeof(int64_t) * ms);
+    g.cap_ax = g.cap_gs = g.cap_vec = 0;
+    SEM_HIP(hipMemset(g.counts, 0, sizeof(int64_t) * 4));
+}
+
+// grow item tables (device addresses change: cached graphs are dropped; the
+// old buffers stay allocated until the batch is freed, since queued work may
+// still read them)
+static void group_reserve(sem_batch *B, Group &g, int64_t nax, int64_t ngs, int64_t nvec)
+{
+    bool grown = false;
+    if (nax > g.cap_ax) {
+        const int64_t c = std::max<int64_t>({nax, 2 * g.cap_ax, 1024});
+        g.ax_items = (Item *)balloc(B, sizeof(Item) * c);
+        g.ax_partial = (double *)balloc(B, sizeof(double) * c);
+        g.cap_ax = c;
+        grown = true;
+    }
+    if (ngs > g.cap_gs) {
+        const int64_t c = std::max<int64_t>({ngs, 2 * g.cap_gs, 1024});
+        g.gs_items = (Item *)balloc(B, sizeof(Item) * c);
+        g.cap_gs = c;
+        grown = true;
+    }
+    if (nvec > g.cap_vec) {
+        const int64_t c = std::max<int64_t>({nvec, 2 * g.cap_vec, 1024});
+        g.vec_items = (Item *)balloc(B, sizeof(Item) * c);
+        g.vec_partial = (double *)balloc(B, sizeof(double) * 2 * c);
+        g.cap_vec = c;
+        grown = true;
+    }
+    if (grown && g.graph) {
+        hipGraphExecDestroy(g.graph);
+        g.graph = nullptr;
+    }
+}
+
+// rebuild a group's tables for the given slots and upload them on stream s
+static void group_build(sem_batch *B, Group &g, const std::vector<int> &ids, hipStream_t s)
+{
+    g.h_slots.assign(ids.begin(), ids.end());
+    g.h_ax.clear();
+    g.h_gs.clear();
+    g.h_vec.clear();
+    g.h_axf.assign(B->max_slots, 0);
+    g.h_axc.assign(B->max_slots, 0);
+    g.h_vf.assign(B->max_slots, 0);
+    g.h_vc.assign(B->max_slots, 0);
+    size_t lds = 0;
+    for (int id : ids) {
+        const SlotDesc &d = B->h_desc[id];
+        const int64_t nt = (d.E + d.epw - 1) / d.epw;
+        g.h_axf[id] = (int64_t)g.h_ax.size();
+        g.h_axc[id] = nt;
+        for (int64_t t = 0; t < nt; ++t) g.h_ax.push_back(Item{id, (int32_t)t});
+        const int64_t ng = (d.gs_n_ids + kGsChunk - 1) / kGsChunk;
+        for (int64_t t = 0; t < ng; ++t) g.h_gs.push_back(Item{id, (int32_t)t});
+        const int64_t nv = (d.nL + kVecChunk - 1) / kVecChunk;
+        g.h_vf[id] = (int64_t)g.h_vec.size();
+        g.h_vc[id] = nv;
+        for (int64_t t = 0; t < nv; ++t) g.h_vec.push_back(Item{id, (int32_t)t});
+        lds = std::max(lds, batch_ax_lds(d.N, d.epw, 0));
+    }
+    group_reserve(B, g, std::max<size_t>(g.h_ax.size(), 1), std::max<size_t>(g.h_gs.size(), 1),
+                  std::max<size_t>(g.h_vec.size(), 1));
+    g.lds = lds;
+    const int64_t counts[4] = {(int64_t)ids.size(), (int64_t)g.h_ax.size(), (int64_t)g.h_gs.size(),
+                               (int64_t)g.h_vec.size()};
+    SEM_HIP(hipMemcpyAsync(g.counts, counts, sizeof(counts), hipMemcpyHostToDevice, s));
+    if (!ids.empty()) SEM_HIP(hipMemcpyAsync(g.slots, g.h_slots.data(), sizeof(int32_t) * ids.size(), hipMemcpyHostToDevice, s));
+    if (!g.h_ax.empty()) SEM_HIP(hipMemcpyAsync(g.ax_items, g.h_ax.data(), sizeof(Item) * g.h_ax.size(), hipMemcpyHostToDevice, s));
+    if (!g.h_gs.empty()) SEM_HIP(hipMemcpyAsync(g.gs_items, g.h_gs.data(), sizeof(Item) * g.h_gs.size(), hipMemcpyHostToDevice, s));
+    if (!g.h_vec.empty()) SEM_HIP(hipMemcpyAsync(g.vec_items, g.h_vec.data(), sizeof(Item) * g.h_vec.size(), hipMemcpyHostToDevice, s));
+    SEM_HIP(hipMemcpyAsync(g.ax_first, g.h_axf.data(), sizeof(int64_t) * B->max_slots, hipMemcpyHostToDevice, s));
+    SEM_HIP(hipMemcpyAsync(g.ax_count, g.h_axc.data(), sizeof(int64_t) * B->max_slots, hipMemcpyHostToDevice, s));
+    SEM_HIP(hipMemcpyAsync(g.vec_first, g.h_vf.data(), sizeof(int64_t) * B->max_slots, hipMemcpyHostToDevice, s));
+    SEM_HIP(hipMemcpyAsync(g.vec_count, g.h_vc.data(), sizeof(int64_t) * B->max_slots, hipMemcpyHostToDevice, s));
+    // host staging vectors must outlive the async copies
+    SEM_HIP(hipStreamSynchronize(s));
+}
+
+static BatchLaunch launch_for(sem_batch *B, const Group &g)
+{
+    BatchLaunch L = B->L;
+    L.ax_lds = std::max<size_t>(g.lds, 16);
+    return L;
+}
+
+static void upload_desc(sem_batch *B, int id, hipStream_t s)
+{
+    SEM_HIP(hipMemcpyAsync(B->d_desc + id, &B->h_desc[id], sizeof(SlotDesc), hipMemcpyHostToDevice, s));
+}
+
+// one CG iteration of every slot in g, precision prec
+static void enqueue_batch_iters(sem_batch *B, Group &g, int prec, int k, hipStream_t s)
+{
+    const GroupDev gd = g.dev();
+    const BatchLaunch L = launch_for(B, g);
+    for (int it = 0; it < k; ++it) {
+        SEM_HIP(batch_ax(prec, 2, B->d_desc, gd, L, s));
+        SEM_HIP(batch_gs(prec, 1, B->d_desc, gd, L, s));
+        SEM_HIP(batch_reduce_sigma(prec, B->d_desc, gd, L, s));
+        SEM_HIP(batch_update(prec, B->d_desc, gd, L, s));
+        SEM_HIP(batch_reduce_rho(prec, B->d_desc, gd, L, s));
+    }
+}
+
+static void run_batch_iters(sem_batch *B, Group &g, int prec, int k, bool use_graph, hipStream_t s)
+{
+    if (g.h_slots.empty()) return;
+    if (!use_graph) {
+        enqueue_batch_iters(B, g, prec, k, s);
+        return;
+    }
+    if (!g.graph || g.graph_k != k || g.graph_lds < g.lds) {
+        if (g.graph) {
+            SEM_HIP(hipGraphExecDestroy(g.graph));
+            g.graph = nullptr;
+        }
+        if (!B->capture) SEM_HIP(hipStreamCreateWithFlags(&B->capture, hipStreamNonBlocking));
+        // capture with the largest LDS seen so far so that later members fit
+        hipGraph_t gr = nullptr;
+        SEM_HIP(hipStreamBeginCapture(B->capture, hipStreamCaptureModeThreadLocal));
+        try {
+            enqueue_batch_iters(B, g, prec, k, B->capture);
+        } catch (...) {
+            hipStreamEndCapture(B->capture, &gr);
+            if (gr) hipGraphDestroy(gr);
+            throw;
+        }
+        SEM_HIP(hipStreamEndCapture(B->capture, &gr));
+        hipGraphExec_t ex = nullptr;
+        const hipError_t e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+        hipGraphDestroy(gr);
+        SEM_HIP(e);
+        g.graph = ex;
+        g.graph_k = k;
+        g.graph_lds = g.lds;
+    }
+    SEM_HIP(hipGraphLaunch(g.graph, s));
+}
+
+static void read_states(sem_batch *B, hipStream_t s)
+{
+    B->h_state.resize(2 * B->max_slots);
+    SEM_HIP(hipMemcpyAsync(B->h_state.data(), B->d_state, sizeof(PcgState) * 2 * B->max_slots,
+                           hipMemcpyDeviceToHost, s));
+    SEM_HIP(hipStreamSynchronize(s));
+}
+
+static void read_scal(sem_batch *B, std::vector<double> &sc, hipStream_t s)
+{
+    sc.resize(2 * B->max_slots);
+    SEM_HIP(hipMemcpyAsync(sc.data(), B->d_scal, sizeof(double) * 2 * B->max_slots, hipMemcpyDeviceToHost, s));
+    SEM_HIP(hipStreamSynchronize(s));
+}
+
+// initialise CG (precision prec) for the given slots from their current r
+static void start_cg(sem_batch *B, const std::vector<int> &ids, int prec, hipStream_t s)
+{
+    if (ids.empty()) return;
+    Group &g = B->gres;
+    group_build(B, g, ids, s);
+    SEM_HIP(batch_cg_init(prec, B->d_desc, g.dev(), launch_for(B, g), s));
+}
+
+// FP64 residual of the given slots; copy_b ids start from x = 0
+static void residuals(sem_batch *B, const std::vector<int> &ids, bool copy_b, hipStream_t s)
+{
+    if (ids.empty()) return;
+    Group &g = B->gres;
+    group_build(B, g, ids, s);
+    const GroupDev gd = g.dev();
+    const BatchLaunch L = launch_for(B, g);
+    if (!copy_b) {
+        SEM_HIP(batch_ax(0, 0, B->d_desc, gd, L, s));
+        SEM_HIP(batch_gs(0, 0, B->d_desc, gd, L, s));
+    }
+    SEM_HIP(batch_residual(copy_b ? 1 : 0, B->d_desc, gd, L, s));
+}
+
+static void finish_slot(sem_batch *B, int id, sem_status st)
+{
+    HostSlot &h = B->slots[id];
+    h.phase = PH_DONE;
+    h.status = st;
+    h.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - h.t0).count();
+}
+
+// Advance every active slot: serve pending residuals / transitions, then
+// replay k CG iterations per precision, then read the states.
+static void step_batch(sem_batch *B, int k, bool use_graph, hipStream_t s)
+{
+    const int ms = B->max_slots;
+    // 1. residual-phase slots
+    std::vector<int> fresh, resid;
+    for (int id = 0; id < ms; ++id) {
+        const HostSlot &h = B->slots[id];
+        if (h.phase == PH_START && !h.opts.x0_given && h.opts.precision == SEM_PREC_FP64) fresh.push_back(id);
+        else if (h.phase == PH_START || h.phase == PH_CHECK || h.phase == PH_RESID) resid.push_back(id);
+    }
+    std::vector<double> sc;
+    std::vector<int> to64, to32;
+    if (!fresh.empty()) {
+        residuals(B, fresh, true, s);
+        read_scal(B, sc, s);
+        for (int id : fresh) {
+            HostSlot &h = B->slots[id];
+            h.bb = sc[2 * id];
+            if (h.bb == 0.0) {
+                h.rel = 0.0;
+                finish_slot(B, id, SEM_OK);
+                continue;
+            }
+            to64.push_back(id);
+        }
+    }
+    if (!resid.empty()) {
+        residuals(B, resid, false, s);
+        read_scal(B, sc, s);
+        for (int id : resid) {
+            HostSlot &h = B->slots[id];
+            if (h.bb < 0.0) h.bb = sc[2 * id];
+            const double rr = sc[2 * id + 1];
+            h.rel = h.bb > 0.0 ? std::sqrt(rr / h.bb) : 0.0;
+            if (h.bb == 0.0 || h.rel <= h.opts.tol) {
+                finish_slot(B, id, SEM_OK);
+                continue;
+            }
+            if (h.opts.precision == SEM_PREC_FP64) {
+                if (h.phase == PH_CHECK) {
+                    if (h.iters >= h.opts.max_iter || h.restarts == 3) {
+                        set_error("batched solve: no convergence within max_iter");
+                        finish_slot(B, id, SEM_ENOCONV);
+                        continue;
+                    }
+                    h.restarts++;
+                }
+                to64.push_back(id);
+            } else {
+                if (h.iters >= h.opts.max_iter || h.outer >= 100) {
+                    set_error("batched mixed solve: no convergence within max_iter");
+                    finish_slot(B, id, SEM_ENOCONV);
+                    continue;
+                }
+                to32.push_back(id);
+            }
+        }
+    }
+    // 2. entering CG
+    for (int id : to64) {
+        HostSlot &h = B->slots[id];
+        SlotDesc &d = B->h_desc[id];
+        d.stop2[0] = h.opts.tol * h.opts.tol * h.bb;
+        d.limit[0] = h.opts.max_iter - h.iters;
+        upload_desc(B, id, s);
+        h.phase = PH_CG64;
+    }
+    start_cg(B, to64, 0, s);
+    if (!to32.empty()) {
+        for (int id : to32) {
+            HostSlot &h = B->slots[id];
+            SlotDesc &d = B->h_desc[id];
+            d.stop2[1] = h.opts.inner_tol * h.opts.inner_tol;
+            const int inner_max = h.opts.inner_max_iter > 0 ? h.opts.inner_max_iter : h.opts.max_iter;
+            d.limit[1] = std::min(inner_max, h.opts.max_iter - h.iters);
+            upload_desc(B, id, s);
+            h.phase = PH_CG32;
+        }
+        Group &g = B->gres;
+        group_build(B, g, to32, s);
+        SEM_HIP(batch_to_fp32(B->d_desc, g.dev(), launch_for(B, g), s));
+        SEM_HIP(batch_cg_init(1, B->d_desc, g.dev(), launch_for(B, g), s));
+    }
+    // 3. CG iterations
+    std::vector<int> cg64, cg32;
+    for (int id = 0; id < ms; ++id) {
+        if (B->slots[id].phase == PH_CG64) cg64.push_back(id);
+        if (B->slots[id].phase == PH_CG32) cg32.push_back(id);
+    }
+    if (cg64 != B->g64.h_slots) group_build(B, B->g64, cg64, s);
+    if (cg32 != B->g32.h_slots) group_build(B, B->g32, cg32, s);
+    if (!cg64.empty()) run_batch_iters(B, B->g64, 0, k, use_graph, s);
+    if (!cg32.empty()) run_batch_iters(B, B->g32, 1, k, use_graph, s);
+    if (cg64.empty() && cg32.empty()) return;
+    read_states(B, s);
+    // 4. transitions out of CG
+    std::vector<int> axpy;
+    for (int id : cg64) {
+        HostSlot &h = B->slots[id];
+        const PcgState &st = B->h_state[2 * id];
+        if (!st.done) continue;
+        h.iters += st.iters;
+        if (st.done == 2) {
+            set_error("batched solve: CG breakdown");
+            finish_slot(B, id, SEM_EBREAKDOWN);
+            continue;
+        }
+        h.phase = PH_CHECK;
+    }
+    for (int id : cg32) {
+        HostSlot &h = B->slots[id];
+        const PcgState &st = B->h_state[2 * id + 1];
+        if (!st.done) continue;
+        h.iters += st.iters;
+        h.outer++;
+        if (st.done == 2 && st.iters == 0) {
+            set_error("batched mixed solve: FP32 inner CG broke down at its first step");
+            finish_slot(B, id, SEM_EBREAKDOWN);
+            continue;
+        }
+        axpy.push_back(id);
+        h.phase = PH_RESID;
+    }
+    if (!axpy.empty()) {
+        Group &g = B->gres;
+        group_build(B, g, axpy, s);
+        SEM_HIP(batch_axpy(B->d_desc, g.dev(), launch_for(B, g), s));
+    }
+}
+
+static int free_slot_index(sem_batch *B)
+{
+    for (int id = 0; id < B->max_slots; ++id)
+        if (B->slots[id].phase == PH_FREE) return id;
+    return -1;
+}
+
+static size_t slot_bytes(const sem_mesh *m, int precision)
+{
+    const size_t nL = (size_t)m->h.nL;
+    size_t b = 3 * nL * 8;                                   // r, p, w FP64
+    if (precision == SEM_PREC_MIXED) b += 4 * nL * 4;        // x, r, p, w FP32
+    return (b + 255) / 256 * 256 + 256;
+}
+
+static int admit_slot(sem_batch *B, sem_mesh *m, const double *b, double *x, const sem_solve_opts &o, hipStream_t s)
+{
+    if (!batch_order_supported(m->h.N)) fail(SEM_EUNSUPPORTED, "batched solves support orders 2..10");
+    if (m->device != B->device) fail(SEM_EINVAL, "mesh is on another device");
+    if (o.precision == SEM_PREC_MIXED && !m->with_fp32) fail(SEM_EINVAL, "mixed precision needs SEM_WITH_FP32");
+    const int id = free_slot_index(B);
+    if (id < 0) fail(SEM_EBUDGET, "no free slot");
+    const size_t need = slot_bytes(m, o.precision);
+    void *buf = nullptr;
+    auto itb = B->free_bufs.lower_bound(need);
+    if (itb != B->free_bufs.end() && itb->first <= 2 * need) {
+        buf = itb->second;
+        const size_t have = itb->first;
+        B->free_bufs.erase(itb);
+        B->slots[id].buf_bytes = have;
+    } else {
+        if (B->budget && B->used + need > B->budget) {
+            // drop cached free buffers before refusing
+            for (auto &fb : B->free_bufs) {
+                hipFree(fb.second);
+                B->allocations.erase(std::find(B->allocations.begin(), B->allocations.end(), fb.second));
+                B->used -= fb.first;
+            }
+            B->free_bufs.clear();
+            if (B->used + need > B->budget) fail(SEM_EBUDGET, "slot vectors exceed the batch budget");
+        }
+        buf = balloc(B, need);
+        B->used += need;
+        B->slots[id].buf_bytes = need;
+    }
+    HostSlot &h = B->slots[id];
+    h.mesh = m;
+    h.opts = o;
+    h.b = b;
+    h.x = x;
+    h.iters = h.outer = h.restarts = 0;
+    h.bb = -1.0;
+    h.rel = 0.0;
+    h.status = SEM_OK;
+    h.buf = buf;
+    h.t0 = std::chrono::steady_clock::now();
+    h.phase = PH_START;
+    if (o.precision == SEM_PREC_MIXED) h.phase = PH_RESID;
+    SlotDesc &d = B->h_desc[id];
+    std::memset(&d, 0, sizeof(d));
+    const HostMesh &hm = m->h;
+    d.N = hm.N;
+    d.epw = B->epw[hm.N] > 0 ? B->epw[hm.N] : default_batch_epw(hm.N);
+    d.E = hm.E;
+    d.nL = hm.nL;
+    d.G[0] = m->G64;
+    d.G[1] = m->G32;
+    d.inv[0] = m->inv64;
+    d.inv[1] = m->inv32;
+    d.mult = m->mult;
+    d.gs_off = m->gs_off;
+    d.gs_idx = m->gs_idx;
+    d.gs_n_sum = hm.gs_n_sum;
+    d.gs_n_ids = hm.gs_n_ids;
+    d.b = b;
+    d.x64 = x;
+    char *p = static_cast<char *>(buf);
+    const size_t v64 = (size_t)hm.nL * 8, v32 = (size_t)hm.nL * 4;
+    auto take = [&](size_t bytes) {
+        void *q = p;
+        p += (bytes + 255) / 256 * 256;
+        return q;
+    };
+    d.x[0] = x;
+    d.r[0] = take(v64);
+    d.p[0] = take(v64);
+    d.w[0] = take(v64);
+    if (o.precision == SEM_PREC_MIXED) {
+        d.x[1] = take(v32);
+        d.r[1] = take(v32);
+        d.p[1] = take(v32);
+        d.w[1] = take(v32);
+    }
+    d.st = B->d_state + 2 * id;
+    d.scal = B->d_scal + 2 * id;
+    SEM_HIP(hipMemsetAsync(d.st, 0, 2 * sizeof(PcgState), s));
+    upload_desc(B, id, s);
+    return id;
+}
+
+static void retire_slot(sem_batch *B, int id)
+{
+    HostSlot &h = B->slots[id];
+    if (h.buf) B->free_bufs.emplace(h.buf_bytes, h.buf);
+    h = HostSlot();
+}
+
+}  // namespace sem
+
+using namespace sem;
+
+extern "C" {
+
+sem_status sem_batch_create(int max_slots, size_t device_budget, void *stream, sem_batch **out)
+{
+    return bguard([&]() -> sem_status {
+        if (!out || max_slots < 1 || max_slots > 65536) fail(SEM_EINVAL, "sem_batch_create: bad arguments");
+        *out = nullptr;
+        hipStream_t s = (hipStream_t)stream;
+        ensure_dtables_all(s);
+        sem_batch *B = new sem_batch();
+        try {
+            B->max_slots = max_slots;
+            B->budget = device_budget;
+            SEM_HIP(hipGetDevice(&B->device));
+            B->slots.assign(max_slots, HostSlot());
+            B->h_desc.assign(max_slots, SlotDesc());
+            B->d_desc = (SlotDesc *)balloc(B, sizeof(SlotDesc) * max_slots);
+            B->d_state = (PcgState *)balloc(B, sizeof(PcgState) * 2 * max_slots);
+            B->d_scal = (double *)balloc(B, sizeof(double) * 2 * max_slots);
+            SEM_HIP(hipMemsetAsync(B->d_state, 0, sizeof(PcgState) * 2 * max_slots, s));
+            group_alloc(B, B->g64);
+            group_alloc(B, B->g32);
+            group_alloc(B, B->gres);
+            const int cap = persistent_grid_cap_public();
+            B->L.ax_grid = cap / 4;
+            B->L.vec_grid = cap;
+            B->L.max_slots = max_slots;
+            B->L.ax_lds = 16;
+            SEM_HIP(hipStreamSynchronize(s));
+        } catch (...) {
+            sem_batch_free(B);
+            throw;
+        }
+        *out = B;
+        return SEM_OK;
+    });
+}
+
+sem_status sem_batch_free(sem_batch *B)
+{
+    if (!B) return SEM_OK;
+    for (Group *g : {&B->g64, &B->g32, &B->gres})
+        if (g->graph) hipGraphExecDestroy(g->graph);
+    if (B->capture) hipStreamDestroy(B->capture);
+    for (void *p : B->allocations) hipFree(p);
+    delete B;
+    return SEM_OK;
+}
+
+sem_status sem_batch_admit(sem_batch *B, sem_mesh *mesh, const double *b, double *x, const sem_solve_opts *opts,
+                           int *slot, void *stream)
+{
+    return bguard([&]() -> sem_status {
+        if (!B || !mesh || !b || !x || !slot) fail(SEM_EINVAL, "sem_batch_admit: null argument");
+        sem_solve_opts o;
+        sem_solve_opts_default(&o);
+        if (opts) o = *opts;
+        if (!(o.tol > 0.0)) fail(SEM_EINVAL, "sem_batch_admit: tol must be positive");
+        if (o.precision != SEM_PREC_FP64 && o.precision != SEM_PREC_MIXED) fail(SEM_EINVAL, "unknown precision");
+        *slot = admit_slot(B, mesh, b, x, o, (hipStream_t)stream);
+        return SEM_OK;
+    });
+}
+
+sem_status sem_batch_step(sem_batch *B, int iterations, int use_graph, void *stream, int *n_active)
+{
+    return bguard([&]() -> sem_status {
+        if (!B || iterations < 1) fail(SEM_EINVAL, "sem_batch_step: bad arguments");
+        step_batch(B, iterations, use_graph != 0, (hipStream_t)stream);
+        if (n_active) {
+            int n = 0;
+            for (const auto &h : B->slots)
+                if (h.phase != PH_FREE && h.phase != PH_DONE) n++;
+            *n_active = n;
+        }
+        return SEM_OK;
+    });
+}
+
+sem_status sem_batch_finished(const sem_batch *B, int *slots, int capacity, int *n)
+{
+    return bguard([&]() -> sem_status {
+        if (!B || !n) fail(SEM_EINVAL, "sem_batch_finished: null argument");
+        int c = 0;
+        for (int id = 0; id < B->max_slots; ++id)
+            if (B->slots[id].phase == PH_DONE) {
+                if (slots && c < capacity) slots[c] = id;
+                c++;
+            }
+        *n = c;
+        return SEM_OK;
+    });
+}
+
+sem_status sem_batch_retire(sem_batch *B, int slot, sem_solve_stats *stats)
+{
+    return bguard([&]() -> sem_status {
+        if (!B || slot < 0 || slot >= B->max_slots) fail(SEM_EINVAL, "sem_batch_retire: bad slot");
+        HostSlot &h = B->slots[slot];
+        if (h.phase == PH_FREE) fail(SEM_EINVAL, "sem_batch_retire: slot is free");
+        if (stats) {
+            std::memset(stats, 0, sizeof(*stats));
+            stats->status = h.phase == PH_DONE ? h.status : SEM_ENOCONV;
+            stats->iterations = h.iters;
+            stats->outer_iterations = h.opts.precision == SEM_PREC_MIXED ? h.outer : h.restarts + 1;
+            stats->rel_residual = h.rel;
+            stats->bnorm = h.bb > 0 ? std::sqrt(h.bb) : 0.0;
+            stats->seconds = h.seconds;
+        }
+        retire_slot(B, slot);
+        return SEM_OK;
+    });
+}
+
+sem_status sem_batch_solve(sem_batch *B, sem_mesh *const *meshes, int n, const double *const *b, double *const *x,
+                           const sem_solve_opts *opts, sem_solve_stats *stats, void *stream)
+{
+    return bguard([&]() -> sem_status {
+        if (!B || !meshes || !b || !x || n < 0) fail(SEM_EINVAL, "sem_batch_solve: null argument");
+        if (n > B->max_slots) fail(SEM_EBUDGET, "sem_batch_solve: more systems than slots");
+        hipStream_t s = (hipStream_t)stream;
+        sem_solve_opts o;
+        sem_solve_opts_default(&o);
+        if (opts) o = *opts;
+        std::vector<int> ids(n);
+        for (int i = 0; i < n; ++i) {
+            sem_status st = sem_batch_admit(B, meshes[i], b[i], x[i], &o, &ids[i], stream);
+            if (st != SEM_OK) {
+                for (int q = 0; q < i; ++q) retire_slot(B, ids[q]);
+                return st;
+            }
+        }
+        const int k = std::max(1, o.poll_every);
+        for (;;) {
+            step_batch(B, k, o.use_graph != 0, s);
+            bool all = true;
+            for (int id : ids)
+                if (B->slots[id].phase != PH_DONE) all = false;
+            if (all) break;
+        }
+        SEM_HIP(hipStreamSynchronize(s));
+        sem_status worst = SEM_OK;
+        for (int i = 0; i < n; ++i) {
+            sem_solve_stats st{};
+            sem_batch_retire(B, ids[i], &st);
+            if (stats) stats[i] = st;
+            if (st.status != SEM_OK && worst == SEM_OK) worst = st.status;
+        }
+        return worst;
+    });
+}
+
+sem_status sem_batch_tune(sem_batch *B, sem_mesh *const *meshes, int n, void *stream)
+{
+    return bguard([&]() -> sem_status {
+        if (!B || (!meshes && n > 0) || n < 0) fail(SEM_EINVAL, "sem_batch_tune: bad arguments");
+        hipStream_t s = (hipStream_t)stream;
+        for (int id = 0; id < B->max_slots; ++id)
+            if (B->slots[id].phase != PH_FREE) fail(SEM_EINVAL, "sem_batch_tune: the batch must be empty");
+        if (n > B->max_slots) n = B->max_slots;
+        // scratch right-hand sides and solutions (zeros) for the timing slots
+        size_t maxnl = 0;
+        for (int i = 0; i < n; ++i) maxnl = std::max<size_t>(maxnl, (size_t)meshes[i]->h.nL);
+        double *zb = nullptr, *zx = nullptr;
+        SEM_HIP(hipMalloc(&zb, std::max<size_t>(maxnl, 1) * 8));
+        SEM_HIP(hipMalloc(&zx, std::max<size_t>(maxnl, 1) * 8));
+        SEM_HIP(hipMemsetAsync(zb, 0, maxnl * 8, s));
+        SEM_HIP(hipMemsetAsync(zx, 0, maxnl * 8, s));
+        hipEvent_t e0, e1;
+        SEM_HIP(hipEventCreate(&e0));
+        SEM_HIP(hipEventCreate(&e1));
+        sem_solve_opts o;
+        sem_solve_opts_default(&o);
+        std::vector<int> ids;
+        auto cleanup = [&]() {
+            for (int id : ids) retire_slot(B, id);
+            ids.clear();
+            hipEventDestroy(e0);
+            hipEventDestroy(e1);
+            hipFree(zb);
+            hipFree(zx);
+        };
+        try {
+            auto time_group = [&](const std::vector<int> &grp) {
+                Group &g = B->gres;
+                group_build(B, g, grp, s);
+                const GroupDev gd = g.dev();
+                const BatchLaunch Lc = launch_for(B, g);
+                SEM_HIP(batch_ax(0, 0, B->d_desc, gd, Lc, s));
+                SEM_HIP(hipEventRecord(e0, s));
+                for (int r = 0; r < 3; ++r) SEM_HIP(batch_ax(0, 0, B->d_desc, gd, Lc, s));
+                SEM_HIP(hipEventRecord(e1, s));
+                SEM_HIP(hipEventSynchronize(e1));
+                float ms = 0;
+                SEM_HIP(hipEventElapsedTime(&ms, e0, e1));
+                return (double)ms;
+            };
+            for (int i = 0; i < n; ++i) ids.push_back(admit_slot(B, meshes[i], zb, zx, o, s));
+            // elements per tile, one order at a time
+            for (int N = 1; N <= SEM_MAX_ORDER; ++N) {
+                std::vector<int> grp;
+                for (int id : ids)
+                    if (B->h_desc[id].N == N) grp.push_back(id);
+                if (grp.empty()) continue;
+                const int P2 = (N + 1) * (N + 1), emax = kBatchBlock / P2;
+                double best = 1e300;
+                int best_e = default_batch_epw(N);
+                for (int e = 1; e <= emax; ++e) {
+                    if (emax > 8 && e != 1 && e != emax && (e & (e - 1)) != 0) continue;
+                    for (int id : grp) {
+                        B->h_desc[id].epw = e;
+                        upload_desc(B, id, s);
+                    }
+                    const double t = time_group(grp);
+                    if (t < best * 0.995) {
+                        best = t;
+                        best_e = e;
+                    }
+                }
+                B->epw[N] = best_e;
+                for (int id : grp) {
+                    B->h_desc[id].epw = best_e;
+                    upload_desc(B, id, s);
+                }
+            }
+            // persistent grid of the operator over the whole set
+            const int cap = persistent_grid_cap_public();
+            double best = 1e300;
+            int best_g = B->L.ax_grid;
+            for (int gsz : {cap / 8, cap / 4, cap / 2, cap}) {
+                B->L.ax_grid = std::max(64, gsz);
+                const double t = time_group(ids);
+                if (t < best * 0.995) {
+                    best = t;
+                    best_g = B->L.ax_grid;
+                }
+            }
+            B->L.ax_grid = best_g;
+            for (Group *g : {&B->g64, &B->g32})
+                if (g->graph) {
+                    hipGraphExecDestroy(g->graph);
+                    g->graph = nullptr;
+                }
+        } catch (...) {
+            cleanup();
+            throw;
+        }
+        cleanup();
+        SEM_HIP(hipStreamSynchronize(s));
+        return SEM_OK;
+    });
+}
+
+sem_status sem_batch_set_epw(sem_batch *B, int N, int epw)
+{
+    return bguard([&]() -> sem_status {
+        if (!B || N < 1 || N > SEM_MAX_ORDER) fail(SEM_EINVAL, "sem_batch_set_epw: bad order");
+        const int P2 = (N + 1) * (N + 1);
+        if (epw < 0 || epw * P2 > kBatchBlock) fail(SEM_EINVAL, "sem_batch_set_epw: epw out of range");
+        B->epw[N] = epw;
+        return SEM_OK;
+    });
+}
+
+sem_status sem_batch_get_epw(const sem_batch *B, int N, int *epw)
+{
+    return bguard([&]() -> sem_status {
+        if (!B || !epw || N < 1 || N > SEM_MAX_ORDER) fail(SEM_EINVAL, "sem_batch_get_epw: bad arguments");
+        *epw = B->epw[N] > 0 ? B->epw[N] : default_batch_epw(N);
+        return SEM_OK;
+    });
+}
+
+}  // extern "C"

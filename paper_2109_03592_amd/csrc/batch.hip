@@ -1,0 +1,475 @@
+// batch.hip -- persistent batched kernels: every CG phase of many solves of
+// different orders and sizes in one launch (the paper's remedy for small
+// kernels called in loops is to move the loop inside the kernel, section 3).
+// Each workgroup walks the group's work table; the slot descriptor and the
+// item are uniform per workgroup and come through scalar loads.
+#include "batch.hpp"
+#include "operator.hpp"
+
+namespace sem {
+
+// read-only views through the constant address space (scalar loads for
+// uniform addresses); the host compilation pass only needs the types
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename X>
+using cptr = const __attribute__((address_space(4))) X *;
+#else
+template <typename X>
+using cptr = const X *;
+#endif
+
+// orders compiled into the batched operator
+#define SEM_BATCH_ORDERS(X) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10)
+
+bool batch_order_supported(int N)
+{
+    switch (N) {
+#define SEM_BO(n) case n:
+        SEM_BATCH_ORDERS(SEM_BO)
+#undef SEM_BO
+        return true;
+    default:
+        return false;
+    }
+}
+
+size_t batch_ax_lds(int N, int epw, int prec)
+{
+    const size_t P3 = (size_t)(N + 1) * (N + 1) * (N + 1);
+    return (size_t)epw * 3 * P3 * (prec == 0 ? 8 : 4);
+}
+
+__device__ inline int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+template <typename T>
+__device__ inline int prec_of() { return sizeof(T) == 8 ? 0 : 1; }
+
+// operator on one tile of one slot (orders dispatched at run time)
+template <typename T, int N, int MODE>
+__device__ inline void slot_tile(const SlotDesc &sd, int64_t tile, T *sm, double &dot, T beta)
+{
+    constexpr int P = N + 1, P2 = P * P, P3 = P2 * P;
+    const int prec = prec_of<T>();
+    const int tid = threadIdx.x;
+    const int el = tid / P2;
+    const int ij = tid - el * P2;
+    const int i = ij % P, j = ij / P;
+    const bool inblk = el < sd.epw;
+    const int lslot = inblk ? el : sd.epw - 1;
+    T *su = sm + (size_t)lslot * 3 * P3;
+    const T *__restrict__ D = dtable<T>(N);
+    LaneRows<T, N> R;
+    R.load(D, i, j);
+    const int64_t e = tile * sd.epw + el;
+    const bool active = inblk && e < sd.E;
+    const T *G = static_cast<const T *>(sd.G[prec]);
+    if (MODE == 0) {
+        // FP64 residual operator: w = A x
+        ax_tile<T, N, 0>(R, D, su, e, active, inblk, i, j, G, reinterpret_cast<const T *>(sd.x64),
+                         reinterpret_cast<T *>(sd.w[0]), nullptr, nullptr, beta, dot);
+    } else {
+        ax_tile<T, N, 2>(R, D, su, e, active, inblk, i, j, G, static_cast<const T *>(sd.r[prec]),
+                         static_cast<T *>(sd.w[prec]), static_cast<const T *>(sd.inv[prec]),
+                         static_cast<T *>(sd.p[prec]), beta, dot);
+    }
+}
+
+// MODE 0: w[0] = A x64 (FP64).  MODE 2: CG operator with the p update and
+// per-item p.Ap partials.
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBatchBlock) void batch_ax_kernel(const SlotDesc *slots_, GroupDev g)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *sm = reinterpret_cast<T *>(smem_raw);
+    cptr<SlotDesc> slots = (cptr<SlotDesc>)slots_;
+    cptr<Item> items = (cptr<Item>)g.ax_items;
+    const int64_t n = ((cptr<int64_t>)g.counts)[1];
+    const int prec = prec_of<T>();
+    for (int64_t it = blockIdx.x; it < n; it += gridDim.x) {
+        const Item item = items[it];
+        const SlotDesc sd = slots[item.slot];
+        double dot = 0.0;
+        T beta = 0;
+        bool skip = false;
+        if (MODE == 2) {
+            skip = uniform_int(sd.st[prec].done) != 0;
+            beta = (T)sd.st[prec].beta;
+        }
+        if (!skip) {
+            switch (sd.N) {
+#define SEM_BCASE(n) \
+    case n: slot_tile<T, n, MODE>(sd, item.local, sm, dot, beta); break;
+                SEM_BATCH_ORDERS(SEM_BCASE)
+#undef SEM_BCASE
+            default: break;
+            }
+        }
+        if (MODE == 2) {
+            double v[1] = {dot};
+            block_reduce_store<1>(v, g.ax_partial + it, 0);
+            __syncthreads();
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBatchBlock) void batch_gs_kernel(const SlotDesc *slots_, GroupDev g, int check_done,
+                                                               int which)
+{
+    cptr<SlotDesc> slots = (cptr<SlotDesc>)slots_;
+    cptr<Item> items = (cptr<Item>)g.gs_items;
+    const int64_t n = ((cptr<int64_t>)g.counts)[2];
+    const int prec = prec_of<T>();
+    for (int64_t it = blockIdx.x; it < n; it += gridDim.x) {
+        const Item item = items[it];
+        const SlotDesc sd = slots[item.slot];
+        if (check_done && uniform_int(sd.st[prec].done)) continue;
+        T *v = static_cast<T *>(which == 0 ? sd.w[prec] : sd.w[0]);
+        const int64_t t = (int64_t)item.local * kGsChunk + threadIdx.x;
+        if (t >= sd.gs_n_ids) continue;
+        const int32_t q0 = sd.gs_off[t], q1 = sd.gs_off[t + 1];
+        if (t < sd.gs_n_sum) {
+            T s = T(0);
+            for (int32_t q = q0; q < q1; ++q) s += v[sd.gs_idx[q]];
+            for (int32_t q = q0; q < q1; ++q) v[sd.gs_idx[q]] = s;
+        } else {
+            for (int32_t q = q0; q < q1; ++q) v[sd.gs_idx[q]] = T(0);
+        }
+    }
+}
+
+__device__ inline double inv_mult_b(uint8_t m) { return 1.0 / (double)m; }
+
+// x += alpha p, r -= alpha w; per-item partials of <r,r>, <r, invdiag r>
+template <typename T>
+__global__ __launch_bounds__(kBatchBlock) void batch_update_kernel(const SlotDesc *slots_, GroupDev g)
+{
+    cptr<SlotDesc> slots = (cptr<SlotDesc>)slots_;
+    cptr<Item> items = (cptr<Item>)g.vec_items;
+    const int64_t n = ((cptr<int64_t>)g.counts)[3];
+    const int prec = prec_of<T>();
+    for (int64_t it = blockIdx.x; it < n; it += gridDim.x) {
+        const Item item = items[it];
+        const SlotDesc sd = slots[item.slot];
+        double rr = 0.0, rz = 0.0;
+        if (!uniform_int(sd.st[prec].done)) {
+            const T alpha = (T)sd.st[prec].alpha;
+            T *x = static_cast<T *>(sd.x[prec]);
+            T *r = static_cast<T *>(sd.r[prec]);
+            const T *p = static_cast<const T *>(sd.p[prec]);
+            const T *w = static_cast<const T *>(sd.w[prec]);
+            const T *iv = static_cast<const T *>(sd.inv[prec]);
+            const int64_t q0 = (int64_t)item.local * kVecChunk;
+            for (int u = 0; u < kVecChunk / kBatchBlock; ++u) {
+                const int64_t q = q0 + u * kBatchBlock + threadIdx.x;
+                if (q >= sd.nL) break;
+                x[q] = x[q] + alpha * p[q];
+                const T rq = r[q] - alpha * w[q];
+                r[q] = rq;
+                const double rd = (double)rq, im = inv_mult_b(sd.mult[q]);
+                rr += rd * rd * im;
+                rz += rd * (double)(iv[q] * rq) * im;
+            }
+        }
+        double v[2] = {rr, rz};
+        block_reduce_store<2>(v, g.vec_partial + 2 * it, 0);
+        __syncthreads();
+    }
+}
+
+// CG start from r: p = 0, partials of <r,r>, <r, invdiag r>
+template <typename T>
+__global__ __launch_bounds__(kBatchBlock) void batch_init_kernel(const SlotDesc *slots_, GroupDev g)
+{
+    cptr<SlotDesc> slots = (cptr<SlotDesc>)slots_;
+    cptr<Item> items = (cptr<Item>)g.vec_items;
+    const int64_t n = ((cptr<int64_t>)g.counts)[3];
+    const int prec = prec_of<T>();
+    for (int64_t it = blockIdx.x; it < n; it += gridDim.x) {
+        const Item item = items[it];
+        const SlotDesc sd = slots[item.slot];
+        const T *r = static_cast<const T *>(sd.r[prec]);
+        T *p = static_cast<T *>(sd.p[prec]);
+        const T *iv = static_cast<const T *>(sd.inv[prec]);
+        double rr = 0.0, rz = 0.0;
+        const int64_t q0 = (int64_t)item.local * kVecChunk;
+        for (int u = 0; u < kVecChunk / kBatchBlock; ++u) {
+            const int64_t q = q0 + u * kBatchBlock + threadIdx.x;
+            if (q >= sd.nL) break;
+            p[q] = T(0);
+            const double rd = (double)r[q], im = inv_mult_b(sd.mult[q]);
+            rr += rd * rd * im;
+            rz += rd * (double)(iv[q] * r[q]) * im;
+        }
+        double v[2] = {rr, rz};
+        block_reduce_store<2>(v, g.vec_partial + 2 * it, 0);
+        __syncthreads();
+    }
+}
+
+// FP64 residual: r = b - w (copy_b: r = b, x = 0); partials of <r,r> (slot 0)
+__global__ __launch_bounds__(kBatchBlock) void batch_residual_kernel(const SlotDesc *slots_, GroupDev g, int copy_b)
+{
+    cptr<SlotDesc> slots = (cptr<SlotDesc>)slots_;
+    cptr<Item> items = (cptr<Item>)g.vec_items;
+    const int64_t n = ((cptr<int64_t>)g.counts)[3];
+    for (int64_t it = blockIdx.x; it < n; it += gridDim.x) {
+        const Item item = items[it];
+        const SlotDesc sd = slots[item.slot];
+        double *r = static_cast<double *>(sd.r[0]);
+        const double *w = static_cast<const double *>(sd.w[0]);
+        double rr = 0.0, bb = 0.0;
+        const int64_t q0 = (int64_t)item.local * kVecChunk;
+        for (int u = 0; u < kVecChunk / kBatchBlock; ++u) {
+            const int64_t q = q0 + u * kBatchBlock + threadIdx.x;
+            if (q >= sd.nL) break;
+            const double bq = sd.b[q];
+            double rq;
+            if (copy_b) {
+                rq = bq;
+                sd.x64[q] = 0.0;
+            } else {
+                rq = bq - w[q];
+            }
+            r[q] = rq;
+            const double im = inv_mult_b(sd.mult[q]);
+            rr += rq * rq * im;
+            bb += bq * bq * im;
+        }
+        double v[2] = {rr, bb};
+        block_reduce_store<2>(v, g.vec_partial + 2 * it, 0);
+        __syncthreads();
+    }
+}
+
+// mixed: r32 = r64 / ||r||, x32 = 0
+__global__ __launch_bounds__(kBatchBlock) void batch_to_fp32_kernel(const SlotDesc *slots_, GroupDev g)
+{
+    cptr<SlotDesc> slots = (cptr<SlotDesc>)slots_;
+    cptr<Item> items = (cptr<Item>)g.vec_items;
+    const int64_t n = ((cptr<int64_t>)g.counts)[3];
+    for (int64_t it = blockIdx.x; it < n; it += gridDim.x) {
+        const Item item = items[it];
+        const SlotDesc sd = slots[item.slot];
+        const double s = 1.0 / sqrt(sd.scal[1]);
+        const double *r = static_cast<const double *>(sd.r[0]);
+        float *r32 = static_cast<float *>(sd.r[1]);
+        float *x32 = static_cast<float *>(sd.x[1]);
+        const int64_t q0 = (int64_t)item.local * kVecChunk;
+        for (int u = 0; u < kVecChunk / kBatchBlock; ++u) {
+            const int64_t q = q0 + u * kBatchBlock + threadIdx.x;
+            if (q >= sd.nL) break;
+            r32[q] = (float)(r[q] * s);
+            x32[q] = 0.0f;
+        }
+    }
+}
+
+// mixed: x64 += ||r|| x32
+__global__ __launch_bounds__(kBatchBlock) void batch_axpy_kernel(const SlotDesc *slots_, GroupDev g)
+{
+    cptr<SlotDesc> slots = (cptr<SlotDesc>)slots_;
+    cptr<Item> items = (cptr<Item>)g.vec_items;
+    const int64_t n = ((cptr<int64_t>)g.counts)[3];
+    for (int64_t it = blockIdx.x; it < n; it += gridDim.x) {
+        const Item item = items[it];
+        const SlotDesc sd = slots[item.slot];
+        const double s = sqrt(sd.scal[1]);
+        const float *x32 = static_cast<const float *>(sd.x[1]);
+        const int64_t q0 = (int64_t)item.local * kVecChunk;
+        for (int u = 0; u < kVecChunk / kBatchBlock; ++u) {
+            const int64_t q = q0 + u * kBatchBlock + threadIdx.x;
+            if (q >= sd.nL) break;
+            sd.x64[q] += s * (double)x32[q];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// per-slot reductions: workgroup b takes the group's b-th slot and sums that
+// slot's item partials in item order (fixed order, independent of the rest)
+template <int NV>
+__device__ inline void slot_sum(const double *__restrict__ part, int64_t first, int64_t count, double (&out)[NV])
+{
+    __shared__ double red[NV][kBatchBlock];
+    double s[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) s[q] = 0.0;
+    for (int64_t b = threadIdx.x; b < count; b += blockDim.x)
+#pragma unroll
+        for (int q = 0; q < NV; ++q) s[q] += part[(first + b) * NV + q];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) red[q][threadIdx.x] = s[q];
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+#pragma unroll
+            for (int q = 0; q < NV; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + h];
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < NV; ++q) out[q] = red[q][0];
+}
+
+__device__ inline int group_slot(const GroupDev &g)
+{
+    const int64_t ns = g.counts[0];
+    if ((int64_t)blockIdx.x >= ns) return -1;
+    return g.slots[blockIdx.x];
+}
+
+__global__ __launch_bounds__(kBatchBlock) void batch_reduce_sigma_kernel(SlotDesc *slots, GroupDev g, int prec)
+{
+    const int sl = group_slot(g);
+    if (sl < 0) return;
+    PcgState *st = slots[sl].st + prec;
+    if (st->done) return;
+    double s[1];
+    slot_sum<1>(g.ax_partial, g.ax_first[sl], g.ax_count[sl], s);
+    if (threadIdx.x == 0) {
+        st->sigma = s[0];
+        if (!(s[0] > 0.0) || !isfinite(s[0])) st->done = 2;
+        else st->alpha = st->rho / s[0];
+    }
+}
+
+__global__ __launch_bounds__(kBatchBlock) void batch_reduce_rho_kernel(SlotDesc *slots, GroupDev g, int prec)
+{
+    const int sl = group_slot(g);
+    if (sl < 0) return;
+    PcgState *st = slots[sl].st + prec;
+    if (st->done) return;
+    double s[2];
+    slot_sum<2>(g.vec_partial, g.vec_first[sl], g.vec_count[sl], s);
+    if (threadIdx.x == 0) {
+        st->iters += 1;
+        st->rr = s[0];
+        st->rho_new = s[1];
+        st->beta = s[1] / st->rho;
+        st->rho = s[1];
+        if (s[0] <= st->stop2) st->done = 1;
+        else if (!isfinite(s[0])) st->done = 2;
+        else if (st->iters >= st->limit) st->done = 3;
+    }
+}
+
+__global__ __launch_bounds__(kBatchBlock) void batch_reduce_init_kernel(SlotDesc *slots, GroupDev g, int prec)
+{
+    const int sl = group_slot(g);
+    if (sl < 0) return;
+    const SlotDesc &sd = slots[sl];
+    PcgState *st = sd.st + prec;
+    double s[2];
+    slot_sum<2>(g.vec_partial, g.vec_first[sl], g.vec_count[sl], s);
+    if (threadIdx.x == 0) {
+        st->rr = s[0];
+        st->rho = s[1];
+        st->rho_new = s[1];
+        st->beta = 0.0;
+        st->alpha = 0.0;
+        st->sigma = 0.0;
+        st->iters = 0;
+        st->limit = sd.limit[prec];
+        st->stop2 = sd.stop2[prec];
+        st->done = (s[0] <= st->stop2) ? 1 : (st->limit <= 0 ? 3 : 0);
+    }
+}
+
+// scal[1] = <r,r>, scal[0] = <b,b> after batch_residual
+__global__ __launch_bounds__(kBatchBlock) void batch_reduce_residual_kernel(SlotDesc *slots, GroupDev g)
+{
+    const int sl = group_slot(g);
+    if (sl < 0) return;
+    double s[2];
+    slot_sum<2>(g.vec_partial, g.vec_first[sl], g.vec_count[sl], s);
+    if (threadIdx.x == 0) {
+        slots[sl].scal[1] = s[0];
+        slots[sl].scal[0] = s[1];
+    }
+}
+
+// ---------------------------------------------------------------------------
+hipError_t batch_ax(int prec, int mode, const SlotDesc *slots, const GroupDev &g, const BatchLaunch &L, hipStream_t s)
+{
+    if (mode == 0)
+        hipLaunchKernelGGL((batch_ax_kernel<double, 0>), dim3(L.ax_grid), dim3(kBatchBlock), L.ax_lds, s, slots, g);
+    else if (prec == 0)
+        hipLaunchKernelGGL((batch_ax_kernel<double, 2>), dim3(L.ax_grid), dim3(kBatchBlock), L.ax_lds, s, slots, g);
+    else
+        hipLaunchKernelGGL((batch_ax_kernel<float, 2>), dim3(L.ax_grid), dim3(kBatchBlock), L.ax_lds, s, slots, g);
+    return hipGetLastError();
+}
+
+hipError_t batch_gs(int prec, int check_done, const SlotDesc *slots, const GroupDev &g, const BatchLaunch &L,
+                    hipStream_t s)
+{
+    if (prec == 0)
+        hipLaunchKernelGGL((batch_gs_kernel<double>), dim3(L.vec_grid), dim3(kBatchBlock), 0, s, slots, g, check_done, 0);
+    else
+        hipLaunchKernelGGL((batch_gs_kernel<float>), dim3(L.vec_grid), dim3(kBatchBlock), 0, s, slots, g, check_done, 0);
+    return hipGetLastError();
+}
+
+hipError_t batch_reduce_sigma(int prec, const SlotDesc *slots, const GroupDev &g, const BatchLaunch &L, hipStream_t s)
+{
+    hipLaunchKernelGGL(batch_reduce_sigma_kernel, dim3(L.max_slots), dim3(kBatchBlock), 0, s,
+                       const_cast<SlotDesc *>(slots), g, prec);
+    return hipGetLastError();
+}
+
+hipError_t batch_update(int prec, const SlotDesc *slots, const GroupDev &g, const BatchLaunch &L, hipStream_t s)
+{
+    if (prec == 0)
+        hipLaunchKernelGGL((batch_update_kernel<double>), dim3(L.vec_grid), dim3(kBatchBlock), 0, s, slots, g);
+    else
+        hipLaunchKernelGGL((batch_update_kernel<float>), dim3(L.vec_grid), dim3(kBatchBlock), 0, s, slots, g);
+    return hipGetLastError();
+}
+
+hipError_t batch_reduce_rho(int prec, const SlotDesc *slots, const GroupDev &g, const BatchLaunch &L, hipStream_t s)
+{
+    hipLaunchKernelGGL(batch_reduce_rho_kernel, dim3(L.max_slots), dim3(kBatchBlock), 0, s,
+                       const_cast<SlotDesc *>(slots), g, prec);
+    return hipGetLastError();
+}
+
+hipError_t batch_cg_init(int prec, const SlotDesc *slots, const GroupDev &g, const BatchLaunch &L, hipStream_t s)
+{
+    if (prec == 0)
+        hipLaunchKernelGGL((batch_init_kernel<double>), dim3(L.vec_grid), dim3(kBatchBlock), 0, s, slots, g);
+    else
+        hipLaunchKernelGGL((batch_init_kernel<float>), dim3(L.vec_grid), dim3(kBatchBlock), 0, s, slots, g);
+    hipLaunchKernelGGL(batch_reduce_init_kernel, dim3(L.max_slots), dim3(kBatchBlock), 0, s,
+                       const_cast<SlotDesc *>(slots), g, prec);
+    return hipGetLastError();
+}
+
+hipError_t batch_residual(int copy_b, const SlotDesc *slots, const GroupDev &g, const BatchLaunch &L, hipStream_t s)
+{
+    hipLaunchKernelGGL(batch_residual_kernel, dim3(L.vec_grid), dim3(kBatchBlock), 0, s, slots, g, copy_b);
+    hipLaunchKernelGGL(batch_reduce_residual_kernel, dim3(L.max_slots), dim3(kBatchBlock), 0, s,
+                       const_cast<SlotDesc *>(slots), g);
+    return hipGetLastError();
+}
+
+hipError_t batch_to_fp32(const SlotDesc *slots, const GroupDev &g, const BatchLaunch &L, hipStream_t s)
+{
+    hipLaunchKernelGGL(batch_to_fp32_kernel, dim3(L.vec_grid), dim3(kBatchBlock), 0, s, slots, g);
+    return hipGetLastError();
+}
+
+hipError_t batch_axpy(const SlotDesc *slots, const GroupDev &g, const BatchLaunch &L, hipStream_t s)
+{
+    hipLaunchKernelGGL(batch_axpy_kernel, dim3(L.vec_grid), dim3(kBatchBlock), 0, s, slots, g);
+    return hipGetLastError();
+}
+
+hipError_t upload_batch_dtables(const double *d64, const float *d32, hipStream_t s)
+{
+    hipError_t e = hipMemcpyToSymbolAsync(HIP_SYMBOL(c_D64), d64, sizeof(double) * kDTableSize, 0,
+                                          hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    return hipMemcpyToSymbolAsync(HIP_SYMBOL(c_D32), d32, sizeof(float) * kDTableSize, 0, hipMemcpyHostToDevice, s);
+}
+
+}  // namespace sem

@@ -15,38 +15,12 @@
 //    <r,z> and <r,r>, per-workgroup partials reduced in a fixed order by a
 //    single-workgroup kernel that also forms alpha and beta on the device.
 #include "kernels.hpp"
+#include "operator.hpp"
 
 namespace sem {
 
-// ---------------------------------------------------------------------------
-// block reductions (fixed order => deterministic)
-template <int NV>
-__device__ inline void block_reduce_store(double (&v)[NV], double *dst, int stride)
-{
-    __shared__ double red[NV][32];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int nwave = (blockDim.x + 63) >> 6;
-#pragma unroll
-    for (int q = 0; q < NV; ++q) {
-        double s = v[q];
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-        if (lane == 0) red[q][wave] = s;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int q = 0; q < NV; ++q) {
-            double s = 0.0;
-            for (int w = 0; w < nwave; ++w) s += red[q][w];
-            dst[(size_t)blockIdx.x * stride + q] = s;
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Local operator (Algorithm 1, h1 = 1).  MODE 0: w = A_L u.  MODE 1: also
-// per-workgroup partial of u.w.  MODE 2 (CG): p <- invdiag*r + beta*p first,
-// then w = A_L p and the partial of p.w.
+// Single mesh, persistent: each workgroup walks element tiles blockIdx.x,
+// blockIdx.x + gridDim.x, ... and stores its dot partial (modes 1, 2).
 template <typename T, int N, int MODE>
 __global__ __launch_bounds__(256) void ax_kernel(AxParams<T> a)
 {
@@ -62,82 +36,19 @@ __global__ __launch_bounds__(256) void ax_kernel(AxParams<T> a)
     const int i = ij % P, j = ij / P;
     const bool inblk = el < a.epw;
     const int slot = inblk ? el : a.epw - 1;  // padding lanes read a valid slot
-    const int64_t e = (int64_t)blockIdx.x * a.epw + el;
-    const bool active = inblk && e < a.E;
     T *su = sm + (size_t)slot * 3 * P3;
-    T *sr = su + P3;
-    T *ss = sr + P3;
-    const T *__restrict__ D = a.D;
-
-    T Di[P], Dj[P], Dti[P], Dtj[P];
-#pragma unroll
-    for (int l = 0; l < P; ++l) {
-        Di[l] = D[i * P + l];
-        Dj[l] = D[j * P + l];
-        Dti[l] = D[l * P + i];
-        Dtj[l] = D[l * P + j];
-    }
-
-    const int64_t base = (active ? e : 0) * P3 + ij;
-    T uc[P];
-    if (MODE == 2) {
-        const T beta = (T)a.st->beta;
-#pragma unroll
-        for (int k = 0; k < P; ++k) {
-            T v = 0;
-            if (active) {
-                const int64_t o = base + k * P2;
-                v = a.invdiag[o] * a.in[o] + beta * a.p[o];
-                a.p[o] = v;
-            }
-            uc[k] = v;
-        }
-    } else {
-#pragma unroll
-        for (int k = 0; k < P; ++k) uc[k] = active ? a.in[base + k * P2] : T(0);
-    }
-    if (inblk) {
-#pragma unroll
-        for (int k = 0; k < P; ++k) su[k * P2 + ij] = uc[k];
-    }
-    __syncthreads();
-
-    const T *__restrict__ Ge = a.G + (active ? e : 0) * 6 * P3 + ij;
-    T wt[P];
-#pragma unroll
-    for (int k = 0; k < P; ++k) {
-        T ur = 0, us = 0, ut = 0;
-#pragma unroll
-        for (int l = 0; l < P; ++l) {
-            ur += Di[l] * su[k * P2 + j * P + l];
-            us += Dj[l] * su[k * P2 + l * P + i];
-            ut += D[k * P + l] * uc[l];
-        }
-        T g1 = 0, g2 = 0, g3 = 0, g4 = 0, g5 = 0, g6 = 0;
-        if (active) {
-            const T *g = Ge + k * P2;
-            g1 = g[0 * P3]; g2 = g[1 * P3]; g3 = g[2 * P3];
-            g4 = g[3 * P3]; g5 = g[4 * P3]; g6 = g[5 * P3];
-        }
-        const T wr = g1 * ur + g4 * us + g5 * ut;
-        const T ws = g2 * us + g4 * ur + g6 * ut;
-        wt[k] = g3 * ut + g5 * ur + g6 * us;
-        if (inblk) {
-            sr[k * P2 + ij] = wr;
-            ss[k * P2 + ij] = ws;
-        }
-    }
-    __syncthreads();
+    const T *__restrict__ D = dtable<T>(N);
+    LaneRows<T, N> R;
+    R.load(D, i, j);
+    T beta = 0;
+    if (MODE == 2) beta = (T)a.st->beta;
 
     double dot = 0.0;
-#pragma unroll
-    for (int k = 0; k < P; ++k) {
-        T acc = 0;
-#pragma unroll
-        for (int l = 0; l < P; ++l)
-            acc += Dti[l] * sr[k * P2 + j * P + l] + Dtj[l] * ss[k * P2 + l * P + i] + D[l * P + k] * wt[l];
-        if (active) a.out[base + k * P2] = acc;
-        if (MODE != 0) dot += (double)uc[k] * (double)acc;
+    const int64_t ntiles = (a.E + a.epw - 1) / a.epw;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t e = tile * a.epw + el;
+        const bool active = inblk && e < a.E;
+        ax_tile<T, N, MODE>(R, D, su, e, active, inblk, i, j, a.G, a.in, a.out, a.invdiag, a.p, beta, dot);
     }
     if (MODE != 0) {
         double v[1] = {dot};
@@ -146,20 +57,27 @@ __global__ __launch_bounds__(256) void ax_kernel(AxParams<T> a)
 }
 
 // ---------------------------------------------------------------------------
-// Gather-scatter from the sorted plan.  Ids [0, n_sum): sum of copies in plan
-// order written to every copy.  Ids [n_sum, n_ids): copies set to 0 (mask).
+// Gather-scatter from the plan sorted by global id (lattice order, so that
+// neighbouring lanes touch neighbouring rows of neighbouring elements).  One
+// lane per global id: ids [0, n_sum) sum their copies (ascending local index,
+// from 0) and write the sum to every copy; ids [n_sum, n_ids) are Dirichlet
+// ids whose copies are set to 0.
 template <typename T>
-__global__ __launch_bounds__(256) void gs_kernel(int64_t first, int64_t n_sum, int64_t n_ids,
-                                                 const int32_t *__restrict__ off,
+__global__ __launch_bounds__(256) void gs_kernel(GsPlan plan, int64_t first, const int32_t *__restrict__ off,
                                                  const int32_t *__restrict__ idx, T *__restrict__ v,
                                                  const PcgState *__restrict__ st)
 {
     if (st && st->done) return;
-    const int64_t t = first + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n_ids) return;
+    // workgroups go to the 8 XCDs round-robin; remap so that each XCD walks
+    // one contiguous range of ids and its L2 sees neighbouring rows together
+    const unsigned nb = gridDim.x, b = blockIdx.x;
+    const unsigned per = nb / 8, rem = nb % 8, xcd = b % 8, k = b / 8;
+    const unsigned lb = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + k;
+    const int64_t t = first + (int64_t)lb * blockDim.x + threadIdx.x;
+    if (t >= plan.n_ids) return;
     const int32_t q0 = off[t], q1 = off[t + 1];
-    if (t < n_sum) {
-        T s = 0;
+    if (t < plan.n_sum) {
+        T s = T(0);
         for (int32_t q = q0; q < q1; ++q) s += v[idx[q]];
         for (int32_t q = q0; q < q1; ++q) v[idx[q]] = s;
     } else {
@@ -243,17 +161,66 @@ __global__ __launch_bounds__(256) void pcg_init_kernel(int64_t n, const T *__res
     block_reduce_store<2>(v, partial, 2);
 }
 
-// x += alpha p, r -= alpha w; partials of <r, r> and <r, invdiag r>
+// x += alpha p, r -= alpha w; partials of <r, r> and <r, invdiag r>.
+// Two consecutive entries per lane and step (16-byte loads for FP64).
+template <typename T>
+struct Pair;
+template <>
+struct Pair<double> {
+    using type = double2;
+};
+template <>
+struct Pair<float> {
+    using type = float2;
+};
+
 template <typename T>
 __global__ __launch_bounds__(256) void pcg_update_kernel(int64_t n, const PcgState *__restrict__ st, T *__restrict__ x,
                                                          T *__restrict__ r, const T *__restrict__ p,
                                                          const T *__restrict__ w, const T *__restrict__ inv,
                                                          const uint8_t *__restrict__ mult, double *__restrict__ partial)
 {
+    using V = typename Pair<T>::type;
+    constexpr int U = 4;  // independent pairs in flight per lane
     if (st->done) return;
     const T alpha = (T)st->alpha;
     double rr = 0.0, rz = 0.0;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t n2 = n >> 1;
+    const int64_t S = (int64_t)gridDim.x * blockDim.x;
+    V *__restrict__ x2 = reinterpret_cast<V *>(x);
+    V *__restrict__ r2 = reinterpret_cast<V *>(r);
+    const V *__restrict__ p2 = reinterpret_cast<const V *>(p);
+    const V *__restrict__ w2 = reinterpret_cast<const V *>(w);
+    const V *__restrict__ i2 = reinterpret_cast<const V *>(inv);
+    const uint16_t *__restrict__ m2 = reinterpret_cast<const uint16_t *>(mult);
+    for (int64_t q0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q0 < n2; q0 += U * S) {
+        V xv[U], rv[U], pv[U], wv[U], iv[U];
+        uint16_t mm[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t q = q0 + u * S;
+            if (q < n2) {
+                xv[u] = x2[q]; rv[u] = r2[q]; pv[u] = p2[q]; wv[u] = w2[q]; iv[u] = i2[q]; mm[u] = m2[q];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t q = q0 + u * S;
+            if (q >= n2) break;
+            xv[u].x = xv[u].x + alpha * pv[u].x;
+            xv[u].y = xv[u].y + alpha * pv[u].y;
+            rv[u].x = rv[u].x - alpha * wv[u].x;
+            rv[u].y = rv[u].y - alpha * wv[u].y;
+            x2[q] = xv[u];
+            r2[q] = rv[u];
+            const double ima = inv_mult((uint8_t)(mm[u] & 0xff)), imb = inv_mult((uint8_t)(mm[u] >> 8));
+            const double ra = (double)rv[u].x, rb = (double)rv[u].y;
+            rr += ra * ra * ima + rb * rb * imb;
+            rz += ra * (double)(iv[u].x * rv[u].x) * ima + rb * (double)(iv[u].y * rv[u].y) * imb;
+        }
+    }
+    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+        const int64_t q = n - 1;
         x[q] = x[q] + alpha * p[q];
         const T rq = r[q] - alpha * w[q];
         r[q] = rq;
@@ -373,15 +340,20 @@ size_t ax_lds_bytes(int N, int epw, size_t elem)
     return (size_t)epw * 3 * P3 * elem;
 }
 
-int64_t ax_blocks(int64_t E, int epw) { return (E + epw - 1) / epw; }
+
+int64_t ax_grid(int64_t E, int epw, int cap)
+{
+    const int64_t tiles = (E + epw - 1) / epw;
+    return tiles < cap ? tiles : cap;
+}
 
 template <typename T, int MODE>
 static hipError_t launch_ax_mode(int N, const AxParams<T> &a, hipStream_t s)
 {
     const int threads = ax_block_threads(N, a.epw);
     const size_t lds = ax_lds_bytes(N, a.epw, sizeof(T));
-    const int64_t blocks = ax_blocks(a.E, a.epw);
-    if (threads > 256 || blocks > INT32_MAX) return hipErrorInvalidConfiguration;
+    const int64_t blocks = ax_grid(a.E, a.epw, a.grid_cap);
+    if (threads > 256 || blocks < 1 || blocks > INT32_MAX) return hipErrorInvalidConfiguration;
     switch (N) {
 #define SEM_AX_CASE(n) \
     case n: hipLaunchKernelGGL((ax_kernel<T, n, MODE>), dim3((unsigned)blocks), dim3(threads), lds, s, a); break;
@@ -404,21 +376,31 @@ template hipError_t launch_ax<double>(int, int, const AxParams<double> &, hipStr
 template hipError_t launch_ax<float>(int, int, const AxParams<float> &, hipStream_t);
 
 template <typename T>
-hipError_t launch_gs(int64_t first, int64_t n_sum, int64_t n_ids, const int32_t *off, const int32_t *idx, T *v,
+hipError_t launch_gs(const GsPlan &plan, const int32_t *off, const int32_t *idx, T *v, bool zero_only,
                      const PcgState *st, hipStream_t s)
 {
-    const int64_t n = n_ids - first;
+    const int64_t first = zero_only ? plan.n_sum : 0;
+    const int64_t n = plan.n_ids - first;
     if (n <= 0) return hipSuccess;
     const int64_t blocks = (n + 255) / 256;
-    hipLaunchKernelGGL((gs_kernel<T>), dim3((unsigned)blocks), dim3(256), 0, s, first, n_sum, n_ids, off, idx, v, st);
+    if (blocks > INT32_MAX) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((gs_kernel<T>), dim3((unsigned)blocks), dim3(256), 0, s, plan, first, off, idx, v, st);
     return hipGetLastError();
 }
-template hipError_t launch_gs<double>(int64_t, int64_t, int64_t, const int32_t *, const int32_t *, double *,
+template hipError_t launch_gs<double>(const GsPlan &, const int32_t *, const int32_t *, double *, bool,
                                       const PcgState *, hipStream_t);
-template hipError_t launch_gs<float>(int64_t, int64_t, int64_t, const int32_t *, const int32_t *, float *,
+template hipError_t launch_gs<float>(const GsPlan &, const int32_t *, const int32_t *, float *, bool,
                                      const PcgState *, hipStream_t);
 
-int vec_blocks(int64_t n) { return grid_for(n, 256, 4096); }
+int vec_blocks(int64_t n) { return grid_for(n, 256, 8192); }
+
+hipError_t upload_dtables(const double *d64, const float *d32, hipStream_t s)
+{
+    hipError_t e = hipMemcpyToSymbolAsync(HIP_SYMBOL(c_D64), d64, sizeof(double) * kDTableSize, 0,
+                                          hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    return hipMemcpyToSymbolAsync(HIP_SYMBOL(c_D32), d32, sizeof(float) * kDTableSize, 0, hipMemcpyHostToDevice, s);
+}
 
 hipError_t launch_scale(int64_t n, const double *a, const double *b, double *out, hipStream_t s)
 {

@@ -9,11 +9,24 @@
 
 namespace sem {
 
+// Derivative matrices of all orders 1..SEM_MAX_ORDER, concatenated.
+constexpr int dtable_offset_host(int N)
+{
+    int o = 0;
+    for (int n = 1; n < N; ++n) o += (n + 1) * (n + 1);
+    return o;
+}
+__host__ __device__ constexpr int dtable_offset(int N)
+{
+    return N <= 1 ? 0 : dtable_offset(N - 1) + N * N;
+}
+constexpr int kDTableSize = dtable_offset_host(SEM_MAX_ORDER + 1);
+
 template <typename T>
 struct AxParams {
     int64_t E;             // elements
-    int epw;               // elements per workgroup
-    const T *D;            // D[i*P+l], P*P entries
+    int epw;               // elements per workgroup (element tile)
+    int grid_cap;          // persistent grid: at most this many workgroups
     const T *G;            // [E][6][P^3]
     const T *in;           // u (modes 0/1) or r (mode 2)
     T *out;                // w
@@ -25,13 +38,14 @@ struct AxParams {
 
 int ax_block_threads(int N, int epw);
 size_t ax_lds_bytes(int N, int epw, size_t elem);
-int64_t ax_blocks(int64_t E, int epw);
+int64_t ax_grid(int64_t E, int epw, int cap);
+hipError_t upload_dtables(const double *d64, const float *d32, hipStream_t s);
 int vec_blocks(int64_t n);
 
 template <typename T>
 hipError_t launch_ax(int N, int mode, const AxParams<T> &a, hipStream_t s);
 template <typename T>
-hipError_t launch_gs(int64_t first, int64_t n_sum, int64_t n_ids, const int32_t *off, const int32_t *idx, T *v,
+hipError_t launch_gs(const GsPlan &plan, const int32_t *off, const int32_t *idx, T *v, bool zero_only,
                      const PcgState *st, hipStream_t s);
 hipError_t launch_scale(int64_t n, const double *a, const double *b, double *out, hipStream_t s);
 hipError_t launch_scatter(int64_t n, const int32_t *gid, const double *vg, double *out, hipStream_t s);

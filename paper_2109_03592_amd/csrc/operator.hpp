@@ -1,0 +1,149 @@
+// operator.hpp -- device building blocks shared by the single-mesh and the
+// batched kernels: fixed-order block reductions, the constant table of GLL
+// derivative matrices and the Algorithm 1 operator on one tile of elements.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace sem {
+
+// ---------------------------------------------------------------------------
+// block reductions (fixed order => deterministic)
+template <int NV>
+__device__ inline void block_reduce_store(double (&v)[NV], double *dst, int stride)
+{
+    __shared__ double red[NV][32];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nwave = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        double s = v[q];
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+        if (lane == 0) red[q][wave] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            double s = 0.0;
+            for (int w = 0; w < nwave; ++w) s += red[q][w];
+            dst[(size_t)blockIdx.x * stride + q] = s;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// GLL derivative matrices of every order in constant memory: the uniform
+// D[k][l] of the t-direction become scalar loads, the per-lane rows vector
+// loads.  Order N lives at offset sum_{n<N} (n+1)^2.
+// (static: every code object that includes this header holds and fills its
+// own copy)
+static __constant__ double c_D64[kDTableSize];
+static __constant__ float c_D32[kDTableSize];
+
+template <typename T>
+__device__ inline const T *dtable(int N);
+template <>
+__device__ inline const double *dtable<double>(int N) { return c_D64 + dtable_offset(N); }
+template <>
+__device__ inline const float *dtable<float>(int N) { return c_D32 + dtable_offset(N); }
+
+// ---------------------------------------------------------------------------
+// Local operator (Algorithm 1, h1 = 1) on one tile of `epw` elements.  Lane
+// (el, i, j) owns column (i,j) of element tile*epw + el.  MODE 0: w = A_L u.
+// MODE 1: also accumulates u.w into `dot`.  MODE 2 (CG): p <- invdiag*r +
+// beta*p first, then w = A_L p and p.w into `dot`.  The caller provides the
+// LDS slot of this lane's element (3 (N+1)^3 values), the lane's rows of D
+// and of D^T, and ends the tile with a barrier before LDS is reused.
+template <typename T, int N>
+struct LaneRows {
+    T Di[N + 1], Dj[N + 1], Dti[N + 1], Dtj[N + 1];
+    __device__ inline void load(const T *__restrict__ D, int i, int j)
+    {
+        constexpr int P = N + 1;
+#pragma unroll
+        for (int l = 0; l < P; ++l) {
+            Di[l] = D[i * P + l];
+            Dj[l] = D[j * P + l];
+            Dti[l] = D[l * P + i];
+            Dtj[l] = D[l * P + j];
+        }
+    }
+};
+
+template <typename T, int N, int MODE>
+__device__ inline void ax_tile(const LaneRows<T, N> &R, const T *__restrict__ D, T *su, int64_t e, bool active,
+                               bool inblk, int i, int j, const T *__restrict__ G, const T *__restrict__ in,
+                               T *__restrict__ out, const T *__restrict__ invdiag, T *__restrict__ p, T beta,
+                               double &dot)
+{
+    constexpr int P = N + 1, P2 = P * P, P3 = P2 * P;
+    T *sr = su + P3;
+    T *ss = sr + P3;
+    const int ij = i + P * j;
+    const int64_t base = (active ? e : 0) * P3 + ij;
+    T uc[P];
+    if (MODE == 2) {
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            T v = 0;
+            if (active) {
+                const int64_t o = base + k * P2;
+                v = invdiag[o] * in[o] + beta * p[o];
+                p[o] = v;
+            }
+            uc[k] = v;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < P; ++k) uc[k] = active ? in[base + k * P2] : T(0);
+    }
+    if (inblk) {
+#pragma unroll
+        for (int k = 0; k < P; ++k) su[k * P2 + ij] = uc[k];
+    }
+    __syncthreads();
+
+    const T *__restrict__ Ge = G + (active ? e : 0) * 6 * P3 + ij;
+    T wt[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        T ur = 0, us = 0, ut = 0;
+#pragma unroll
+        for (int l = 0; l < P; ++l) {
+            ur += R.Di[l] * su[k * P2 + j * P + l];
+            us += R.Dj[l] * su[k * P2 + l * P + i];
+            ut += D[k * P + l] * uc[l];
+        }
+        T g1 = 0, g2 = 0, g3 = 0, g4 = 0, g5 = 0, g6 = 0;
+        if (active) {
+            const T *g = Ge + k * P2;
+            g1 = g[0 * P3]; g2 = g[1 * P3]; g3 = g[2 * P3];
+            g4 = g[3 * P3]; g5 = g[4 * P3]; g6 = g[5 * P3];
+        }
+        const T wr = g1 * ur + g4 * us + g5 * ut;
+        const T ws = g2 * us + g4 * ur + g6 * ut;
+        wt[k] = g3 * ut + g5 * ur + g6 * us;
+        if (inblk) {
+            sr[k * P2 + ij] = wr;
+            ss[k * P2 + ij] = ws;
+        }
+    }
+    __syncthreads();
+
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        T acc = 0;
+#pragma unroll
+        for (int l = 0; l < P; ++l)
+            acc += R.Dti[l] * sr[k * P2 + j * P + l] + R.Dtj[l] * ss[k * P2 + l * P + i] + D[l * P + k] * wt[l];
+        if (active) out[base + k * P2] = acc;
+        if (MODE != 0) dot += (double)uc[k] * (double)acc;
+    }
+    __syncthreads();  // the LDS slot is rewritten by the next tile
+}
+
+
+}  // namespace sem

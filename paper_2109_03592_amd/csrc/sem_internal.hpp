@@ -69,6 +69,13 @@ struct PcgState {
     int pad;
 };
 
+// Device gather-scatter plan: CSR over global ids sorted in lattice order,
+// summed ids [0, n_sum) first, then Dirichlet ids up to n_ids.
+struct GsPlan {
+    int64_t n_sum;
+    int64_t n_ids;
+};
+
 // ---------------------------------------------------------------------------
 struct DeviceBuf {
     void *p = nullptr;
@@ -82,8 +89,6 @@ struct sem_mesh {
     int device = 0;
     int with_fp32 = 0;
     // device arrays
-    double *D64 = nullptr;
-    float *D32 = nullptr;
     double *G64 = nullptr;     // [E][6][P^3]
     float *G32 = nullptr;
     double *B64 = nullptr;     // [nL]
@@ -91,8 +96,9 @@ struct sem_mesh {
     float *inv32 = nullptr;
     uint8_t *mult = nullptr;   // [nL] multiplicity per local node
     int32_t *gid = nullptr;    // [nL]
-    int32_t *gs_off = nullptr;
+    int32_t *gs_off = nullptr;     // gather-scatter plan (CSR)
     int32_t *gs_idx = nullptr;
+    sem::GsPlan gsplan{};
     // Krylov work space, allocated on the first solve
     double *x64 = nullptr, *r64 = nullptr, *p64 = nullptr, *w64 = nullptr;
     float *x32 = nullptr, *r32 = nullptr, *p32 = nullptr, *w32 = nullptr;
@@ -101,11 +107,13 @@ struct sem_mesh {
     sem::PcgState *state = nullptr;  // [2]: FP64 solve, FP32 inner solve
     double *scal = nullptr;          // small device scratch for norms
     int ax_epw = 1;                  // elements per workgroup of the operator
+    int ax_grid_cap = 4096;          // persistent operator grid
     std::vector<hipEvent_t> events;  // profiling event pool
     hipStream_t capture_stream = nullptr;
     hipGraphExec_t graph[2] = {nullptr, nullptr};  // CG iteration blocks, FP64 / FP32
     int graph_k[2] = {0, 0};
     int graph_epw[2] = {0, 0};
+    int graph_grid[2] = {0, 0};
     size_t device_bytes = 0;
     std::vector<void *> allocations;
 };
