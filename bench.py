@@ -43,10 +43,10 @@ def bytes_per_point(N: int, kind: str, dtype_bytes: int = 8) -> float:
     """Algorithmic HBM bytes per local point of one kernel launch."""
     if kind == "ax":          # read u, 6 geometric factors; write w
         return dtype_bytes * (1 + 6 + 1)
-    if kind == "ax_pcg":      # read r, invdiag, p, 6 factors; write p, w
-        return dtype_bytes * (3 + 6 + 2)
-    if kind == "update":      # read x, r, p, w, invdiag, mult(1 B); write x, r
-        return dtype_bytes * 7 + 1
+    if kind == "ax_pcg":      # read r, invdiag, p, x, 6 factors; write p, w, x
+        return dtype_bytes * (4 + 6 + 3)
+    if kind == "update":      # read r, w, invdiag, mult (1 B); write r
+        return dtype_bytes * 4 + 1
     raise ValueError(kind)
 
 
@@ -93,6 +93,47 @@ def cpu_baseline(seconds_target: float = 15.0):
     }
 
 
+def batched_section(sem, torch, SI):
+    """64 independent jittered box meshes (seeds 100+i) solved together,
+    FP64 and mixed, after the autotuner; aggregate throughput."""
+    cases = SI.batched_box_cases(64)
+    meshes, bs = [], []
+    t0 = time.perf_counter()
+    for c in cases:
+        m = sem.box_mesh(c.N, c.nel, vertices=SI.jittered_box_vertices(c.nel, seed=c.seed), with_fp32=True)
+        xyz = torch.from_numpy(m.export_coords()).cuda()
+        f = 3.0 * np.pi ** 2 * torch.sin(np.pi * xyz[0]) * torch.sin(np.pi * xyz[1]) * torch.sin(np.pi * xyz[2])
+        meshes.append(m)
+        bs.append(m.mass(f))
+    t_setup = time.perf_counter() - t0
+    B = sem.Batch(max_slots=64)
+    t0 = time.perf_counter()
+    B.tune(meshes)
+    t_tune = time.perf_counter() - t0
+    res = {"meshes": len(meshes), "elements": int(sum(m.E for m in meshes)),
+           "local_nodes": int(sum(m.n_local for m in meshes)), "global_nodes": int(sum(m.n_global for m in meshes)),
+           "orders": sorted({m.N for m in meshes}), "setup_s": t_setup, "tune_s": t_tune,
+           "epw": {int(N): B.epw(N) for N in sorted({m.N for m in meshes})}}
+    for prec in ("fp64", "mixed"):
+        B.solve(meshes, bs, tol=1e-10, precision=prec, poll_every=16)   # warm-up (graph capture)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xs, rs = B.solve(meshes, bs, tol=1e-10, precision=prec, poll_every=16, raise_on_error=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ok = sum(r.ok and r.rel_residual <= 1e-10 for r in rs)
+        dof_iters = sum(m.n_global * r.iterations for m, r in zip(meshes, rs))
+        res[prec] = {"seconds": dt, "solves_per_s": len(meshes) / dt, "converged": ok,
+                     "iterations_max": max(r.iterations for r in rs), "iterations_sum": sum(r.iterations for r in rs),
+                     "gdofs_aggregate": dof_iters / dt / 1e9}
+        log(f"batched {prec}: {len(meshes)} solves in {dt:.3f} s ({len(meshes) / dt:.1f} solves/s), "
+            f"{ok} converged, aggregate {res[prec]['gdofs_aggregate']:.2f} GDOF/s")
+    B.close()
+    for m in meshes:
+        m.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,6 +145,11 @@ def main():
     ap.add_argument("--no-solve", action="store_true", help="skip the full FP64 / mixed solves")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-axgs", action="store_true", help="skip the stand-alone Ax+gs timing")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-mesh solves")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
+    ap.add_argument("--serve-rates", default="100,1000")
+    ap.add_argument("--serve-duration", type=float, default=5.0)
+    ap.add_argument("--serve-drain", type=float, default=20.0)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -158,7 +204,7 @@ def main():
     t_graph = ev0.elapsed_time(ev1) / 1e3
 
     ax_bytes = bytes_per_point(N, "ax_pcg") * nL
-    roof = {"bound": "hbm", "kernel": f"ax_kernel<double,{N},pcg>",
+    roof = {"bound": "hbm", "kernel": f"ax_kernel<double,{N},cg>",
             "achieved": ax_bytes / (ax_ms / 1e3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "traffic": None}
     roof["frac"] = roof["achieved"] / roof["peak"]
@@ -237,6 +283,16 @@ def main():
                 sol[prec]["rel_diff_vs_fp64"] = err
         sol["mixed_speedup"] = sol["fp64"]["seconds"] / sol["mixed"]["seconds"]
         out["solve"] = sol
+
+    # ---- batched: 64 jittered boxes, E log-uniform in [8, 4096], N in {5,7,9} ----
+    if not args.no_batch:
+        out["batched"] = batched_section(sem, torch, SI)
+
+    # ---- serving: Poisson arrivals of mixed-size solves -------------------------
+    if not args.no_serve:
+        from paper_2109_03592_amd.serve import serve_rates
+        out["serving"] = serve_rates([float(v) for v in args.serve_rates.split(",")], duration=args.serve_duration,
+                                     max_requests=2000, drain_limit=args.serve_drain, max_slots=64, budget_gb=200.0)
 
     # ---- CPU oracle on a bounded sample ---------------------------------------
     if not args.no_cpu:

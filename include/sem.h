@@ -206,7 +206,7 @@ typedef struct {
      * iterations, and the number of operator launches timed */
     double ms_operator;       /* local operator (with the fused p update)      */
     double ms_gather_scatter;
-    double ms_update;         /* x/r update, dot products, alpha/beta          */
+    double ms_update;         /* alpha, r update with dot products, beta      */
     int operator_launches;
 } sem_solve_stats;
 

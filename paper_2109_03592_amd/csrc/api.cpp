@@ -199,6 +199,7 @@ static void enqueue_ax(sem_mesh *m, int mode, const T *in, T *out, hipStream_t s
     if (mode == 2) {
         a.invdiag = Prec<T>::inv(m);
         a.p = Prec<T>::p(m);
+        a.x = Prec<T>::x(m);
         a.st = Prec<T>::st(m);
     }
     SEM_HIP(launch_ax<T>(m->h.N, mode, a, s));
@@ -261,8 +262,8 @@ static void enqueue_iterations(sem_mesh *m, int k, hipStream_t s, Profiler *prof
         enqueue_gs<T>(m, Prec<T>::w(m), st, s);
         if (prof) prof->mark(s);
         SEM_HIP(launch_reduce_sigma(m->partials, axb, st, s));
-        SEM_HIP(launch_pcg_update<T>(nL, st, Prec<T>::x(m), Prec<T>::r(m), Prec<T>::p(m), Prec<T>::w(m),
-                                     Prec<T>::inv(m), m->mult, m->partials, s));
+        SEM_HIP(launch_pcg_update<T>(nL, st, Prec<T>::r(m), Prec<T>::w(m), Prec<T>::inv(m), m->mult, m->partials,
+                                     s));
         SEM_HIP(launch_reduce_rho(m->partials, vec_blocks(nL), st, s));
         if (prof) prof->mark(s);
     }
@@ -345,6 +346,7 @@ static PcgState cg_loop(sem_mesh *m, double stop2, int limit, int poll, bool gra
         run_iterations<T>(m, poll, graph, s, prof);
         hs = read_state(Prec<T>::st(m), s);
     }
+    SEM_HIP(launch_pcg_finish<T>(m->h.nL, Prec<T>::st(m), Prec<T>::x(m), Prec<T>::p(m), s));
     return hs;
 }
 
@@ -378,6 +380,7 @@ static sem_status solve_fp64(sem_mesh *m, const double *b, double *x, const sem_
         out.ms_gather_scatter = prof.ms_gs;
         out.ms_update = prof.ms_up;
         out.operator_launches = prof.launches;
+        SEM_HIP(launch_pcg_finish<double>(nL, m->state, m->x64, m->p64, s));
         const PcgState hs = read_state(m->state, s);
         SEM_HIP(hipMemcpyAsync(x, m->x64, sizeof(double) * nL, hipMemcpyDeviceToDevice, s));
         SEM_HIP(hipStreamSynchronize(s));

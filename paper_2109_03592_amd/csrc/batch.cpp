@@ -433,12 +433,26 @@ static void step_batch(sem_batch *B, int k, bool use_graph, hipStream_t s)
     if (!cg32.empty()) run_batch_iters(B, B->g32, 1, k, use_graph, s);
     if (cg64.empty() && cg32.empty()) return;
     read_states(B, s);
-    // 4. transitions out of CG
-    std::vector<int> axpy;
-    for (int id : cg64) {
+    // 4. transitions out of CG (first the deferred last x step of every slot
+    //    whose CG run ended)
+    std::vector<int> fin64, fin32, axpy;
+    for (int id : cg64)
+        if (B->h_state[2 * id].done) fin64.push_back(id);
+    for (int id : cg32)
+        if (B->h_state[2 * id + 1].done) fin32.push_back(id);
+    if (!fin64.empty()) {
+        Group &g = B->gres;
+        group_build(B, g, fin64, s);
+        SEM_HIP(batch_finish(0, B->d_desc, g.dev(), launch_for(B, g), s));
+    }
+    if (!fin32.empty()) {
+        Group &g = B->gres;
+        group_build(B, g, fin32, s);
+        SEM_HIP(batch_finish(1, B->d_desc, g.dev(), launch_for(B, g), s));
+    }
+    for (int id : fin64) {
         HostSlot &h = B->slots[id];
         const PcgState &st = B->h_state[2 * id];
-        if (!st.done) continue;
         h.iters += st.iters;
         if (st.done == 2) {
             set_error("batched solve: CG breakdown");
@@ -447,10 +461,9 @@ static void step_batch(sem_batch *B, int k, bool use_graph, hipStream_t s)
         }
         h.phase = PH_CHECK;
     }
-    for (int id : cg32) {
+    for (int id : fin32) {
         HostSlot &h = B->slots[id];
         const PcgState &st = B->h_state[2 * id + 1];
-        if (!st.done) continue;
         h.iters += st.iters;
         h.outer++;
         if (st.done == 2 && st.iters == 0) {

@@ -46,7 +46,7 @@ __device__ inline int prec_of() { return sizeof(T) == 8 ? 0 : 1; }
 
 // operator on one tile of one slot (orders dispatched at run time)
 template <typename T, int N, int MODE>
-__device__ inline void slot_tile(const SlotDesc &sd, int64_t tile, T *sm, double &dot, T beta)
+__device__ inline void slot_tile(const SlotDesc &sd, int64_t tile, T *sm, double &dot, T beta, T alpha)
 {
     constexpr int P = N + 1, P2 = P * P, P3 = P2 * P;
     const int prec = prec_of<T>();
@@ -66,11 +66,11 @@ __device__ inline void slot_tile(const SlotDesc &sd, int64_t tile, T *sm, double
     if (MODE == 0) {
         // FP64 residual operator: w = A x
         ax_tile<T, N, 0>(R, D, su, e, active, inblk, i, j, G, reinterpret_cast<const T *>(sd.x64),
-                         reinterpret_cast<T *>(sd.w[0]), nullptr, nullptr, beta, dot);
+                         reinterpret_cast<T *>(sd.w[0]), nullptr, nullptr, beta, nullptr, alpha, dot);
     } else {
         ax_tile<T, N, 2>(R, D, su, e, active, inblk, i, j, G, static_cast<const T *>(sd.r[prec]),
                          static_cast<T *>(sd.w[prec]), static_cast<const T *>(sd.inv[prec]),
-                         static_cast<T *>(sd.p[prec]), beta, dot);
+                         static_cast<T *>(sd.p[prec]), beta, static_cast<T *>(sd.x[prec]), alpha, dot);
     }
 }
 
@@ -89,16 +89,17 @@ __global__ __launch_bounds__(kBatchBlock) void batch_ax_kernel(const SlotDesc *s
         const Item item = items[it];
         const SlotDesc sd = slots[item.slot];
         double dot = 0.0;
-        T beta = 0;
+        T beta = 0, alpha = 0;
         bool skip = false;
         if (MODE == 2) {
             skip = uniform_int(sd.st[prec].done) != 0;
             beta = (T)sd.st[prec].beta;
+            alpha = (T)sd.st[prec].alpha;
         }
         if (!skip) {
             switch (sd.N) {
 #define SEM_BCASE(n) \
-    case n: slot_tile<T, n, MODE>(sd, item.local, sm, dot, beta); break;
+    case n: slot_tile<T, n, MODE>(sd, item.local, sm, dot, beta, alpha); break;
                 SEM_BATCH_ORDERS(SEM_BCASE)
 #undef SEM_BCASE
             default: break;
@@ -140,7 +141,8 @@ __global__ __launch_bounds__(kBatchBlock) void batch_gs_kernel(const SlotDesc *s
 
 __device__ inline double inv_mult_b(uint8_t m) { return 1.0 / (double)m; }
 
-// x += alpha p, r -= alpha w; per-item partials of <r,r>, <r, invdiag r>
+// CG update after the gather-scatter: r -= alpha w; per-item partials of
+// <r,r>, <r, invdiag r>.  The x step is applied by the next operator launch.
 template <typename T>
 __global__ __launch_bounds__(kBatchBlock) void batch_update_kernel(const SlotDesc *slots_, GroupDev g)
 {
@@ -154,16 +156,13 @@ __global__ __launch_bounds__(kBatchBlock) void batch_update_kernel(const SlotDes
         double rr = 0.0, rz = 0.0;
         if (!uniform_int(sd.st[prec].done)) {
             const T alpha = (T)sd.st[prec].alpha;
-            T *x = static_cast<T *>(sd.x[prec]);
             T *r = static_cast<T *>(sd.r[prec]);
-            const T *p = static_cast<const T *>(sd.p[prec]);
             const T *w = static_cast<const T *>(sd.w[prec]);
             const T *iv = static_cast<const T *>(sd.inv[prec]);
             const int64_t q0 = (int64_t)item.local * kVecChunk;
             for (int u = 0; u < kVecChunk / kBatchBlock; ++u) {
                 const int64_t q = q0 + u * kBatchBlock + threadIdx.x;
                 if (q >= sd.nL) break;
-                x[q] = x[q] + alpha * p[q];
                 const T rq = r[q] - alpha * w[q];
                 r[q] = rq;
                 const double rd = (double)rq, im = inv_mult_b(sd.mult[q]);
@@ -261,6 +260,31 @@ __global__ __launch_bounds__(kBatchBlock) void batch_to_fp32_kernel(const SlotDe
             if (q >= sd.nL) break;
             r32[q] = (float)(r[q] * s);
             x32[q] = 0.0f;
+        }
+    }
+}
+
+// end of a slot's CG run: the last deferred x step (none after a breakdown)
+template <typename T>
+__global__ __launch_bounds__(kBatchBlock) void batch_finish_kernel(const SlotDesc *slots_, GroupDev g)
+{
+    cptr<SlotDesc> slots = (cptr<SlotDesc>)slots_;
+    cptr<Item> items = (cptr<Item>)g.vec_items;
+    const int64_t n = ((cptr<int64_t>)g.counts)[3];
+    const int prec = prec_of<T>();
+    for (int64_t it = blockIdx.x; it < n; it += gridDim.x) {
+        const Item item = items[it];
+        const SlotDesc sd = slots[item.slot];
+        const PcgState *st = sd.st + prec;
+        if (uniform_int(st->done) == 2 || uniform_int(st->iters) == 0) continue;
+        const T alpha = (T)st->alpha;
+        T *x = static_cast<T *>(sd.x[prec]);
+        const T *p = static_cast<const T *>(sd.p[prec]);
+        const int64_t q0 = (int64_t)item.local * kVecChunk;
+        for (int u = 0; u < kVecChunk / kBatchBlock; ++u) {
+            const int64_t q = q0 + u * kBatchBlock + threadIdx.x;
+            if (q >= sd.nL) break;
+            x[q] = x[q] + alpha * p[q];
         }
     }
 }
@@ -455,6 +479,15 @@ hipError_t batch_residual(int copy_b, const SlotDesc *slots, const GroupDev &g, 
 hipError_t batch_to_fp32(const SlotDesc *slots, const GroupDev &g, const BatchLaunch &L, hipStream_t s)
 {
     hipLaunchKernelGGL(batch_to_fp32_kernel, dim3(L.vec_grid), dim3(kBatchBlock), 0, s, slots, g);
+    return hipGetLastError();
+}
+
+hipError_t batch_finish(int prec, const SlotDesc *slots, const GroupDev &g, const BatchLaunch &L, hipStream_t s)
+{
+    if (prec == 0)
+        hipLaunchKernelGGL((batch_finish_kernel<double>), dim3(L.vec_grid), dim3(kBatchBlock), 0, s, slots, g);
+    else
+        hipLaunchKernelGGL((batch_finish_kernel<float>), dim3(L.vec_grid), dim3(kBatchBlock), 0, s, slots, g);
     return hipGetLastError();
 }
 

@@ -71,6 +71,7 @@ hipError_t batch_ax(int prec, int mode, const SlotDesc *slots, const GroupDev &g
 hipError_t batch_gs(int prec, int check_done, const SlotDesc *slots, const GroupDev &g, const BatchLaunch &L,
                     hipStream_t s);
 hipError_t batch_reduce_sigma(int prec, const SlotDesc *slots, const GroupDev &g, const BatchLaunch &L, hipStream_t s);
+// r -= alpha w after the gather-scatter, with the dot-product partials
 hipError_t batch_update(int prec, const SlotDesc *slots, const GroupDev &g, const BatchLaunch &L, hipStream_t s);
 hipError_t batch_reduce_rho(int prec, const SlotDesc *slots, const GroupDev &g, const BatchLaunch &L, hipStream_t s);
 // CG start: r[prec] holds the residual; p[prec] <- 0; rho, rr; limit/stop2 from the slot
@@ -79,6 +80,8 @@ hipError_t batch_cg_init(int prec, const SlotDesc *slots, const GroupDev &g, con
 hipError_t batch_residual(int copy_b, const SlotDesc *slots, const GroupDev &g, const BatchLaunch &L, hipStream_t s);
 // mixed: r32 = r64 / sqrt(scal[1]), x32 = 0
 hipError_t batch_to_fp32(const SlotDesc *slots, const GroupDev &g, const BatchLaunch &L, hipStream_t s);
+// end of CG for the group's slots: the deferred last x step
+hipError_t batch_finish(int prec, const SlotDesc *slots, const GroupDev &g, const BatchLaunch &L, hipStream_t s);
 // mixed: x64 += sqrt(scal[1]) x32
 hipError_t batch_axpy(const SlotDesc *slots, const GroupDev &g, const BatchLaunch &L, hipStream_t s);
 // orders the batched operator is built for

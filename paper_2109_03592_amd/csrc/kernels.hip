@@ -40,15 +40,19 @@ __global__ __launch_bounds__(256) void ax_kernel(AxParams<T> a)
     const T *__restrict__ D = dtable<T>(N);
     LaneRows<T, N> R;
     R.load(D, i, j);
-    T beta = 0;
-    if (MODE == 2) beta = (T)a.st->beta;
+    T beta = 0, alpha = 0;
+    if (MODE == 2) {
+        beta = (T)a.st->beta;
+        alpha = (T)a.st->alpha;
+    }
 
     double dot = 0.0;
     const int64_t ntiles = (a.E + a.epw - 1) / a.epw;
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t e = tile * a.epw + el;
         const bool active = inblk && e < a.E;
-        ax_tile<T, N, MODE>(R, D, su, e, active, inblk, i, j, a.G, a.in, a.out, a.invdiag, a.p, beta, dot);
+        ax_tile<T, N, MODE>(R, D, su, e, active, inblk, i, j, a.G, a.in, a.out, a.invdiag, a.p, beta, a.x, alpha,
+                            dot);
     }
     if (MODE != 0) {
         double v[1] = {dot};
@@ -161,8 +165,10 @@ __global__ __launch_bounds__(256) void pcg_init_kernel(int64_t n, const T *__res
     block_reduce_store<2>(v, partial, 2);
 }
 
-// x += alpha p, r -= alpha w; partials of <r, r> and <r, invdiag r>.
-// Two consecutive entries per lane and step (16-byte loads for FP64).
+// CG update after the gather-scatter: r -= alpha w; partials of <r,r> and
+// <r, invdiag r>.  (x += alpha p is applied by the next operator launch, or
+// by pcg_finish_kernel at the end of the run.)  Two consecutive entries per
+// lane and step, four steps in flight.
 template <typename T>
 struct Pair;
 template <>
@@ -175,43 +181,39 @@ struct Pair<float> {
 };
 
 template <typename T>
-__global__ __launch_bounds__(256) void pcg_update_kernel(int64_t n, const PcgState *__restrict__ st, T *__restrict__ x,
-                                                         T *__restrict__ r, const T *__restrict__ p,
-                                                         const T *__restrict__ w, const T *__restrict__ inv,
-                                                         const uint8_t *__restrict__ mult, double *__restrict__ partial)
+__global__ __launch_bounds__(256) void pcg_update_kernel(int64_t n, const PcgState *__restrict__ st,
+                                                         T *__restrict__ r, const T *__restrict__ w,
+                                                         const T *__restrict__ inv,
+                                                         const uint8_t *__restrict__ mult,
+                                                         double *__restrict__ partial)
 {
     using V = typename Pair<T>::type;
-    constexpr int U = 4;  // independent pairs in flight per lane
+    constexpr int U = 4;
     if (st->done) return;
     const T alpha = (T)st->alpha;
     double rr = 0.0, rz = 0.0;
     const int64_t n2 = n >> 1;
     const int64_t S = (int64_t)gridDim.x * blockDim.x;
-    V *__restrict__ x2 = reinterpret_cast<V *>(x);
     V *__restrict__ r2 = reinterpret_cast<V *>(r);
-    const V *__restrict__ p2 = reinterpret_cast<const V *>(p);
     const V *__restrict__ w2 = reinterpret_cast<const V *>(w);
     const V *__restrict__ i2 = reinterpret_cast<const V *>(inv);
     const uint16_t *__restrict__ m2 = reinterpret_cast<const uint16_t *>(mult);
     for (int64_t q0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q0 < n2; q0 += U * S) {
-        V xv[U], rv[U], pv[U], wv[U], iv[U];
+        V rv[U], wv[U], iv[U];
         uint16_t mm[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t q = q0 + u * S;
             if (q < n2) {
-                xv[u] = x2[q]; rv[u] = r2[q]; pv[u] = p2[q]; wv[u] = w2[q]; iv[u] = i2[q]; mm[u] = m2[q];
+                rv[u] = r2[q]; wv[u] = w2[q]; iv[u] = i2[q]; mm[u] = m2[q];
             }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t q = q0 + u * S;
             if (q >= n2) break;
-            xv[u].x = xv[u].x + alpha * pv[u].x;
-            xv[u].y = xv[u].y + alpha * pv[u].y;
             rv[u].x = rv[u].x - alpha * wv[u].x;
             rv[u].y = rv[u].y - alpha * wv[u].y;
-            x2[q] = xv[u];
             r2[q] = rv[u];
             const double ima = inv_mult((uint8_t)(mm[u] & 0xff)), imb = inv_mult((uint8_t)(mm[u] >> 8));
             const double ra = (double)rv[u].x, rb = (double)rv[u].y;
@@ -221,7 +223,6 @@ __global__ __launch_bounds__(256) void pcg_update_kernel(int64_t n, const PcgSta
     }
     if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
         const int64_t q = n - 1;
-        x[q] = x[q] + alpha * p[q];
         const T rq = r[q] - alpha * w[q];
         r[q] = rq;
         const double rd = (double)rq, im = inv_mult(mult[q]);
@@ -462,17 +463,38 @@ template hipError_t launch_pcg_init<float>(int64_t, const float *, const float *
                                            PcgState *, double, int, hipStream_t);
 
 template <typename T>
-hipError_t launch_pcg_update(int64_t n, const PcgState *st, T *x, T *r, const T *p, const T *w, const T *inv,
-                             const uint8_t *mult, double *partial, hipStream_t s)
+hipError_t launch_pcg_update(int64_t n, const PcgState *st, T *r, const T *w, const T *inv, const uint8_t *mult,
+                             double *partial, hipStream_t s)
 {
     const int blocks = vec_blocks(n);
-    hipLaunchKernelGGL((pcg_update_kernel<T>), dim3(blocks), dim3(256), 0, s, n, st, x, r, p, w, inv, mult, partial);
+    hipLaunchKernelGGL((pcg_update_kernel<T>), dim3(blocks), dim3(256), 0, s, n, st, r, w, inv, mult, partial);
     return hipGetLastError();
 }
-template hipError_t launch_pcg_update<double>(int64_t, const PcgState *, double *, double *, const double *,
-                                              const double *, const double *, const uint8_t *, double *, hipStream_t);
-template hipError_t launch_pcg_update<float>(int64_t, const PcgState *, float *, float *, const float *,
-                                             const float *, const float *, const uint8_t *, double *, hipStream_t);
+template hipError_t launch_pcg_update<double>(int64_t, const PcgState *, double *, const double *, const double *,
+                                              const uint8_t *, double *, hipStream_t);
+template hipError_t launch_pcg_update<float>(int64_t, const PcgState *, float *, const float *, const float *,
+                                             const uint8_t *, double *, hipStream_t);
+
+// End of a CG run: apply the last x step (not after a breakdown, whose alpha
+// was never formed).
+template <typename T>
+__global__ __launch_bounds__(256) void pcg_finish_kernel(int64_t n, const PcgState *__restrict__ st,
+                                                         T *__restrict__ x, const T *__restrict__ p)
+{
+    if (st->done == 2 || st->iters == 0) return;
+    const T alpha = (T)st->alpha;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
+        x[q] = x[q] + alpha * p[q];
+}
+
+template <typename T>
+hipError_t launch_pcg_finish(int64_t n, const PcgState *st, T *x, const T *p, hipStream_t s)
+{
+    hipLaunchKernelGGL((pcg_finish_kernel<T>), dim3(vec_blocks(n)), dim3(256), 0, s, n, st, x, p);
+    return hipGetLastError();
+}
+template hipError_t launch_pcg_finish<double>(int64_t, const PcgState *, double *, const double *, hipStream_t);
+template hipError_t launch_pcg_finish<float>(int64_t, const PcgState *, float *, const float *, hipStream_t);
 
 hipError_t launch_reduce_sigma(const double *partial, int64_t n, PcgState *st, hipStream_t s)
 {

@@ -33,7 +33,8 @@ struct AxParams {
     double *partial;       // per-workgroup dot partials (modes 1/2)
     const T *invdiag;      // mode 2
     T *p;                  // mode 2: search direction, updated in place
-    const PcgState *st;    // mode 2: beta and the done flag
+    T *x;                  // mode 2: iterate, receives the previous step alpha*p
+    const PcgState *st;    // mode 2: alpha, beta and the done flag
 };
 
 int ax_block_threads(int N, int epw);
@@ -60,8 +61,10 @@ template <typename T>
 hipError_t launch_pcg_init(int64_t n, const T *r, const T *inv, const uint8_t *mult, double *partial,
                            PcgState *st, double stop2, int limit, hipStream_t s);
 template <typename T>
-hipError_t launch_pcg_update(int64_t n, const PcgState *st, T *x, T *r, const T *p, const T *w, const T *inv,
-                             const uint8_t *mult, double *partial, hipStream_t s);
+hipError_t launch_pcg_update(int64_t n, const PcgState *st, T *r, const T *w, const T *inv, const uint8_t *mult,
+                             double *partial, hipStream_t s);
+template <typename T>
+hipError_t launch_pcg_finish(int64_t n, const PcgState *st, T *x, const T *p, hipStream_t s);
 hipError_t launch_reduce_sigma(const double *partial, int64_t n, PcgState *st, hipStream_t s);
 hipError_t launch_reduce_rho(const double *partial, int64_t n, PcgState *st, hipStream_t s);
 hipError_t launch_reduce_scalar(const double *partial, int64_t n, double *out, hipStream_t s);

@@ -53,8 +53,9 @@ __device__ inline const float *dtable<float>(int N) { return c_D32 + dtable_offs
 // ---------------------------------------------------------------------------
 // Local operator (Algorithm 1, h1 = 1) on one tile of `epw` elements.  Lane
 // (el, i, j) owns column (i,j) of element tile*epw + el.  MODE 0: w = A_L u.
-// MODE 1: also accumulates u.w into `dot`.  MODE 2 (CG): p <- invdiag*r +
-// beta*p first, then w = A_L p and p.w into `dot`.  The caller provides the
+// MODE 1: also accumulates u.w into `dot`.  MODE 2 (CG): first x <- x +
+// alpha*p (the previous iteration's step) and p <- invdiag*r + beta*p, then
+// w = A_L p and p.w into `dot`.  The caller provides the
 // LDS slot of this lane's element (3 (N+1)^3 values), the lane's rows of D
 // and of D^T, and ends the tile with a barrier before LDS is reused.
 template <typename T, int N>
@@ -77,7 +78,7 @@ template <typename T, int N, int MODE>
 __device__ inline void ax_tile(const LaneRows<T, N> &R, const T *__restrict__ D, T *su, int64_t e, bool active,
                                bool inblk, int i, int j, const T *__restrict__ G, const T *__restrict__ in,
                                T *__restrict__ out, const T *__restrict__ invdiag, T *__restrict__ p, T beta,
-                               double &dot)
+                               T *__restrict__ x, T alpha, double &dot)
 {
     constexpr int P = N + 1, P2 = P * P, P3 = P2 * P;
     T *sr = su + P3;
@@ -91,7 +92,10 @@ __device__ inline void ax_tile(const LaneRows<T, N> &R, const T *__restrict__ D,
             T v = 0;
             if (active) {
                 const int64_t o = base + k * P2;
-                v = invdiag[o] * in[o] + beta * p[o];
+                const T pold = p[o];
+                // the previous iteration's x step, deferred to here where p is read anyway
+                x[o] = x[o] + alpha * pold;
+                v = invdiag[o] * in[o] + beta * pold;
                 p[o] = v;
             }
             uc[k] = v;
