@@ -128,6 +128,29 @@ def batched_section(sem, torch, SI):
                      "gdofs_aggregate": dof_iters / dt / 1e9}
         log(f"batched {prec}: {len(meshes)} solves in {dt:.3f} s ({len(meshes) / dt:.1f} solves/s), "
             f"{ok} converged, aggregate {res[prec]['gdofs_aggregate']:.2f} GDOF/s")
+    # steady CG iteration rate with every slot active (tolerances no run reaches)
+    for prec in ("fp64", "mixed"):
+        xs = [m.zeros() for m in meshes]
+        slots = [B.admit(m, b, x, tol=1e-300, max_iter=10 ** 6, precision=prec, inner_tol=1e-30,
+                         inner_max_iter=10 ** 6) for m, b, x in zip(meshes, bs, xs)]
+        B.step(16)
+        B.step(16)
+        torch.cuda.synchronize()
+        reps = 8
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            B.step(16)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / (16 * reps)
+        live = len(slots) - len(B.finished())
+        for sl in slots:
+            B.retire(sl)
+        key = f"steady_{prec}"
+        res[key] = {"ms_per_iteration": dt * 1e3, "active": live,
+                    "gdofs": res["global_nodes"] / dt / 1e9,
+                    "local_points_per_s": res["local_nodes"] / dt}
+        log(f"batched steady {prec}: {dt * 1e3:.3f} ms per iteration of all {live} slots -> "
+            f"{res[key]['gdofs']:.2f} GDOF/s ({res['local_nodes'] / dt / 1e9:.2f} G local points/s)")
     B.close()
     for m in meshes:
         m.close()

@@ -232,9 +232,10 @@ sem_status sem_pcg_solve(sem_mesh *mesh, const double *b, double *x, const sem_s
  * Batched and continuous solves.  A batch holds up to max_slots concurrent
  * solves ("slots"), each on any mesh (orders 2..10, any size) with its own
  * right-hand side, solution and precision.  Every CG phase of all slots runs
- * as one persistent launch over a table of (slot, element tile) work items --
- * the paper moves loops of small kernels inside the kernel (section 3) -- and
- * poll_every iterations are replayed as one hipGraph.  Each slot's dot
+ * as one persistent launch over a table of (slot, element tile) work items
+ * (the operator: one launch per order present) -- the paper moves loops of
+ * small kernels inside the kernel (section 3) -- and poll_every iterations
+ * are replayed as one hipGraph.  Each slot's dot
  * products are summed from its own items in a fixed order, so a slot's result
  * does not depend on which other slots share the launches.
  *
@@ -251,7 +252,9 @@ sem_status sem_batch_free(sem_batch *batch);
  * each candidate elements-per-workgroup and keep the fastest; then choose the
  * persistent grid size.  The batch must have no admitted slots. */
 sem_status sem_batch_tune(sem_batch *batch, sem_mesh *const *meshes, int n, void *stream);
-sem_status sem_batch_set_epw(sem_batch *batch, int N, int epw);  /* 0 restores the default */
+/* Elements per operator workgroup for order N (epw (N+1)^2 <= 256; 0 restores
+ * the default).  The batch must have no admitted slots (SEM_EINVAL). */
+sem_status sem_batch_set_epw(sem_batch *batch, int N, int epw);
 sem_status sem_batch_get_epw(const sem_batch *batch, int N, int *epw);
 
 /* One-shot: solve A_i x_i = b_i for i < n together (b_i, x_i device FP64

@@ -56,10 +56,10 @@ struct Group {
     std::vector<int32_t> h_slots;
     std::vector<Item> h_ax, h_gs, h_vec;
     std::vector<int64_t> h_axf, h_axc, h_vf, h_vc;
-    size_t lds = 0;
+    unsigned orders = 0;          // orders present in the tables
     hipGraphExec_t graph = nullptr;
     int graph_k = 0;
-    size_t graph_lds = 0;
+    unsigned graph_orders = 0;    // orders the cached graph launches
     GroupDev dev() const
     {
         GroupDev g;
@@ -124,14 +124,16 @@ static void *balloc(sem_batch *B, size_t bytes)
     return p;
 }
 
+// elements per operator tile: fill whole waves, preferring small tiles
 static int default_batch_epw(int N)
 {
     const int P2 = (N + 1) * (N + 1);
     int best = 1;
     double best_fill = 0.0;
-    for (int e = 1; e * P2 <= kBatchBlock; ++e) {
-        const double fill = (double)(e * P2) / kBatchBlock;
-        if (fill > best_fill + 1e-9) {
+    for (int e = 1; e * P2 <= 256; ++e) {
+        const int t = e * P2, tr = (t + 63) / 64 * 64;
+        const double fill = (double)t / tr;
+        if (fill > best_fill + 0.06) {
             best_fill = fill;
             best = e;
         }
@@ -139,17 +141,19 @@ static int default_batch_epw(int N)
     return best;
 }
 
+static int batch_epw(const sem_batch *B, int N) { return B->epw[N] > 0 ? B->epw[N] : default_batch_epw(N); }
+
 static void group_alloc(sem_batch *B, Group &g)
 {
     const int ms = B->max_slots;
     g.slots = (int32_t *)balloc(B, sizeof(int32_t) * ms);
-    g.counts = (int64_t *)balloc(B, sizeof(int64_t) * 4);
+    g.counts = (int64_t *)balloc(B, sizeof(int64_t) * kCountSize);
     g.ax_first = (int64_t *)balloc(B, sizeof(int64_t) * ms);
     g.ax_count = (int64_t *)balloc(B, sizeof(int64_t) * ms);
     g.vec_first = (int64_t *)balloc(B, sizeof(int64_t) * ms);
     g.vec_count = (int64_t *)balloc(B, sizeof(int64_t) * ms);
     g.cap_ax = g.cap_gs = g.cap_vec = 0;
-    SEM_HIP(hipMemset(g.counts, 0, sizeof(int64_t) * 4));
+    SEM_HIP(hipMemset(g.counts, 0, sizeof(int64_t) * kCountSize));
 }
 
 // grow item tables (device addresses change: cached graphs are dropped; the
@@ -195,26 +199,38 @@ static void group_build(sem_batch *B, Group &g, const std::vector<int> &ids, hip
     g.h_axc.assign(B->max_slots, 0);
     g.h_vf.assign(B->max_slots, 0);
     g.h_vc.assign(B->max_slots, 0);
-    size_t lds = 0;
+    int64_t counts[kCountSize] = {0};
+    g.orders = 0;
+    // operator items by order (one launch per order), then by slot
+    for (int N = 1; N <= SEM_MAX_ORDER; ++N) {
+        const int64_t first = (int64_t)g.h_ax.size();
+        for (int id : ids) {
+            const SlotDesc &d = B->h_desc[id];
+            if (d.N != N) continue;
+            const int64_t nt = (d.E + d.epw - 1) / d.epw;
+            g.h_axf[id] = (int64_t)g.h_ax.size();
+            g.h_axc[id] = nt;
+            for (int64_t t = 0; t < nt; ++t) g.h_ax.push_back(Item{id, (int32_t)t});
+        }
+        counts[kCountAxRange + 2 * N] = first;
+        counts[kCountAxRange + 2 * N + 1] = (int64_t)g.h_ax.size() - first;
+        if ((int64_t)g.h_ax.size() > first) g.orders |= 1u << N;
+    }
     for (int id : ids) {
         const SlotDesc &d = B->h_desc[id];
-        const int64_t nt = (d.E + d.epw - 1) / d.epw;
-        g.h_axf[id] = (int64_t)g.h_ax.size();
-        g.h_axc[id] = nt;
-        for (int64_t t = 0; t < nt; ++t) g.h_ax.push_back(Item{id, (int32_t)t});
         const int64_t ng = (d.gs_n_ids + kGsChunk - 1) / kGsChunk;
         for (int64_t t = 0; t < ng; ++t) g.h_gs.push_back(Item{id, (int32_t)t});
         const int64_t nv = (d.nL + kVecChunk - 1) / kVecChunk;
         g.h_vf[id] = (int64_t)g.h_vec.size();
         g.h_vc[id] = nv;
         for (int64_t t = 0; t < nv; ++t) g.h_vec.push_back(Item{id, (int32_t)t});
-        lds = std::max(lds, batch_ax_lds(d.N, d.epw, 0));
     }
     group_reserve(B, g, std::max<size_t>(g.h_ax.size(), 1), std::max<size_t>(g.h_gs.size(), 1),
                   std::max<size_t>(g.h_vec.size(), 1));
-    g.lds = lds;
-    const int64_t counts[4] = {(int64_t)ids.size(), (int64_t)g.h_ax.size(), (int64_t)g.h_gs.size(),
-                               (int64_t)g.h_vec.size()};
+    counts[0] = (int64_t)ids.size();
+    counts[1] = (int64_t)g.h_ax.size();
+    counts[2] = (int64_t)g.h_gs.size();
+    counts[3] = (int64_t)g.h_vec.size();
     SEM_HIP(hipMemcpyAsync(g.counts, counts, sizeof(counts), hipMemcpyHostToDevice, s));
     if (!ids.empty()) SEM_HIP(hipMemcpyAsync(g.slots, g.h_slots.data(), sizeof(int32_t) * ids.size(), hipMemcpyHostToDevice, s));
     if (!g.h_ax.empty()) SEM_HIP(hipMemcpyAsync(g.ax_items, g.h_ax.data(), sizeof(Item) * g.h_ax.size(), hipMemcpyHostToDevice, s));
@@ -228,12 +244,15 @@ static void group_build(sem_batch *B, Group &g, const std::vector<int> &ids, hip
     SEM_HIP(hipStreamSynchronize(s));
 }
 
-static BatchLaunch launch_for(sem_batch *B, const Group &g)
+static BatchLaunch launch_for(sem_batch *B, unsigned orders)
 {
     BatchLaunch L = B->L;
-    L.ax_lds = std::max<size_t>(g.lds, 16);
+    L.orders = orders;
+    for (int N = 0; N <= SEM_MAX_ORDER; ++N) L.epw[N] = N >= 1 ? batch_epw(B, N) : 1;
     return L;
 }
+
+static BatchLaunch launch_for(sem_batch *B, const Group &g) { return launch_for(B, g.orders); }
 
 static void upload_desc(sem_batch *B, int id, hipStream_t s)
 {
@@ -241,10 +260,10 @@ static void upload_desc(sem_batch *B, int id, hipStream_t s)
 }
 
 // one CG iteration of every slot in g, precision prec
-static void enqueue_batch_iters(sem_batch *B, Group &g, int prec, int k, hipStream_t s)
+static void enqueue_batch_iters(sem_batch *B, Group &g, int prec, int k, unsigned orders, hipStream_t s)
 {
     const GroupDev gd = g.dev();
-    const BatchLaunch L = launch_for(B, g);
+    const BatchLaunch L = launch_for(B, orders);
     for (int it = 0; it < k; ++it) {
         SEM_HIP(batch_ax(prec, 2, B->d_desc, gd, L, s));
         SEM_HIP(batch_gs(prec, 1, B->d_desc, gd, L, s));
@@ -258,20 +277,22 @@ static void run_batch_iters(sem_batch *B, Group &g, int prec, int k, bool use_gr
 {
     if (g.h_slots.empty()) return;
     if (!use_graph) {
-        enqueue_batch_iters(B, g, prec, k, s);
+        enqueue_batch_iters(B, g, prec, k, g.orders, s);
         return;
     }
-    if (!g.graph || g.graph_k != k || g.graph_lds < g.lds) {
+    // a cached graph serves any membership whose orders it launches (an
+    // order without items exits at once)
+    if (!g.graph || g.graph_k != k || (g.orders & ~g.graph_orders) != 0) {
+        const unsigned orders = g.orders | (g.graph ? g.graph_orders : 0u);
         if (g.graph) {
             SEM_HIP(hipGraphExecDestroy(g.graph));
             g.graph = nullptr;
         }
         if (!B->capture) SEM_HIP(hipStreamCreateWithFlags(&B->capture, hipStreamNonBlocking));
-        // capture with the largest LDS seen so far so that later members fit
         hipGraph_t gr = nullptr;
         SEM_HIP(hipStreamBeginCapture(B->capture, hipStreamCaptureModeThreadLocal));
         try {
-            enqueue_batch_iters(B, g, prec, k, B->capture);
+            enqueue_batch_iters(B, g, prec, k, orders, B->capture);
         } catch (...) {
             hipStreamEndCapture(B->capture, &gr);
             if (gr) hipGraphDestroy(gr);
@@ -284,7 +305,7 @@ static void run_batch_iters(sem_batch *B, Group &g, int prec, int k, bool use_gr
         SEM_HIP(e);
         g.graph = ex;
         g.graph_k = k;
-        g.graph_lds = g.lds;
+        g.graph_orders = orders;
     }
     SEM_HIP(hipGraphLaunch(g.graph, s));
 }
@@ -543,7 +564,7 @@ static int admit_slot(sem_batch *B, sem_mesh *m, const double *b, double *x, con
     std::memset(&d, 0, sizeof(d));
     const HostMesh &hm = m->h;
     d.N = hm.N;
-    d.epw = B->epw[hm.N] > 0 ? B->epw[hm.N] : default_batch_epw(hm.N);
+    d.epw = batch_epw(B, hm.N);
     d.E = hm.E;
     d.nL = hm.nL;
     d.G[0] = m->G64;
@@ -616,10 +637,9 @@ sem_status sem_batch_create(int max_slots, size_t device_budget, void *stream, s
             group_alloc(B, B->g32);
             group_alloc(B, B->gres);
             const int cap = persistent_grid_cap_public();
-            B->L.ax_grid = cap / 4;
+            B->L.ax_grid = cap;
             B->L.vec_grid = cap;
             B->L.max_slots = max_slots;
-            B->L.ax_lds = 16;
             SEM_HIP(hipStreamSynchronize(s));
         } catch (...) {
             sem_batch_free(B);
@@ -796,11 +816,12 @@ sem_status sem_batch_tune(sem_batch *B, sem_mesh *const *meshes, int n, void *st
                 for (int id : ids)
                     if (B->h_desc[id].N == N) grp.push_back(id);
                 if (grp.empty()) continue;
-                const int P2 = (N + 1) * (N + 1), emax = kBatchBlock / P2;
+                const int P2 = (N + 1) * (N + 1), emax = 256 / P2;
                 double best = 1e300;
                 int best_e = default_batch_epw(N);
                 for (int e = 1; e <= emax; ++e) {
                     if (emax > 8 && e != 1 && e != emax && (e & (e - 1)) != 0) continue;
+                    B->epw[N] = e;
                     for (int id : grp) {
                         B->h_desc[id].epw = e;
                         upload_desc(B, id, s);
@@ -850,8 +871,15 @@ sem_status sem_batch_set_epw(sem_batch *B, int N, int epw)
     return bguard([&]() -> sem_status {
         if (!B || N < 1 || N > SEM_MAX_ORDER) fail(SEM_EINVAL, "sem_batch_set_epw: bad order");
         const int P2 = (N + 1) * (N + 1);
-        if (epw < 0 || epw * P2 > kBatchBlock) fail(SEM_EINVAL, "sem_batch_set_epw: epw out of range");
+        if (epw < 0 || epw * P2 > 256) fail(SEM_EINVAL, "sem_batch_set_epw: epw out of range");
+        for (int id = 0; id < B->max_slots; ++id)
+            if (B->slots[id].phase != PH_FREE) fail(SEM_EINVAL, "sem_batch_set_epw: the batch must be empty");
         B->epw[N] = epw;
+        for (Group *g : {&B->g64, &B->g32})
+            if (g->graph) {
+                hipGraphExecDestroy(g->graph);
+                g->graph = nullptr;
+            }
         return SEM_OK;
     });
 }

@@ -33,79 +33,56 @@ bool batch_order_supported(int N)
     }
 }
 
-size_t batch_ax_lds(int N, int epw, int prec)
-{
-    const size_t P3 = (size_t)(N + 1) * (N + 1) * (N + 1);
-    return (size_t)epw * 3 * P3 * (prec == 0 ? 8 : 4);
-}
-
 __device__ inline int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 template <typename T>
 __device__ inline int prec_of() { return sizeof(T) == 8 ? 0 : 1; }
+template <typename T>
+static inline int prec_of_host() { return sizeof(T) == 8 ? 0 : 1; }
 
-// operator on one tile of one slot (orders dispatched at run time)
+// Operator of one order N over that order's items of the group.  MODE 0:
+// w[0] = A x64 (FP64).  MODE 2: CG operator with the p update and per-item
+// p.Ap partials.  A workgroup is epw elements x (N+1)^2 lanes, as in the
+// single-mesh kernel; the derivative rows are loaded once per workgroup.
 template <typename T, int N, int MODE>
-__device__ inline void slot_tile(const SlotDesc &sd, int64_t tile, T *sm, double &dot, T beta, T alpha)
+__global__ __launch_bounds__(256) void batch_ax_kernel(const SlotDesc *slots_, GroupDev g, int epw)
 {
     constexpr int P = N + 1, P2 = P * P, P3 = P2 * P;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *sm = reinterpret_cast<T *>(smem_raw);
+    cptr<SlotDesc> slots = (cptr<SlotDesc>)slots_;
+    cptr<Item> items = (cptr<Item>)g.ax_items;
+    const int64_t first = ((cptr<int64_t>)g.counts)[kCountAxRange + 2 * N];
+    const int64_t n = ((cptr<int64_t>)g.counts)[kCountAxRange + 2 * N + 1];
     const int prec = prec_of<T>();
     const int tid = threadIdx.x;
     const int el = tid / P2;
     const int ij = tid - el * P2;
     const int i = ij % P, j = ij / P;
-    const bool inblk = el < sd.epw;
-    const int lslot = inblk ? el : sd.epw - 1;
-    T *su = sm + (size_t)lslot * 3 * P3;
+    const bool inblk = el < epw;
+    T *su = sm + (size_t)(inblk ? el : epw - 1) * 3 * P3;
     const T *__restrict__ D = dtable<T>(N);
+    __shared__ T sDt[lane_rows_lds<T, N>()];
     LaneRows<T, N> R;
-    R.load(D, i, j);
-    const int64_t e = tile * sd.epw + el;
-    const bool active = inblk && e < sd.E;
-    const T *G = static_cast<const T *>(sd.G[prec]);
-    if (MODE == 0) {
-        // FP64 residual operator: w = A x
-        ax_tile<T, N, 0>(R, D, su, e, active, inblk, i, j, G, reinterpret_cast<const T *>(sd.x64),
-                         reinterpret_cast<T *>(sd.w[0]), nullptr, nullptr, beta, nullptr, alpha, dot);
-    } else {
-        ax_tile<T, N, 2>(R, D, su, e, active, inblk, i, j, G, static_cast<const T *>(sd.r[prec]),
-                         static_cast<T *>(sd.w[prec]), static_cast<const T *>(sd.inv[prec]),
-                         static_cast<T *>(sd.p[prec]), beta, static_cast<T *>(sd.x[prec]), alpha, dot);
-    }
-}
-
-// MODE 0: w[0] = A x64 (FP64).  MODE 2: CG operator with the p update and
-// per-item p.Ap partials.
-template <typename T, int MODE>
-__global__ __launch_bounds__(kBatchBlock) void batch_ax_kernel(const SlotDesc *slots_, GroupDev g)
-{
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *sm = reinterpret_cast<T *>(smem_raw);
-    cptr<SlotDesc> slots = (cptr<SlotDesc>)slots_;
-    cptr<Item> items = (cptr<Item>)g.ax_items;
-    const int64_t n = ((cptr<int64_t>)g.counts)[1];
-    const int prec = prec_of<T>();
-    for (int64_t it = blockIdx.x; it < n; it += gridDim.x) {
+    R.load(D, i, j, sDt);
+    for (int64_t it = first + blockIdx.x; it < first + n; it += gridDim.x) {
         const Item item = items[it];
         const SlotDesc sd = slots[item.slot];
+        const int64_t e = (int64_t)item.local * epw + el;
+        const bool active = inblk && e < sd.E;
         double dot = 0.0;
-        T beta = 0, alpha = 0;
-        bool skip = false;
-        if (MODE == 2) {
-            skip = uniform_int(sd.st[prec].done) != 0;
-            beta = (T)sd.st[prec].beta;
-            alpha = (T)sd.st[prec].alpha;
-        }
-        if (!skip) {
-            switch (sd.N) {
-#define SEM_BCASE(n) \
-    case n: slot_tile<T, n, MODE>(sd, item.local, sm, dot, beta, alpha); break;
-                SEM_BATCH_ORDERS(SEM_BCASE)
-#undef SEM_BCASE
-            default: break;
+        if (MODE == 0) {
+            ax_tile<T, N, 0>(R, D, su, e, active, inblk, i, j, static_cast<const T *>(sd.G[0]),
+                             reinterpret_cast<const T *>(sd.x64), static_cast<T *>(sd.w[0]), nullptr, nullptr, T(0),
+                             nullptr, T(0), dot);
+        } else {
+            if (uniform_int(sd.st[prec].done) == 0) {
+                const T beta = (T)sd.st[prec].beta, alpha = (T)sd.st[prec].alpha;
+                ax_tile<T, N, 2>(R, D, su, e, active, inblk, i, j, static_cast<const T *>(sd.G[prec]),
+                                 static_cast<const T *>(sd.r[prec]), static_cast<T *>(sd.w[prec]),
+                                 static_cast<const T *>(sd.inv[prec]), static_cast<T *>(sd.p[prec]), beta,
+                                 static_cast<T *>(sd.x[prec]), alpha, dot);
             }
-        }
-        if (MODE == 2) {
             double v[1] = {dot};
             block_reduce_store<1>(v, g.ax_partial + it, 0);
             __syncthreads();
@@ -128,14 +105,7 @@ __global__ __launch_bounds__(kBatchBlock) void batch_gs_kernel(const SlotDesc *s
         T *v = static_cast<T *>(which == 0 ? sd.w[prec] : sd.w[0]);
         const int64_t t = (int64_t)item.local * kGsChunk + threadIdx.x;
         if (t >= sd.gs_n_ids) continue;
-        const int32_t q0 = sd.gs_off[t], q1 = sd.gs_off[t + 1];
-        if (t < sd.gs_n_sum) {
-            T s = T(0);
-            for (int32_t q = q0; q < q1; ++q) s += v[sd.gs_idx[q]];
-            for (int32_t q = q0; q < q1; ++q) v[sd.gs_idx[q]] = s;
-        } else {
-            for (int32_t q = q0; q < q1; ++q) v[sd.gs_idx[q]] = T(0);
-        }
+        gs_id<T>(t, sd.gs_n_sum, sd.gs_off, sd.gs_idx, v);
     }
 }
 
@@ -413,15 +383,40 @@ __global__ __launch_bounds__(kBatchBlock) void batch_reduce_residual_kernel(Slot
 }
 
 // ---------------------------------------------------------------------------
+size_t batch_ax_lds(int N, int epw, int prec)
+{
+    const size_t P3 = (size_t)(N + 1) * (N + 1) * (N + 1);
+    return (size_t)epw * 3 * P3 * (prec == 0 ? 8 : 4);
+}
+
+template <typename T, int MODE>
+static hipError_t batch_ax_order(int N, const SlotDesc *slots, const GroupDev &g, const BatchLaunch &L, hipStream_t s)
+{
+    const int epw = L.epw[N];
+    const int threads = ax_block_threads(N, epw);
+    if (epw < 1 || threads > 256) return hipErrorInvalidConfiguration;
+    const size_t lds = batch_ax_lds(N, epw, prec_of_host<T>());
+    switch (N) {
+#define SEM_BCASE(n) \
+    case n: hipLaunchKernelGGL((batch_ax_kernel<T, n, MODE>), dim3(L.ax_grid), dim3(threads), lds, s, slots, g, epw); break;
+        SEM_BATCH_ORDERS(SEM_BCASE)
+#undef SEM_BCASE
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t batch_ax(int prec, int mode, const SlotDesc *slots, const GroupDev &g, const BatchLaunch &L, hipStream_t s)
 {
-    if (mode == 0)
-        hipLaunchKernelGGL((batch_ax_kernel<double, 0>), dim3(L.ax_grid), dim3(kBatchBlock), L.ax_lds, s, slots, g);
-    else if (prec == 0)
-        hipLaunchKernelGGL((batch_ax_kernel<double, 2>), dim3(L.ax_grid), dim3(kBatchBlock), L.ax_lds, s, slots, g);
-    else
-        hipLaunchKernelGGL((batch_ax_kernel<float, 2>), dim3(L.ax_grid), dim3(kBatchBlock), L.ax_lds, s, slots, g);
-    return hipGetLastError();
+    for (int N = 1; N <= SEM_MAX_ORDER; ++N) {
+        if (!(L.orders & (1u << N))) continue;
+        hipError_t e;
+        if (mode == 0) e = batch_ax_order<double, 0>(N, slots, g, L, s);
+        else if (prec == 0) e = batch_ax_order<double, 2>(N, slots, g, L, s);
+        else e = batch_ax_order<float, 2>(N, slots, g, L, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t batch_gs(int prec, int check_done, const SlotDesc *slots, const GroupDev &g, const BatchLaunch &L,

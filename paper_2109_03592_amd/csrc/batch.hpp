@@ -45,10 +45,16 @@ struct SlotDesc {
     int limit[2];       // iteration limit per precision
 };
 
+// counts[] of a group: [0] n_slots, [1] ax items, [2] gs items, [3] vec
+// items, then per order N the operator items' [first, count] at
+// kCountAxRange + 2N (operator items are sorted by order, then slot)
+constexpr int kCountAxRange = 4;
+constexpr int kCountSize = kCountAxRange + 2 * (SEM_MAX_ORDER + 1);
+
 // Device view of one group (all arrays sized for the batch capacity).
 struct GroupDev {
     const int32_t *slots;     // [n_slots] slot ids
-    const int64_t *counts;    // [0] n_slots, [1] ax items, [2] gs items, [3] vec items
+    const int64_t *counts;    // kCountSize entries, see above
     const Item *ax_items, *gs_items, *vec_items;
     const int64_t *ax_first;  // per slot id: first ax item, count
     const int64_t *ax_count;
@@ -59,13 +65,14 @@ struct GroupDev {
 };
 
 struct BatchLaunch {
-    int ax_grid;          // persistent workgroups of the operator
-    int vec_grid;         // persistent workgroups of gs / vector kernels
-    int max_slots;        // grid of the per-slot reductions
-    size_t ax_lds;        // dynamic LDS of the operator (largest epw (N+1)^3 3 elem)
+    int ax_grid;                     // persistent workgroups of each order's operator launch
+    int vec_grid;                    // persistent workgroups of gs / vector kernels
+    int max_slots;                   // grid of the per-slot reductions
+    unsigned orders;                 // bit N set: launch the order-N operator
+    int epw[SEM_MAX_ORDER + 1];      // elements per operator tile, per order
 };
 
-// phases of the batched kernels
+// phases of the batched kernels (the operator: one launch per order in L.orders)
 hipError_t batch_ax(int prec, int mode, const SlotDesc *slots, const GroupDev &g, const BatchLaunch &L,
                     hipStream_t s);
 hipError_t batch_gs(int prec, int check_done, const SlotDesc *slots, const GroupDev &g, const BatchLaunch &L,
@@ -86,6 +93,5 @@ hipError_t batch_finish(int prec, const SlotDesc *slots, const GroupDev &g, cons
 hipError_t batch_axpy(const SlotDesc *slots, const GroupDev &g, const BatchLaunch &L, hipStream_t s);
 // orders the batched operator is built for
 bool batch_order_supported(int N);
-size_t batch_ax_lds(int N, int epw, int prec);
 
 }  // namespace sem

@@ -38,8 +38,9 @@ __global__ __launch_bounds__(256) void ax_kernel(AxParams<T> a)
     const int slot = inblk ? el : a.epw - 1;  // padding lanes read a valid slot
     T *su = sm + (size_t)slot * 3 * P3;
     const T *__restrict__ D = dtable<T>(N);
+    __shared__ T sDt[lane_rows_lds<T, N>()];
     LaneRows<T, N> R;
-    R.load(D, i, j);
+    R.load(D, i, j, sDt);
     T beta = 0, alpha = 0;
     if (MODE == 2) {
         beta = (T)a.st->beta;
@@ -79,14 +80,7 @@ __global__ __launch_bounds__(256) void gs_kernel(GsPlan plan, int64_t first, con
     const unsigned lb = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + k;
     const int64_t t = first + (int64_t)lb * blockDim.x + threadIdx.x;
     if (t >= plan.n_ids) return;
-    const int32_t q0 = off[t], q1 = off[t + 1];
-    if (t < plan.n_sum) {
-        T s = T(0);
-        for (int32_t q = q0; q < q1; ++q) s += v[idx[q]];
-        for (int32_t q = q0; q < q1; ++q) v[idx[q]] = s;
-    } else {
-        for (int32_t q = q0; q < q1; ++q) v[idx[q]] = T(0);
-    }
+    gs_id<T>(t, plan.n_sum, off, idx, v);
 }
 
 // ---------------------------------------------------------------------------

@@ -35,6 +35,46 @@ __device__ inline void block_reduce_store(double (&v)[NV], double *dst, int stri
 }
 
 // ---------------------------------------------------------------------------
+// Direct-stiffness summation of one global id t of a plan (offsets `off` into
+// local indices `idx`, every id has at least one copy): ids below n_sum get
+// the sum of their copies, added in ascending local index starting from 0,
+// written back to every copy; the other ids are Dirichlet ids whose copies
+// are set to 0.  The first kGsUnroll copies (a hexahedral vertex has 8) are
+// loaded without branches -- positions past the id's last copy re-read that
+// copy -- so all index loads, then all value loads, are in flight together.
+constexpr int kGsUnroll = 8;
+
+template <typename T>
+__device__ inline void gs_id(int64_t t, int64_t n_sum, const int32_t *__restrict__ off,
+                             const int32_t *__restrict__ idx, T *__restrict__ v)
+{
+    const int32_t q0 = off[t], q1 = off[t + 1];
+    const int32_t last = q1 - 1;
+    int32_t ix[kGsUnroll];
+#pragma unroll
+    for (int c = 0; c < kGsUnroll; ++c) ix[c] = idx[min(q0 + c, last)];
+    const int32_t cnt = q1 - q0;
+    if (t < n_sum) {
+        T val[kGsUnroll];
+#pragma unroll
+        for (int c = 0; c < kGsUnroll; ++c) val[c] = v[ix[c]];
+        T s = T(0);
+#pragma unroll
+        for (int c = 0; c < kGsUnroll; ++c) s = c < cnt ? s + val[c] : s;
+        for (int32_t q = q0 + kGsUnroll; q < q1; ++q) s += v[idx[q]];
+#pragma unroll
+        for (int c = 0; c < kGsUnroll; ++c)
+            if (c < cnt) v[ix[c]] = s;
+        for (int32_t q = q0 + kGsUnroll; q < q1; ++q) v[idx[q]] = s;
+    } else {
+#pragma unroll
+        for (int c = 0; c < kGsUnroll; ++c)
+            if (c < cnt) v[ix[c]] = T(0);
+        for (int32_t q = q0 + kGsUnroll; q < q1; ++q) v[idx[q]] = T(0);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // GLL derivative matrices of every order in constant memory: the uniform
 // D[k][l] of the t-direction become scalar loads, the per-lane rows vector
 // loads.  Order N lives at offset sum_{n<N} (n+1)^2.
@@ -60,19 +100,67 @@ __device__ inline const float *dtable<float>(int N) { return c_D32 + dtable_offs
 // and of D^T, and ends the tile with a barrier before LDS is reused.
 template <typename T, int N>
 struct LaneRows {
-    T Di[N + 1], Dj[N + 1], Dti[N + 1], Dtj[N + 1];
-    __device__ inline void load(const T *__restrict__ D, int i, int j)
+    static constexpr int P = N + 1;
+    // at high order the D^T rows (and above that the D rows too) come from
+    // an LDS copy of D instead of VGPRs (keeps the FP64 kernels at two waves
+    // per SIMD)
+    static constexpr bool kDtLds = sizeof(T) == 8 ? N >= 8 : N >= 11;
+    static constexpr bool kDLds = sizeof(T) == 8 ? N >= 10 : false;
+    static constexpr int kDtLen = kDtLds ? 1 : P;
+    static constexpr int kDLen = kDLds ? 1 : P;
+    T Di_[kDLen], Dj_[kDLen], Dti_[kDtLen], Dtj_[kDtLen];
+    const T *sD;
+    int ci, cj;
+    // sDbuf: P*P values of LDS (used when kDtLds); the caller's first barrier
+    // after load() publishes it
+    __device__ inline void load(const T *__restrict__ D, int i, int j, T *sDbuf)
     {
-        constexpr int P = N + 1;
+        if constexpr (!kDLds) {
 #pragma unroll
-        for (int l = 0; l < P; ++l) {
-            Di[l] = D[i * P + l];
-            Dj[l] = D[j * P + l];
-            Dti[l] = D[l * P + i];
-            Dtj[l] = D[l * P + j];
+            for (int l = 0; l < P; ++l) {
+                Di_[l] = D[i * P + l];
+                Dj_[l] = D[j * P + l];
+            }
         }
+        if constexpr (kDtLds) {
+            for (int q = threadIdx.x; q < P * P; q += blockDim.x) sDbuf[q] = D[q];
+            sD = sDbuf;
+        } else {
+#pragma unroll
+            for (int l = 0; l < P; ++l) {
+                Dti_[l] = D[l * P + i];
+                Dtj_[l] = D[l * P + j];
+            }
+            sD = nullptr;
+        }
+        ci = i;
+        cj = j;
+    }
+    __device__ inline T di(int l) const
+    {
+        if constexpr (kDLds) return sD[ci * P + l];
+        else return Di_[l];
+    }
+    __device__ inline T dj(int l) const
+    {
+        if constexpr (kDLds) return sD[cj * P + l];
+        else return Dj_[l];
+    }
+    __device__ inline T dti(int l) const
+    {
+        if constexpr (kDtLds) return sD[l * P + ci];
+        else return Dti_[l];
+    }
+    __device__ inline T dtj(int l) const
+    {
+        if constexpr (kDtLds) return sD[l * P + cj];
+        else return Dtj_[l];
     }
 };
+
+// LDS values a kernel reserves for LaneRows::load
+template <typename T, int N>
+constexpr int lane_rows_lds() { return LaneRows<T, N>::kDtLds ? (N + 1) * (N + 1) : 1; }
 
 template <typename T, int N, int MODE>
 __device__ inline void ax_tile(const LaneRows<T, N> &R, const T *__restrict__ D, T *su, int64_t e, bool active,
@@ -117,8 +205,8 @@ __device__ inline void ax_tile(const LaneRows<T, N> &R, const T *__restrict__ D,
         T ur = 0, us = 0, ut = 0;
 #pragma unroll
         for (int l = 0; l < P; ++l) {
-            ur += R.Di[l] * su[k * P2 + j * P + l];
-            us += R.Dj[l] * su[k * P2 + l * P + i];
+            ur += R.di(l) * su[k * P2 + j * P + l];
+            us += R.dj(l) * su[k * P2 + l * P + i];
             ut += D[k * P + l] * uc[l];
         }
         T g1 = 0, g2 = 0, g3 = 0, g4 = 0, g5 = 0, g6 = 0;
@@ -142,7 +230,7 @@ __device__ inline void ax_tile(const LaneRows<T, N> &R, const T *__restrict__ D,
         T acc = 0;
 #pragma unroll
         for (int l = 0; l < P; ++l)
-            acc += R.Dti[l] * sr[k * P2 + j * P + l] + R.Dtj[l] * ss[k * P2 + l * P + i] + D[l * P + k] * wt[l];
+            acc += R.dti(l) * sr[k * P2 + j * P + l] + R.dtj(l) * ss[k * P2 + l * P + i] + D[l * P + k] * wt[l];
         if (active) out[base + k * P2] = acc;
         if (MODE != 0) dot += (double)uc[k] * (double)acc;
     }

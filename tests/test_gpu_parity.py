@@ -64,6 +64,37 @@ def test_ax_fp64_all_orders(semlib, oracle_mod, N):
     assert e2 <= 1e-12 and einf <= 1e-12, (e2, einf)
 
 
+@pytest.mark.parametrize("N", list(range(1, 13)))
+def test_ax_fp32_all_orders(semlib, oracle_mod, N):
+    """FP32 operator (geometric factors rounded to FP32) at every order against
+    the oracle applied to the FP32-rounded input: the error is FP32 rounding
+    of O(N) operations per output."""
+    nel = (3, 2, 3) if N <= 9 else (2, 2, 2)
+    print(f"case: ax fp32 N={N} nel={nel}", flush=True)
+    m, om = _box(semlib, oracle_mod, N, nel, seed=N, with_fp32=True)
+    u32 = SI.random_local(om.nloc, 200 + N).astype(np.float32)
+    w = _host(m.ax(_dev(u32, torch.float32)))
+    ref = om.ax(u32.astype(np.float64))
+    e2, einf = _relerr(w, ref)
+    assert e2 <= 2e-6 and einf <= 2e-5, (e2, einf)
+
+
+@pytest.mark.parametrize("N,nel", [(8, (2, 2, 2)), (9, (2, 2, 2)), (10, (2, 1, 2)), (12, (1, 2, 1))])
+def test_pcg_high_order(semlib, oracle_mod, N, nel):
+    """CG at the orders whose operator reads D rows from LDS."""
+    print(f"case: pcg fp64 + mixed box N={N} nel={nel}", flush=True)
+    m, om = _box(semlib, oracle_mod, N, nel, seed=30 + N, with_fp32=True)
+    x, y, z = om.coords()
+    b = om.mass(SI.sin3_forcing(x, y, z))
+    _, ro = om.pcg(b, tol=1e-10)
+    for prec in ("fp64", "mixed"):
+        xg, res = m.solve(_dev(b), tol=1e-10, precision=prec)
+        assert res.ok, (prec, res)
+        assert om.true_residual(b, _host(xg)) <= 1e-10, (prec, res)
+        if prec == "fp64":
+            assert abs(res.iterations - ro.iterations) <= max(3, 0.05 * ro.iterations), (res, ro)
+
+
 def test_ax_dot_and_fp32(semlib, oracle_mod):
     print("case: ax dot + fp32, box 4x4x4 N=7", flush=True)
     m, om = _box(semlib, oracle_mod, 7, (4, 4, 4), with_fp32=True)
