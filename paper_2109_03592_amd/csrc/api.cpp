@@ -264,7 +264,7 @@ static void enqueue_iterations(sem_mesh *m, int k, hipStream_t s, Profiler *prof
         SEM_HIP(launch_reduce_sigma(m->partials, axb, st, s));
         SEM_HIP(launch_pcg_update<T>(nL, st, Prec<T>::r(m), Prec<T>::w(m), Prec<T>::inv(m), m->mult, m->partials,
                                      s));
-        SEM_HIP(launch_reduce_rho(m->partials, vec_blocks(nL), st, s));
+        SEM_HIP(launch_reduce_rho(m->partials, update_blocks(nL), st, s));
         if (prof) prof->mark(s);
     }
     if (prof) prof->flush(s);
@@ -547,7 +547,8 @@ sem_status sem_setup(const sem_mesh_desc *desc, void *stream, sem_mesh **out)
             m->gs_off = dalloc<int32_t>(m, h.gs_off.size());
             m->gs_idx = dalloc<int32_t>(m, h.gs_idx.size());
             m->ax_grid_cap = persistent_grid_cap();
-            const int64_t np = std::max<int64_t>(std::max<int64_t>(m->ax_grid_cap, 65536), 2 * (int64_t)vec_blocks(nL)) + 64;
+            const int64_t np = std::max<int64_t>(std::max<int64_t>(m->ax_grid_cap, 65536),
+                                                2 * (int64_t)std::max(vec_blocks(nL), update_blocks(nL))) + 64;
             m->partials = dalloc<double>(m, np);
             m->n_partials = np;
             m->state = dalloc<PcgState>(m, 2);

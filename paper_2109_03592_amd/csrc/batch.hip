@@ -125,19 +125,33 @@ __global__ __launch_bounds__(kBatchBlock) void batch_update_kernel(const SlotDes
         const SlotDesc sd = slots[item.slot];
         double rr = 0.0, rz = 0.0;
         if (!uniform_int(sd.st[prec].done)) {
+            constexpr int U = kVecChunk / kBatchBlock;
             const T alpha = (T)sd.st[prec].alpha;
             T *r = static_cast<T *>(sd.r[prec]);
             const T *w = static_cast<const T *>(sd.w[prec]);
             const T *iv = static_cast<const T *>(sd.inv[prec]);
             const int64_t q0 = (int64_t)item.local * kVecChunk;
-            for (int u = 0; u < kVecChunk / kBatchBlock; ++u) {
+            const int64_t qlast = min(q0 + kVecChunk, sd.nL) - 1;
+            // all loads of the chunk in flight at once (past the end: re-read the last entry)
+            T rv[U], wv[U], ivv[U];
+            uint8_t mv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t q = min(q0 + u * kBatchBlock + threadIdx.x, qlast);
+                rv[u] = r[q];
+                wv[u] = w[q];
+                ivv[u] = iv[q];
+                mv[u] = sd.mult[q];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
                 const int64_t q = q0 + u * kBatchBlock + threadIdx.x;
-                if (q >= sd.nL) break;
-                const T rq = r[q] - alpha * w[q];
+                if (q > qlast) break;
+                const T rq = rv[u] - alpha * wv[u];
                 r[q] = rq;
-                const double rd = (double)rq, im = inv_mult_b(sd.mult[q]);
+                const double rd = (double)rq, im = inv_mult_b(mv[u]);
                 rr += rd * rd * im;
-                rz += rd * (double)(iv[q] * rq) * im;
+                rz += rd * (double)(ivv[u] * rq) * im;
             }
         }
         double v[2] = {rr, rz};

@@ -162,7 +162,8 @@ __global__ __launch_bounds__(256) void pcg_init_kernel(int64_t n, const T *__res
 // CG update after the gather-scatter: r -= alpha w; partials of <r,r> and
 // <r, invdiag r>.  (x += alpha p is applied by the next operator launch, or
 // by pcg_finish_kernel at the end of the run.)  Two consecutive entries per
-// lane and step, four steps in flight.
+// lane and step over a wide grid (more waves in flight beat more steps in
+// flight per lane here).
 template <typename T>
 struct Pair;
 template <>
@@ -182,7 +183,7 @@ __global__ __launch_bounds__(256) void pcg_update_kernel(int64_t n, const PcgSta
                                                          double *__restrict__ partial)
 {
     using V = typename Pair<T>::type;
-    constexpr int U = 4;
+    constexpr int U = 1;
     if (st->done) return;
     const T alpha = (T)st->alpha;
     double rr = 0.0, rz = 0.0;
@@ -388,6 +389,7 @@ template hipError_t launch_gs<float>(const GsPlan &, const int32_t *, const int3
                                      const PcgState *, hipStream_t);
 
 int vec_blocks(int64_t n) { return grid_for(n, 256, 8192); }
+int update_blocks(int64_t n) { return grid_for((n + 1) / 2, 256, 65536); }
 
 hipError_t upload_dtables(const double *d64, const float *d32, hipStream_t s)
 {
@@ -460,7 +462,7 @@ template <typename T>
 hipError_t launch_pcg_update(int64_t n, const PcgState *st, T *r, const T *w, const T *inv, const uint8_t *mult,
                              double *partial, hipStream_t s)
 {
-    const int blocks = vec_blocks(n);
+    const int blocks = update_blocks(n);
     hipLaunchKernelGGL((pcg_update_kernel<T>), dim3(blocks), dim3(256), 0, s, n, st, r, w, inv, mult, partial);
     return hipGetLastError();
 }

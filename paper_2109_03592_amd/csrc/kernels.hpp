@@ -42,6 +42,7 @@ size_t ax_lds_bytes(int N, int epw, size_t elem);
 int64_t ax_grid(int64_t E, int epw, int cap);
 hipError_t upload_dtables(const double *d64, const float *d32, hipStream_t s);
 int vec_blocks(int64_t n);
+int update_blocks(int64_t n);  // workgroups of the PCG update (one partial pair each)
 
 template <typename T>
 hipError_t launch_ax(int N, int mode, const AxParams<T> &a, hipStream_t s);

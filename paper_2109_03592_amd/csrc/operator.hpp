@@ -39,38 +39,46 @@ __device__ inline void block_reduce_store(double (&v)[NV], double *dst, int stri
 // local indices `idx`, every id has at least one copy): ids below n_sum get
 // the sum of their copies, added in ascending local index starting from 0,
 // written back to every copy; the other ids are Dirichlet ids whose copies
-// are set to 0.  The first kGsUnroll copies (a hexahedral vertex has 8) are
-// loaded without branches -- positions past the id's last copy re-read that
-// copy -- so all index loads, then all value loads, are in flight together.
-constexpr int kGsUnroll = 8;
-
+// are set to 0.  Copies are loaded four at a time without branches --
+// positions past the id's last copy re-read that copy -- so the index loads,
+// then the value loads, of a face id (2 copies) or an edge id (4) are in
+// flight together; a vertex id (8) takes a second group.
 template <typename T>
 __device__ inline void gs_id(int64_t t, int64_t n_sum, const int32_t *__restrict__ off,
                              const int32_t *__restrict__ idx, T *__restrict__ v)
 {
     const int32_t q0 = off[t], q1 = off[t + 1];
-    const int32_t last = q1 - 1;
-    int32_t ix[kGsUnroll];
+    const int32_t last = q1 - 1, cnt = q1 - q0;
+    int32_t ix[8];
 #pragma unroll
-    for (int c = 0; c < kGsUnroll; ++c) ix[c] = idx[min(q0 + c, last)];
-    const int32_t cnt = q1 - q0;
+    for (int c = 0; c < 4; ++c) ix[c] = idx[min(q0 + c, last)];
+    if (cnt > 4) {
+#pragma unroll
+        for (int c = 4; c < 8; ++c) ix[c] = idx[min(q0 + c, last)];
+    }
     if (t < n_sum) {
-        T val[kGsUnroll];
+        T val[8];
 #pragma unroll
-        for (int c = 0; c < kGsUnroll; ++c) val[c] = v[ix[c]];
+        for (int c = 0; c < 4; ++c) val[c] = v[ix[c]];
         T s = T(0);
 #pragma unroll
-        for (int c = 0; c < kGsUnroll; ++c) s = c < cnt ? s + val[c] : s;
-        for (int32_t q = q0 + kGsUnroll; q < q1; ++q) s += v[idx[q]];
+        for (int c = 0; c < 4; ++c) s = c < cnt ? s + val[c] : s;
+        if (cnt > 4) {
 #pragma unroll
-        for (int c = 0; c < kGsUnroll; ++c)
+            for (int c = 4; c < 8; ++c) val[c] = v[ix[c]];
+#pragma unroll
+            for (int c = 4; c < 8; ++c) s = c < cnt ? s + val[c] : s;
+            for (int32_t q = q0 + 8; q < q1; ++q) s += v[idx[q]];
+        }
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
             if (c < cnt) v[ix[c]] = s;
-        for (int32_t q = q0 + kGsUnroll; q < q1; ++q) v[idx[q]] = s;
+        for (int32_t q = q0 + 8; q < q1; ++q) v[idx[q]] = s;
     } else {
 #pragma unroll
-        for (int c = 0; c < kGsUnroll; ++c)
+        for (int c = 0; c < 8; ++c)
             if (c < cnt) v[ix[c]] = T(0);
-        for (int32_t q = q0 + kGsUnroll; q < q1; ++q) v[idx[q]] = T(0);
+        for (int32_t q = q0 + 8; q < q1; ++q) v[idx[q]] = T(0);
     }
 }
 
@@ -162,7 +170,45 @@ struct LaneRows {
 template <typename T, int N>
 constexpr int lane_rows_lds() { return LaneRows<T, N>::kDtLds ? (N + 1) * (N + 1) : 1; }
 
-template <typename T, int N, int MODE>
+// Position of point (i,j,k) inside an element's block of (N+1)^3 vector
+// entries.  LAYOUT 0 (element order): i + (N+1) j + (N+1)^2 k.  LAYOUT 1
+// (boundary first): the face k=0, the face k=N, then per interior plane the
+// ring of (i,j) with i or j in {0,N} -- together every point on the element
+// boundary -- and after them the interior points in element order.  The
+// gather-scatter only touches element-boundary points, which the second
+// layout keeps in the first 1 - ((N-1)/(N+1))^3 of each block.
+template <int N, int LAYOUT>
+struct ColumnIndex {
+    static constexpr int P = N + 1, P2 = P * P, R = 4 * N, I2 = (N - 1) * (N - 1);
+    static constexpr int NB = 2 * P2 + (N - 1) * R;  // boundary points per element
+    int ij, base, stride;
+    __device__ inline ColumnIndex(int i, int j)
+    {
+        ij = i + P * j;
+        if (LAYOUT == 1) {
+            const bool ring = i == 0 || i == N || j == 0 || j == N;
+            int rpos;
+            if (j == 0) rpos = i;
+            else if (j == N) rpos = P + 2 * (N - 1) + i;
+            else rpos = P + 2 * (j - 1) + (i == N ? 1 : 0);
+            const int ipos = (j - 1) * (N - 1) + (i - 1);
+            base = ring ? 2 * P2 - R + rpos : NB - I2 + ipos;
+            stride = ring ? R : I2;
+        } else {
+            base = ij;
+            stride = P2;
+        }
+    }
+    __device__ inline int off(int k) const
+    {
+        if (LAYOUT == 0) return ij + k * P2;
+        if (k == 0) return ij;
+        if (k == N) return P2 + ij;
+        return base + k * stride;
+    }
+};
+
+template <typename T, int N, int MODE, int LAYOUT = 0>
 __device__ inline void ax_tile(const LaneRows<T, N> &R, const T *__restrict__ D, T *su, int64_t e, bool active,
                                bool inblk, int i, int j, const T *__restrict__ G, const T *__restrict__ in,
                                T *__restrict__ out, const T *__restrict__ invdiag, T *__restrict__ p, T beta,
@@ -172,14 +218,15 @@ __device__ inline void ax_tile(const LaneRows<T, N> &R, const T *__restrict__ D,
     T *sr = su + P3;
     T *ss = sr + P3;
     const int ij = i + P * j;
-    const int64_t base = (active ? e : 0) * P3 + ij;
+    const ColumnIndex<N, LAYOUT> ci(i, j);
+    const int64_t eb = (active ? e : 0) * P3;
     T uc[P];
     if (MODE == 2) {
 #pragma unroll
         for (int k = 0; k < P; ++k) {
             T v = 0;
             if (active) {
-                const int64_t o = base + k * P2;
+                const int64_t o = eb + ci.off(k);
                 const T pold = p[o];
                 // the previous iteration's x step, deferred to here where p is read anyway
                 x[o] = x[o] + alpha * pold;
@@ -190,7 +237,7 @@ __device__ inline void ax_tile(const LaneRows<T, N> &R, const T *__restrict__ D,
         }
     } else {
 #pragma unroll
-        for (int k = 0; k < P; ++k) uc[k] = active ? in[base + k * P2] : T(0);
+        for (int k = 0; k < P; ++k) uc[k] = active ? in[eb + ci.off(k)] : T(0);
     }
     if (inblk) {
 #pragma unroll
@@ -231,7 +278,7 @@ __device__ inline void ax_tile(const LaneRows<T, N> &R, const T *__restrict__ D,
 #pragma unroll
         for (int l = 0; l < P; ++l)
             acc += R.dti(l) * sr[k * P2 + j * P + l] + R.dtj(l) * ss[k * P2 + l * P + i] + D[l * P + k] * wt[l];
-        if (active) out[base + k * P2] = acc;
+        if (active) out[eb + ci.off(k)] = acc;
         if (MODE != 0) dot += (double)uc[k] * (double)acc;
     }
     __syncthreads();  // the LDS slot is rewritten by the next tile
