@@ -183,7 +183,9 @@ typedef struct {
     double tol;          /* stop when ||b - A x|| <= tol ||b|| (unique-dof 2-norm) */
     int max_iter;        /* limit on PCG iterations (inner ones for mixed)         */
     int precision;       /* SEM_PREC_FP64 or SEM_PREC_MIXED                        */
-    double inner_tol;    /* mixed: relative tolerance of each FP32 inner solve     */
+    double inner_tol;    /* mixed: relative tolerance of each FP32 inner solve
+                            (loosened to 0.5 tol/rel when the FP64 relative
+                            residual rel needs less reduction, at most 0.5)     */
     int inner_max_iter;  /* mixed: limit per inner solve                           */
     int poll_every;      /* iterations between host convergence checks            */
     int use_graph;       /* replay poll_every iterations as one hipGraph           */

@@ -441,6 +441,14 @@ static sem_status solve_fp64(sem_mesh *m, const double *b, double *x, const sem_
     return status;
 }
 
+// Relative tolerance of the next FP32 inner solve when the FP64 residual is
+// rel: inner_tol, but never tighter than the reduction still needed (with a
+// factor 2 of margin) -- the last refinement step then stops early.
+double inner_tolerance(const sem_solve_opts &o, double rel)
+{
+    return std::min(0.5, std::max(o.inner_tol, 0.5 * o.tol / rel));
+}
+
 static sem_status solve_mixed(sem_mesh *m, const double *b, double *x, const sem_solve_opts &o, sem_solve_stats &out,
                               hipStream_t s)
 {
@@ -483,7 +491,8 @@ static sem_status solve_mixed(sem_mesh *m, const double *b, double *x, const sem
         SEM_HIP(launch_to_fp32_scaled(nL, m->r64, m->scal + 1, m->r32, s));
         SEM_HIP(hipMemsetAsync(m->x32, 0, sizeof(float) * nL, s));
         const int limit = std::min(inner_max, o.max_iter - total);
-        const PcgState hs = cg_loop<float>(m, o.inner_tol * o.inner_tol, limit, poll, o.use_graph != 0, s, pp);
+        const double eta = inner_tolerance(o, rel);
+        const PcgState hs = cg_loop<float>(m, eta * eta, limit, poll, o.use_graph != 0, s, pp);
         total += hs.iters;
         outer++;
         if (hs.iters == 0 && hs.done == 2) {

@@ -25,6 +25,7 @@ namespace sem {
 hipError_t upload_batch_dtables(const double *d64, const float *d32, hipStream_t s);
 void ensure_dtables_all(hipStream_t s);
 int persistent_grid_cap_public();
+double inner_tolerance(const sem_solve_opts &o, double rel);
 
 enum Phase { PH_FREE = 0, PH_START, PH_CG64, PH_CHECK, PH_RESID, PH_CG32, PH_DONE };
 
@@ -431,7 +432,8 @@ static void step_batch(sem_batch *B, int k, bool use_graph, hipStream_t s)
         for (int id : to32) {
             HostSlot &h = B->slots[id];
             SlotDesc &d = B->h_desc[id];
-            d.stop2[1] = h.opts.inner_tol * h.opts.inner_tol;
+            const double eta = inner_tolerance(h.opts, h.rel);
+            d.stop2[1] = eta * eta;
             const int inner_max = h.opts.inner_max_iter > 0 ? h.opts.inner_max_iter : h.opts.max_iter;
             d.limit[1] = std::min(inner_max, h.opts.max_iter - h.iters);
             upload_desc(B, id, s);
