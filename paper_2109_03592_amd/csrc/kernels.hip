@@ -234,12 +234,31 @@ template <int NV>
 __device__ inline void sum_partials(const double *__restrict__ partial, int64_t n, double (&out)[NV])
 {
     __shared__ double red[NV][1024];
-    double s[NV];
+    // eight partial sums per thread (eight loads in flight), combined in order
+    constexpr int K = 8;
+    double s[NV], acc[K][NV];
 #pragma unroll
-    for (int q = 0; q < NV; ++q) s[q] = 0.0;
-    for (int64_t b = threadIdx.x; b < n; b += blockDim.x)
+    for (int c = 0; c < K; ++c)
 #pragma unroll
-        for (int q = 0; q < NV; ++q) s[q] += partial[b * NV + q];
+        for (int q = 0; q < NV; ++q) acc[c][q] = 0.0;
+    const int64_t B = blockDim.x;
+    int64_t b = threadIdx.x;
+    for (; b + (K - 1) * B < n; b += K * B)
+#pragma unroll
+        for (int c = 0; c < K; ++c)
+#pragma unroll
+            for (int q = 0; q < NV; ++q) acc[c][q] += partial[(b + c * B) * NV + q];
+#pragma unroll
+    for (int c = 0; c < K; ++c)
+        if (b + c * B < n)
+#pragma unroll
+            for (int q = 0; q < NV; ++q) acc[c][q] += partial[(b + c * B) * NV + q];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        s[q] = 0.0;
+#pragma unroll
+        for (int c = 0; c < K; ++c) s[q] += acc[c][q];
+    }
 #pragma unroll
     for (int q = 0; q < NV; ++q) red[q][threadIdx.x] = s[q];
     __syncthreads();
