@@ -218,7 +218,7 @@ def main():
     ap.add_argument("--no-axgs", action="store_true", help="skip the stand-alone Ax+gs timing")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-mesh solves")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
-    ap.add_argument("--serve-rates", default="100,1000")
+    ap.add_argument("--serve-rates", default="10,100,1000")
     ap.add_argument("--serve-duration", type=float, default=5.0)
     ap.add_argument("--serve-drain", type=float, default=20.0)
     ap.add_argument("--copy-calibration", action="store_true",
