@@ -139,7 +139,8 @@ sem_status sem_host_setup(const sem_mesh_desc *desc, sem_mesh_info *info, int64_
 /* Replace the geometric factors and lumped mass of a mesh with caller-supplied
  * ones (host arrays in the sem_export_geom layout: G[6][n_local], B[n_local]),
  * e.g. factors computed by another code for the same element layout.  The
- * Jacobi diagonal and the FP32 copies are rebuilt; graphs stay valid.
+ * Jacobi diagonal and the FP32 copies are rebuilt; graphs stay valid.  A
+ * Helmholtz form set by sem_set_helmholtz is dropped (its h2 B used the old B).
  * Errors: SEM_EINVAL (null pointers, non-positive assembled diagonal). */
 sem_status sem_load_geometry(sem_mesh *mesh, const double *G, const double *B, void *stream);
 
@@ -151,6 +152,18 @@ sem_status sem_load_geometry(sem_mesh *mesh, const double *G, const double *B, v
  * sem_get_operator_config reads it. */
 sem_status sem_set_operator_config(sem_mesh *mesh, int epw, int grid);
 sem_status sem_get_operator_config(const sem_mesh *mesh, int *epw, int *grid);
+
+/* Helmholtz form of the operator (Eq. 4 with the variable coefficient h1 of
+ * Algorithm 1): afterwards sem_ax, sem_axgs and sem_pcg_solve apply
+ *   A_L u = sum_q h1_q (grad phi)^T G_q (grad u) + h2 B u
+ * i.e. the three products of the combine step are scaled by h1 at the point
+ * and h2 B u is added, and the Jacobi preconditioner is rebuilt from that
+ * operator's assembled diagonal.  h1, h2: device FP64 E-vectors (n_local) or
+ * NULL (h1 = 1, h2 = 0); both NULL restores the Poisson operator.  The values
+ * are copied (and FP32 copies made with SEM_WITH_FP32).  For CG the caller
+ * keeps h1 > 0 and h2 >= 0.  Batched solves (sem_batch_*) take Poisson meshes
+ * only.  Synchronises `stream`.  Errors: SEM_EINVAL, SEM_ENOMEM, SEM_EHIP. */
+sem_status sem_set_helmholtz(sem_mesh *mesh, const double *h1, const double *h2, void *stream);
 
 /* Local operator, Algorithm 1: w = A_L u element by element (no
  * gather-scatter).  u, w: device E-vectors of `dtype` (SEM_FP64 or SEM_FP32;

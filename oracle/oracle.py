@@ -296,8 +296,8 @@ class OracleMesh:
         """Unique-dof inner product sum_local a b / mult."""
         return float(np.sum(a * b / self.local_mult()))
 
-    def true_residual(self, b, x):
-        r = b - self.apply(x)
+    def true_residual(self, b, x, h1=None, h2=None):
+        r = b - self.apply(x, h1, h2)
         return np.sqrt(self.dot(r, r)) / np.sqrt(self.dot(b, b))
 
 

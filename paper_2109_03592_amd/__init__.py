@@ -153,6 +153,16 @@ class Mesh:
         L.check(self._lib.sem_get_operator_config(self._h, C.byref(e), C.byref(g)), "sem_get_operator_config")
         return e.value, g.value
 
+    def set_helmholtz(self, h1: Optional[torch.Tensor] = None, h2: Optional[torch.Tensor] = None, stream=None):
+        """Helmholtz form h1 (grad, grad) + h2 B of the operator (None: h1 = 1,
+        h2 = 0; both None restores Poisson).  h1, h2: FP64 E-vectors."""
+        for t, name in ((h1, "h1"), (h2, "h2")):
+            if t is not None:
+                self._vec(t, name, torch.float64)
+        L.check(self._lib.sem_set_helmholtz(self._h, None if h1 is None else h1.data_ptr(),
+                                            None if h2 is None else h2.data_ptr(), _stream_handle(stream)),
+                "sem_set_helmholtz")
+
     # -- operators -----------------------------------------------------------
     def ax(self, u: torch.Tensor, w: Optional[torch.Tensor] = None, dot: bool = False, stream=None):
         """w = A_L u (no gather-scatter); with dot=True also returns sum u.w (device scalar)."""

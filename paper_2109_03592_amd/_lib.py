@@ -66,6 +66,7 @@ SIGNATURES = {
     "sem_load_geometry": (_i, [_vp, _vp, _vp, _vp]),
     "sem_set_operator_config": (_i, [_vp, _i, _i]),
     "sem_get_operator_config": (_i, [_vp, C.POINTER(_i), C.POINTER(_i)]),
+    "sem_set_helmholtz": (_i, [_vp, _vp, _vp, _vp]),
     "sem_ax": (_i, [_vp, _i, _vp, _vp, _vp, _vp]),
     "sem_gs": (_i, [_vp, _i, _vp, _vp]),
     "sem_axgs": (_i, [_vp, _i, _vp, _vp, _vp]),

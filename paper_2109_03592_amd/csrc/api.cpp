@@ -173,6 +173,8 @@ struct Prec<double> {
     static double *p(sem_mesh *m) { return m->p64; }
     static double *w(sem_mesh *m) { return m->w64; }
     static PcgState *st(sem_mesh *m) { return m->state; }
+    static const double *h1(sem_mesh *m) { return m->helm ? m->h1_64 : nullptr; }
+    static const double *h2b(sem_mesh *m) { return m->helm ? m->h2b64 : nullptr; }
 };
 template <>
 struct Prec<float> {
@@ -183,6 +185,8 @@ struct Prec<float> {
     static float *p(sem_mesh *m) { return m->p32; }
     static float *w(sem_mesh *m) { return m->w32; }
     static PcgState *st(sem_mesh *m) { return m->state + 1; }
+    static const float *h1(sem_mesh *m) { return m->helm ? m->h1_32 : nullptr; }
+    static const float *h2b(sem_mesh *m) { return m->helm ? m->h2b32 : nullptr; }
 };
 
 template <typename T>
@@ -196,6 +200,8 @@ static void enqueue_ax(sem_mesh *m, int mode, const T *in, T *out, hipStream_t s
     a.in = in;
     a.out = out;
     a.partial = m->partials;
+    a.h1 = Prec<T>::h1(m);
+    a.h2b = Prec<T>::h2b(m);
     if (mode == 2) {
         a.invdiag = Prec<T>::inv(m);
         a.p = Prec<T>::p(m);
@@ -755,6 +761,15 @@ sem_status sem_load_geometry(sem_mesh *m, const double *G, const double *B, void
         }
         std::vector<double>().swap(h.G);
         std::vector<double>().swap(h.invdiag);
+        if (m->helm) {
+            // h2*B was formed with the old B: back to the Poisson form
+            for (int q = 0; q < 2; ++q)
+                if (m->graph[q]) {
+                    SEM_HIP(hipGraphExecDestroy(m->graph[q]));
+                    m->graph[q] = nullptr;
+                }
+            m->helm = 0;
+        }
         return SEM_OK;
     });
 }
@@ -780,6 +795,58 @@ sem_status sem_get_operator_config(const sem_mesh *m, int *epw, int *grid)
         if (!m) fail(SEM_EINVAL, "sem_get_operator_config: null mesh");
         if (epw) *epw = m->ax_epw;
         if (grid) *grid = m->ax_grid_cap;
+        return SEM_OK;
+    });
+}
+
+sem_status sem_set_helmholtz(sem_mesh *m, const double *h1, const double *h2, void *stream)
+{
+    return guarded([&]() -> sem_status {
+        if (!m) fail(SEM_EINVAL, "sem_set_helmholtz: null mesh");
+        hipStream_t s = (hipStream_t)stream;
+        const int64_t nL = m->h.nL;
+        // cached CG graphs launch the operator of the current form
+        for (int q = 0; q < 2; ++q)
+            if (m->graph[q]) {
+                SEM_HIP(hipStreamSynchronize(s));
+                SEM_HIP(hipGraphExecDestroy(m->graph[q]));
+                m->graph[q] = nullptr;
+            }
+        const bool helm = h1 || h2;
+        if (helm && !m->h1_64) {
+            m->h1_64 = dalloc<double>(m, nL);
+            m->h2b64 = dalloc<double>(m, nL);
+            if (m->with_fp32) {
+                m->h1_32 = dalloc<float>(m, nL);
+                m->h2b32 = dalloc<float>(m, nL);
+            }
+        }
+        if (helm) {
+            if (h1) SEM_HIP(hipMemcpyAsync(m->h1_64, h1, sizeof(double) * nL, hipMemcpyDeviceToDevice, s));
+            else SEM_HIP(launch_fill(nL, 1.0, m->h1_64, s));
+            if (h2) SEM_HIP(launch_scale(nL, h2, m->B64, m->h2b64, s));
+            else SEM_HIP(launch_fill(nL, 0.0, m->h2b64, s));
+            if (m->with_fp32) {
+                SEM_HIP(launch_fp64_to_fp32(nL, m->h1_64, m->h1_32, s));
+                SEM_HIP(launch_fp64_to_fp32(nL, m->h2b64, m->h2b32, s));
+            }
+        }
+        // Jacobi: assembled diagonal of the new operator, inverted (0 on masked nodes)
+        double *diag = nullptr;
+        SEM_HIP(hipMalloc(&diag, sizeof(double) * std::max<int64_t>(nL, 1)));
+        try {
+            SEM_HIP(launch_helm_diag(m->h.N, m->h.E, m->G64, helm ? m->h1_64 : nullptr, helm ? m->h2b64 : nullptr,
+                                     diag, s));
+            SEM_HIP(launch_gs<double>(m->gsplan, m->gs_off, m->gs_idx, diag, false, nullptr, s));
+            SEM_HIP(launch_invert_positive(nL, diag, m->inv64, s));
+            if (m->with_fp32) SEM_HIP(launch_fp64_to_fp32(nL, m->inv64, m->inv32, s));
+            SEM_HIP(hipStreamSynchronize(s));
+        } catch (...) {
+            hipFree(diag);
+            throw;
+        }
+        SEM_HIP(hipFree(diag));
+        m->helm = helm ? 1 : 0;
         return SEM_OK;
     });
 }

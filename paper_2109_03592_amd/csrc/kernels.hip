@@ -21,7 +21,7 @@ namespace sem {
 
 // Single mesh, persistent: each workgroup walks element tiles blockIdx.x,
 // blockIdx.x + gridDim.x, ... and stores its dot partial (modes 1, 2).
-template <typename T, int N, int MODE>
+template <typename T, int N, int MODE, bool HELM>
 __global__ __launch_bounds__(256) void ax_kernel(AxParams<T> a)
 {
     constexpr int P = N + 1, P2 = P * P, P3 = P2 * P;
@@ -52,8 +52,8 @@ __global__ __launch_bounds__(256) void ax_kernel(AxParams<T> a)
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t e = tile * a.epw + el;
         const bool active = inblk && e < a.E;
-        ax_tile<T, N, MODE>(R, D, su, e, active, inblk, i, j, a.G, a.in, a.out, a.invdiag, a.p, beta, a.x, alpha,
-                            dot);
+        ax_tile<T, N, MODE, 0, HELM>(R, D, su, e, active, inblk, i, j, a.G, a.in, a.out, a.invdiag, a.p, beta, a.x,
+                                     alpha, dot, a.h1, a.h2b);
     }
     if (MODE != 0) {
         double v[1] = {dot};
@@ -334,6 +334,52 @@ __global__ __launch_bounds__(1024) void reduce_init_kernel(const double *__restr
 }
 
 // ---------------------------------------------------------------------------
+// Diagonal of the local Helmholtz operator, one lane per local point
+// (i,j,k) of element e.  The basis function of the point has an r-derivative
+// only on its r-line, so the diagonal is the h1*g1-weighted sum of D[l][i]^2
+// along that line, likewise for s and t, plus the cross terms at the point
+// itself (2 h1 (g4 D_ii D_jj + g5 D_ii D_kk + g6 D_jj D_kk)) and h2*B.
+__global__ __launch_bounds__(256) void helm_diag_kernel(int N, int64_t E, const double *__restrict__ G,
+                                                        const double *__restrict__ h1,
+                                                        const double *__restrict__ h2b, double *__restrict__ diag)
+{
+    const int P = N + 1, P2 = P * P, P3 = P2 * P;
+    const double *D = c_D64 + dtable_offset(N);
+    const int64_t n = E * P3;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t e = q / P3;
+        const int pt = (int)(q - e * P3);
+        const int k = pt / P2, j = (pt / P) % P, i = pt % P;
+        const double *Ge = G + e * 6 * P3;
+        const double *he = h1 ? h1 + e * P3 : nullptr;
+        double d = 0.0;
+        for (int l = 0; l < P; ++l) {
+            const int pr = l + P * j + P2 * k, ps = i + P * l + P2 * k, pt3 = i + P * j + P2 * l;
+            const double hr = he ? he[pr] : 1.0, hs = he ? he[ps] : 1.0, ht = he ? he[pt3] : 1.0;
+            const double dr = D[l * P + i], ds = D[l * P + j], dt = D[l * P + k];
+            d += hr * Ge[0 * P3 + pr] * dr * dr + hs * Ge[1 * P3 + ps] * ds * ds + ht * Ge[2 * P3 + pt3] * dt * dt;
+        }
+        const double h = he ? he[pt] : 1.0;
+        const double dii = D[i * P + i], djj = D[j * P + j], dkk = D[k * P + k];
+        d += 2.0 * h * (Ge[3 * P3 + pt] * dii * djj + Ge[4 * P3 + pt] * dii * dkk + Ge[5 * P3 + pt] * djj * dkk);
+        if (h2b) d += h2b[q];
+        diag[q] = d;
+    }
+}
+
+__global__ void invert_positive_kernel(int64_t n, const double *__restrict__ v, double *__restrict__ out)
+{
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
+        out[q] = v[q] > 0.0 ? 1.0 / v[q] : 0.0;
+}
+
+__global__ void fill_kernel(int64_t n, double value, double *__restrict__ out)
+{
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
+        out[q] = value;
+}
+
+// ---------------------------------------------------------------------------
 // host launchers
 static inline int grid_for(int64_t n, int block, int cap)
 {
@@ -362,7 +408,7 @@ int64_t ax_grid(int64_t E, int epw, int cap)
     return tiles < cap ? tiles : cap;
 }
 
-template <typename T, int MODE>
+template <typename T, int MODE, bool HELM>
 static hipError_t launch_ax_mode(int N, const AxParams<T> &a, hipStream_t s)
 {
     const int threads = ax_block_threads(N, a.epw);
@@ -371,7 +417,7 @@ static hipError_t launch_ax_mode(int N, const AxParams<T> &a, hipStream_t s)
     if (threads > 256 || blocks < 1 || blocks > INT32_MAX) return hipErrorInvalidConfiguration;
     switch (N) {
 #define SEM_AX_CASE(n) \
-    case n: hipLaunchKernelGGL((ax_kernel<T, n, MODE>), dim3((unsigned)blocks), dim3(threads), lds, s, a); break;
+    case n: hipLaunchKernelGGL((ax_kernel<T, n, MODE, HELM>), dim3((unsigned)blocks), dim3(threads), lds, s, a); break;
         SEM_AX_CASE(1) SEM_AX_CASE(2) SEM_AX_CASE(3) SEM_AX_CASE(4) SEM_AX_CASE(5) SEM_AX_CASE(6)
         SEM_AX_CASE(7) SEM_AX_CASE(8) SEM_AX_CASE(9) SEM_AX_CASE(10) SEM_AX_CASE(11) SEM_AX_CASE(12)
 #undef SEM_AX_CASE
@@ -383,9 +429,14 @@ static hipError_t launch_ax_mode(int N, const AxParams<T> &a, hipStream_t s)
 template <typename T>
 hipError_t launch_ax(int N, int mode, const AxParams<T> &a, hipStream_t s)
 {
-    if (mode == 0) return launch_ax_mode<T, 0>(N, a, s);
-    if (mode == 1) return launch_ax_mode<T, 1>(N, a, s);
-    return launch_ax_mode<T, 2>(N, a, s);
+    if (a.h1) {
+        if (mode == 0) return launch_ax_mode<T, 0, true>(N, a, s);
+        if (mode == 1) return launch_ax_mode<T, 1, true>(N, a, s);
+        return launch_ax_mode<T, 2, true>(N, a, s);
+    }
+    if (mode == 0) return launch_ax_mode<T, 0, false>(N, a, s);
+    if (mode == 1) return launch_ax_mode<T, 1, false>(N, a, s);
+    return launch_ax_mode<T, 2, false>(N, a, s);
 }
 template hipError_t launch_ax<double>(int, int, const AxParams<double> &, hipStream_t);
 template hipError_t launch_ax<float>(int, int, const AxParams<float> &, hipStream_t);
@@ -408,6 +459,25 @@ template hipError_t launch_gs<float>(const GsPlan &, const int32_t *, const int3
                                      const PcgState *, hipStream_t);
 
 int vec_blocks(int64_t n) { return grid_for(n, 256, 8192); }
+
+hipError_t launch_helm_diag(int N, int64_t E, const double *G, const double *h1, const double *h2b, double *diag,
+                            hipStream_t s)
+{
+    if (N < 1 || N > SEM_MAX_ORDER) return hipErrorInvalidValue;
+    const int64_t n = E * (int64_t)(N + 1) * (N + 1) * (N + 1);
+    hipLaunchKernelGGL(helm_diag_kernel, dim3(vec_blocks(n)), dim3(256), 0, s, N, E, G, h1, h2b, diag);
+    return hipGetLastError();
+}
+hipError_t launch_invert_positive(int64_t n, const double *v, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(invert_positive_kernel, dim3(vec_blocks(n)), dim3(256), 0, s, n, v, out);
+    return hipGetLastError();
+}
+hipError_t launch_fill(int64_t n, double value, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(fill_kernel, dim3(vec_blocks(n)), dim3(256), 0, s, n, value, out);
+    return hipGetLastError();
+}
 int update_blocks(int64_t n) { return grid_for((n + 1) / 2, 256, 65536); }
 
 hipError_t upload_dtables(const double *d64, const float *d32, hipStream_t s)

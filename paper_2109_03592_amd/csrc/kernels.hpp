@@ -35,6 +35,8 @@ struct AxParams {
     T *p;                  // mode 2: search direction, updated in place
     T *x;                  // mode 2: iterate, receives the previous step alpha*p
     const PcgState *st;    // mode 2: alpha, beta and the done flag
+    const T *h1;           // Helmholtz: h1 per local point (nullptr: Poisson)
+    const T *h2b;          // Helmholtz: h2*B per local point (with h1)
 };
 
 int ax_block_threads(int N, int epw);
@@ -69,5 +71,11 @@ hipError_t launch_pcg_finish(int64_t n, const PcgState *st, T *x, const T *p, hi
 hipError_t launch_reduce_sigma(const double *partial, int64_t n, PcgState *st, hipStream_t s);
 hipError_t launch_reduce_rho(const double *partial, int64_t n, PcgState *st, hipStream_t s);
 hipError_t launch_reduce_scalar(const double *partial, int64_t n, double *out, hipStream_t s);
+// diagonal of the local Helmholtz operator (h1 == nullptr: 1, h2b == nullptr: 0)
+hipError_t launch_helm_diag(int N, int64_t E, const double *G, const double *h1, const double *h2b, double *diag,
+                            hipStream_t s);
+// out = v > 0 ? 1/v : 0
+hipError_t launch_invert_positive(int64_t n, const double *v, double *out, hipStream_t s);
+hipError_t launch_fill(int64_t n, double value, double *out, hipStream_t s);
 
 }  // namespace sem

@@ -208,11 +208,15 @@ struct ColumnIndex {
     }
 };
 
-template <typename T, int N, int MODE, int LAYOUT = 0>
+// HELM: Helmholtz form -- the three products of the combine step are scaled
+// by h1 at the point (Algorithm 1's h1) and h2*B*u is added to the output
+// (the h2 term of Eq. 4); h2b holds h2*B per point.
+template <typename T, int N, int MODE, int LAYOUT = 0, bool HELM = false>
 __device__ inline void ax_tile(const LaneRows<T, N> &R, const T *__restrict__ D, T *su, int64_t e, bool active,
                                bool inblk, int i, int j, const T *__restrict__ G, const T *__restrict__ in,
                                T *__restrict__ out, const T *__restrict__ invdiag, T *__restrict__ p, T beta,
-                               T *__restrict__ x, T alpha, double &dot)
+                               T *__restrict__ x, T alpha, double &dot, const T *__restrict__ h1 = nullptr,
+                               const T *__restrict__ h2b = nullptr)
 {
     constexpr int P = N + 1, P2 = P * P, P3 = P2 * P;
     T *sr = su + P3;
@@ -262,9 +266,15 @@ __device__ inline void ax_tile(const LaneRows<T, N> &R, const T *__restrict__ D,
             g1 = g[0 * P3]; g2 = g[1 * P3]; g3 = g[2 * P3];
             g4 = g[3 * P3]; g5 = g[4 * P3]; g6 = g[5 * P3];
         }
-        const T wr = g1 * ur + g4 * us + g5 * ut;
-        const T ws = g2 * us + g4 * ur + g6 * ut;
+        T wr = g1 * ur + g4 * us + g5 * ut;
+        T ws = g2 * us + g4 * ur + g6 * ut;
         wt[k] = g3 * ut + g5 * ur + g6 * us;
+        if (HELM) {
+            const T h = active ? h1[eb + ci.off(k)] : T(0);
+            wr *= h;
+            ws *= h;
+            wt[k] *= h;
+        }
         if (inblk) {
             sr[k * P2 + ij] = wr;
             ss[k * P2 + ij] = ws;
@@ -278,6 +288,7 @@ __device__ inline void ax_tile(const LaneRows<T, N> &R, const T *__restrict__ D,
 #pragma unroll
         for (int l = 0; l < P; ++l)
             acc += R.dti(l) * sr[k * P2 + j * P + l] + R.dtj(l) * ss[k * P2 + l * P + i] + D[l * P + k] * wt[l];
+        if (HELM && active) acc += h2b[eb + ci.off(k)] * uc[k];
         if (active) out[eb + ci.off(k)] = acc;
         if (MODE != 0) dot += (double)uc[k] * (double)acc;
     }

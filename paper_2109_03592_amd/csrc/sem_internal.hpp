@@ -99,6 +99,11 @@ struct sem_mesh {
     int32_t *gs_off = nullptr;     // gather-scatter plan (CSR)
     int32_t *gs_idx = nullptr;
     sem::GsPlan gsplan{};
+    // Helmholtz coefficients (sem_set_helmholtz): h1 and h2*B per local node;
+    // helm = 0 is the Poisson operator
+    int helm = 0;
+    double *h1_64 = nullptr, *h2b64 = nullptr;
+    float *h1_32 = nullptr, *h2b32 = nullptr;
     // Krylov work space, allocated on the first solve
     double *x64 = nullptr, *r64 = nullptr, *p64 = nullptr, *w64 = nullptr;
     float *x32 = nullptr, *r32 = nullptr, *p32 = nullptr, *w32 = nullptr;

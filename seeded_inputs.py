@@ -60,6 +60,11 @@ def random_local(n: int, seed: int, dtype=np.float64) -> np.ndarray:
     return np.random.default_rng(seed).uniform(-1.0, 1.0, size=int(n)).astype(dtype)
 
 
+def uniform_local(n: int, seed: int, lo: float, hi: float) -> np.ndarray:
+    """U[lo, hi) values for an E-vector (e.g. positive coefficients)."""
+    return np.random.default_rng(seed).uniform(lo, hi, size=int(n))
+
+
 def elements_from_target(e_star: float) -> Tuple[int, int, int]:
     """Box element counts from a target element count E*:
     nx = round(cbrt E*), ny = round(sqrt(E*/nx)), nz = max(1, round(E*/(nx ny)))."""

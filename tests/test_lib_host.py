@@ -44,6 +44,7 @@ def test_version_and_error_text(L):
     # a null descriptor is an error, not a crash
     assert lib.sem_host_setup(None, None, *([None] * 8)) == L.SEM_EINVAL
     assert lib.sem_info(None, None) == L.SEM_EINVAL
+    assert lib.sem_set_helmholtz(None, None, None, None) == L.SEM_EINVAL
 
 
 def test_inverted_element_rejected(L):
