@@ -47,6 +47,10 @@ def bytes_per_point(N: int, kind: str, dtype_bytes: int = 8) -> float:
         return dtype_bytes * (4 + 6 + 3)
     if kind == "update":      # read r, w, invdiag, mult (1 B); write r
         return dtype_bytes * 4 + 1
+    if kind == "ax_helm":     # plain operator + h1, h2*B
+        return dtype_bytes * (1 + 6 + 2 + 1)
+    if kind == "ax_pcg_helm":  # CG operator + h1, h2*B
+        return dtype_bytes * (4 + 6 + 2 + 3)
     raise ValueError(kind)
 
 
@@ -141,6 +145,91 @@ def cpu_baseline(seconds_target: float = 15.0):
     }
 
 
+def helmholtz_section(mesh, b, args, torch, SI, stream):
+    """Helmholtz form (seeded h1 in [0.5, 2), h2 in [0, 3) per local point):
+    stand-alone Ax+gs applies and profiled PCG iterations; the Poisson form is
+    restored afterwards."""
+    nL, nG, N = mesh.n_local, mesh.n_global, mesh.N
+    h1 = torch.from_numpy(SI.uniform_local(nL, 41, 0.5, 2.0)).cuda()
+    h2 = torch.from_numpy(SI.uniform_local(nL, 61, 0.0, 3.0)).cuda()
+    mesh.set_helmholtz(h1, h2)
+    del h1, h2
+    u = torch.from_numpy(SI.random_local(nL, 3)).cuda()
+    w = torch.empty_like(u)
+    for _ in range(3):
+        mesh.ax(u, w)
+        mesh.gs(w)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(3 * args.applies)]
+    torch.cuda.synchronize()
+    for q in range(args.applies):
+        evs[3 * q].record(stream)
+        mesh.ax(u, w)
+        evs[3 * q + 1].record(stream)
+        mesh.gs(w)
+        evs[3 * q + 2].record(stream)
+    torch.cuda.synchronize()
+    t_ax = np.mean([evs[3 * q].elapsed_time(evs[3 * q + 1]) for q in range(args.applies)]) / 1e3
+    tot = evs[0].elapsed_time(evs[-1]) / 1e3 / args.applies
+    del u, w
+    x = mesh.zeros()
+    mesh.solve(b, x, fixed_iters=max(1, args.warmup), profile=True, initial_guess=False)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    _, res = mesh.solve(b, x, fixed_iters=args.steps, profile=True, initial_guess=False)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_it = e0.elapsed_time(e1) / 1e3 / args.steps
+    ax_ms = res.ms_operator / max(1, res.operator_launches)
+    mesh.set_helmholtz(None, None)
+    r = {"ax_gs_gdofs": nG / tot / 1e9, "ms_per_apply": tot * 1e3, "ms_ax": t_ax * 1e3,
+         "ax_gbs": bytes_per_point(N, "ax_helm") * nL / t_ax / 1e9,
+         "pcg_ms_per_iteration": t_it * 1e3, "pcg_gdofs": nG / t_it / 1e9,
+         "pcg_operator_ms": ax_ms, "pcg_operator_gbs": bytes_per_point(N, "ax_pcg_helm") * nL / ax_ms / 1e6}
+    log(f"helmholtz: ax+gs {r['ax_gs_gdofs']:.2f} GDOF/s (ax {t_ax * 1e3:.3f} ms, {r['ax_gbs']:.0f} GB/s); "
+        f"pcg {t_it * 1e3:.3f} ms/iteration ({r['pcg_gdofs']:.2f} GDOF/s), operator {ax_ms:.3f} ms "
+        f"({r['pcg_operator_gbs']:.0f} GB/s)")
+    return r
+
+
+def sweep(sem, torch, SI, orders, sizes, applies: int = 20):
+    """Ax+gs apply rate against order N and element count E on jittered boxes
+    (the analogue of the paper's Nekbone sweeps, section 3): FP64 and FP32,
+    GDOF/s and the algorithmic HBM fraction."""
+    stream = torch.cuda.current_stream()
+    rows = []
+    for N in orders:
+        for E in sizes:
+            nel = SI.elements_from_target(E)
+            m = sem.box_mesh(N, nel, vertices=SI.jittered_box_vertices(nel, seed=1), with_fp32=True)
+            info = m.info
+            row = {"N": N, "E": m.E, "nel": list(nel), "n_local": m.n_local, "n_global": m.n_global}
+            for name, dt, eb in (("fp64", torch.float64, 8), ("fp32", torch.float32, 4)):
+                u = torch.from_numpy(SI.random_local(m.n_local, 3)).to(device="cuda", dtype=dt)
+                w = torch.empty_like(u)
+                for _ in range(3):
+                    m.ax(u, w)
+                    m.gs(w)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                torch.cuda.synchronize()
+                e0.record(stream)
+                for _ in range(applies):
+                    m.ax(u, w)
+                    m.gs(w)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                t = e0.elapsed_time(e1) / 1e3 / applies
+                byt = bytes_per_point(N, "ax", eb) * m.n_local + gs_bytes(info, eb)
+                row[name] = {"ms": t * 1e3, "gdofs": m.n_global / t / 1e9, "hbm_frac": byt / t / 1e9 / HBM_PEAK_GBS}
+                del u, w
+            m.close()
+            rows.append(row)
+            log(f"sweep N={N:2d} E={row['E']:6d}: fp64 {row['fp64']['gdofs']:7.2f} GDOF/s "
+                f"({row['fp64']['hbm_frac'] * 100:5.1f}% HBM), fp32 {row['fp32']['gdofs']:7.2f} GDOF/s "
+                f"({row['fp32']['hbm_frac'] * 100:5.1f}% HBM)")
+    return rows
+
+
 def batched_section(sem, torch, SI):
     """64 independent jittered box meshes (seeds 100+i) solved together,
     FP64 and mixed, after the autotuner; aggregate throughput."""
@@ -218,9 +307,14 @@ def main():
     ap.add_argument("--no-axgs", action="store_true", help="skip the stand-alone Ax+gs timing")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-mesh solves")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
+    ap.add_argument("--no-helm", action="store_true", help="skip the Helmholtz-form timing")
     ap.add_argument("--serve-rates", default="10,100,1000")
     ap.add_argument("--serve-duration", type=float, default=5.0)
     ap.add_argument("--serve-drain", type=float, default=20.0)
+    ap.add_argument("--sweep", action="store_true",
+                    help="only run the Ax+gs sweep over orders and element counts (one JSON line)")
+    ap.add_argument("--sweep-orders", default="2,3,4,5,6,7,8,9,10,11,12")
+    ap.add_argument("--sweep-sizes", default="32,256,2048,16384")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain copy of known size (for scaling byte counters)")
     args = ap.parse_args()
@@ -240,6 +334,13 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.sweep:
+        import paper_2109_03592_amd as sem
+        import seeded_inputs as SI
+        rows = sweep(sem, torch, SI, [int(v) for v in args.sweep_orders.split(",")],
+                     [int(v) for v in args.sweep_sizes.split(",")])
+        print(json.dumps({"sweep": rows}), flush=True)
         return
     stream = torch.cuda.current_stream()
     nx, ny, nz = args.nel
@@ -360,6 +461,10 @@ def main():
                 sol[prec]["rel_diff_vs_fp64"] = err
         sol["mixed_speedup"] = sol["fp64"]["seconds"] / sol["mixed"]["seconds"]
         out["solve"] = sol
+
+    # ---- Helmholtz form (h1-weighted stiffness + h2 B) on the same mesh ------
+    if not args.no_helm:
+        out["helmholtz"] = helmholtz_section(mesh, b, args, torch, SI, stream)
 
     # ---- batched: 64 jittered boxes, E log-uniform in [8, 4096], N in {5,7,9} ----
     if not args.no_batch:

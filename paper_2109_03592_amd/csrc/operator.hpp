@@ -154,6 +154,14 @@ struct LaneRows {
         if constexpr (kDLds) return sD[cj * P + l];
         else return Dj_[l];
     }
+    // uniform D[k][l] of the t-direction: constant memory (scalar loads), or
+    // the LDS copy where the constant table would not fit the SGPRs
+    static constexpr bool kTLds = kDLds;
+    __device__ inline T dk(const T *__restrict__ D, int k, int l) const
+    {
+        if constexpr (kTLds) return sD[k * P + l];
+        else return D[k * P + l];
+    }
     __device__ inline T dti(int l) const
     {
         if constexpr (kDtLds) return sD[l * P + ci];
@@ -258,7 +266,7 @@ __device__ inline void ax_tile(const LaneRows<T, N> &R, const T *__restrict__ D,
         for (int l = 0; l < P; ++l) {
             ur += R.di(l) * su[k * P2 + j * P + l];
             us += R.dj(l) * su[k * P2 + l * P + i];
-            ut += D[k * P + l] * uc[l];
+            ut += R.dk(D, k, l) * uc[l];
         }
         T g1 = 0, g2 = 0, g3 = 0, g4 = 0, g5 = 0, g6 = 0;
         if (active) {
@@ -287,7 +295,7 @@ __device__ inline void ax_tile(const LaneRows<T, N> &R, const T *__restrict__ D,
         T acc = 0;
 #pragma unroll
         for (int l = 0; l < P; ++l)
-            acc += R.dti(l) * sr[k * P2 + j * P + l] + R.dtj(l) * ss[k * P2 + l * P + i] + D[l * P + k] * wt[l];
+            acc += R.dti(l) * sr[k * P2 + j * P + l] + R.dtj(l) * ss[k * P2 + l * P + i] + R.dk(D, l, k) * wt[l];
         if (HELM && active) acc += h2b[eb + ci.off(k)] * uc[k];
         if (active) out[eb + ci.off(k)] = acc;
         if (MODE != 0) dot += (double)uc[k] * (double)acc;
