@@ -65,6 +65,12 @@ def uniform_local(n: int, seed: int, lo: float, hi: float) -> np.ndarray:
     return np.random.default_rng(seed).uniform(lo, hi, size=int(n))
 
 
+def travelling_forcing(x, y, z, t: float, speed: float = 0.02):
+    """sin(pi (x + speed t)) sin(pi y) sin(pi z): a smoothly moving forcing
+    whose successive right-hand sides resemble those of a time-stepping run."""
+    return np.sin(np.pi * (x + speed * t)) * np.sin(np.pi * y) * np.sin(np.pi * z)
+
+
 def elements_from_target(e_star: float) -> Tuple[int, int, int]:
     """Box element counts from a target element count E*:
     nx = round(cbrt E*), ny = round(sqrt(E*/nx)), nz = max(1, round(E*/(nx ny)))."""
