@@ -244,6 +244,43 @@ sem_status sem_pcg_solve(sem_mesh *mesh, const double *b, double *x, const sem_s
                          sem_solve_stats *stats, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Projection onto previous solutions (section 2: successive solves of a time
+ * step are accelerated by projecting onto the span of earlier solutions,
+ * after Fischer).  A projection space keeps an A-orthonormal basis
+ * x_1..x_l of earlier solutions of one mesh's current operator (A-inner
+ * product x^T A y = unique-dof sum of x and the assembled A y), together with
+ * A x_i.  For a right-hand side b the guess
+ *   xbar = sum_i (x_i . b) x_i
+ * is the element of the span closest to the solution in the A-norm.
+ *
+ * Ownership: the space owns 2 max_vectors device E-vectors (FP64) and keeps
+ * the mesh pointer: free the space before the mesh.  When the mesh's operator
+ * changes (sem_set_helmholtz, sem_load_geometry) the basis is emptied.
+ */
+typedef struct sem_proj sem_proj;
+
+/* max_vectors: 1..32.  Errors: SEM_EINVAL, SEM_ENOMEM. */
+sem_status sem_proj_create(sem_mesh *mesh, int max_vectors, sem_proj **out);
+sem_status sem_proj_free(sem_proj *proj);
+/* Forget the basis. */
+sem_status sem_proj_reset(sem_proj *proj);
+/* Number of basis vectors held. */
+sem_status sem_proj_size(sem_proj *proj, int *n);
+/* x = sum_i (x_i . b) x_i (x = 0 for an empty basis).  b, x: device FP64
+ * E-vectors, b continuous and masked; asynchronous on `stream`. */
+sem_status sem_proj_project(sem_proj *proj, const double *b, double *x, void *stream);
+/* Add a solution x (device FP64 E-vector, continuous, masked): one operator
+ * apply, two passes of A-Gram-Schmidt against the basis, A-normalisation.  A
+ * remainder whose A-norm is below 1e-8 of x's is dropped (*added = 0, may be
+ * NULL); a full basis restarts from x alone.  Synchronises `stream`. */
+sem_status sem_proj_add(sem_proj *proj, const double *x, int *added, void *stream);
+/* sem_pcg_solve started from the projection (opts->x0_given is forced), then
+ * the solution joins the basis when the solve succeeded.  Same arguments,
+ * statistics and errors as sem_pcg_solve. */
+sem_status sem_proj_solve(sem_proj *proj, const double *b, double *x, const sem_solve_opts *opts,
+                          sem_solve_stats *stats, void *stream);
+
+/* ---------------------------------------------------------------------------
  * Batched and continuous solves.  A batch holds up to max_slots concurrent
  * solves ("slots"), each on any mesh (orders 2..10, any size) with its own
  * right-hand side, solution and precision.  Every CG phase of all slots runs

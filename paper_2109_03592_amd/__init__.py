@@ -371,6 +371,67 @@ class Batch:
         return x, _result(st)
 
 
+class Projection:
+    """Projection onto previous solutions of one mesh (C ABI sem_proj_*):
+    successive solves start from the A-norm best approximation in the span of
+    earlier solutions."""
+
+    def __init__(self, mesh: "Mesh", max_vectors: int = 8):
+        self._lib = mesh._lib
+        self.mesh = mesh
+        h = C.c_void_p()
+        L.check(self._lib.sem_proj_create(mesh._h, int(max_vectors), C.byref(h)), "sem_proj_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.sem_proj_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __len__(self) -> int:
+        n = C.c_int()
+        L.check(self._lib.sem_proj_size(self._h, C.byref(n)), "sem_proj_size")
+        return n.value
+
+    def reset(self):
+        L.check(self._lib.sem_proj_reset(self._h), "sem_proj_reset")
+
+    def project(self, b: torch.Tensor, x: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        x = self.mesh.zeros() if x is None else x
+        self.mesh._vec(b, "b", torch.float64)
+        self.mesh._vec(x, "x", torch.float64)
+        L.check(self._lib.sem_proj_project(self._h, b.data_ptr(), x.data_ptr(), _stream_handle(stream)),
+                "sem_proj_project")
+        return x
+
+    def add(self, x: torch.Tensor, stream=None) -> bool:
+        self.mesh._vec(x, "x", torch.float64)
+        a = C.c_int()
+        L.check(self._lib.sem_proj_add(self._h, x.data_ptr(), C.byref(a), _stream_handle(stream)), "sem_proj_add")
+        return bool(a.value)
+
+    def solve(self, b: torch.Tensor, x: Optional[torch.Tensor] = None, stream=None, raise_on_error: bool = True,
+              **kw) -> Tuple[torch.Tensor, SolveResult]:
+        """Projected PCG solve; the solution then joins the basis."""
+        x = self.mesh.zeros() if x is None else x
+        self.mesh._vec(b, "b", torch.float64)
+        self.mesh._vec(x, "x", torch.float64)
+        o = _opts(self._lib, **kw)
+        st = L.SolveStats()
+        status = self._lib.sem_proj_solve(self._h, b.data_ptr(), x.data_ptr(), C.byref(o), C.byref(st),
+                                          _stream_handle(stream))
+        res = _result(st)
+        if raise_on_error and status != L.SEM_OK:
+            raise SemError(status, "sem_proj_solve")
+        return x, res
+
+
 def box_mesh(N: int, nel: Sequence[int], vertices=None, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0),
              periodic=(0, 0, 0), **kw) -> Mesh:
     return Mesh(N, nel, periodic=periodic, lo=lo, hi=hi, mapping=SEM_MAP_BOX, vertices=vertices, **kw)

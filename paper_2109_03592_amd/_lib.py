@@ -67,6 +67,13 @@ SIGNATURES = {
     "sem_set_operator_config": (_i, [_vp, _i, _i]),
     "sem_get_operator_config": (_i, [_vp, C.POINTER(_i), C.POINTER(_i)]),
     "sem_set_helmholtz": (_i, [_vp, _vp, _vp, _vp]),
+    "sem_proj_create": (_i, [_vp, _i, C.POINTER(_vp)]),
+    "sem_proj_free": (_i, [_vp]),
+    "sem_proj_reset": (_i, [_vp]),
+    "sem_proj_size": (_i, [_vp, C.POINTER(_i)]),
+    "sem_proj_project": (_i, [_vp, _vp, _vp, _vp]),
+    "sem_proj_add": (_i, [_vp, _vp, C.POINTER(_i), _vp]),
+    "sem_proj_solve": (_i, [_vp, _vp, _vp, C.POINTER(SolveOpts), C.POINTER(SolveStats), _vp]),
     "sem_ax": (_i, [_vp, _i, _vp, _vp, _vp, _vp]),
     "sem_gs": (_i, [_vp, _i, _vp, _vp]),
     "sem_axgs": (_i, [_vp, _i, _vp, _vp, _vp]),

@@ -761,6 +761,7 @@ sem_status sem_load_geometry(sem_mesh *m, const double *G, const double *B, void
         }
         std::vector<double>().swap(h.G);
         std::vector<double>().swap(h.invdiag);
+        m->op_version++;
         if (m->helm) {
             // h2*B was formed with the old B: back to the Poisson form
             for (int q = 0; q < 2; ++q)
@@ -847,6 +848,7 @@ sem_status sem_set_helmholtz(sem_mesh *m, const double *h1, const double *h2, vo
         }
         SEM_HIP(hipFree(diag));
         m->helm = helm ? 1 : 0;
+        m->op_version++;
         return SEM_OK;
     });
 }

@@ -102,6 +102,7 @@ struct sem_mesh {
     // Helmholtz coefficients (sem_set_helmholtz): h1 and h2*B per local node;
     // helm = 0 is the Poisson operator
     int helm = 0;
+    int op_version = 0;  // bumped whenever the operator changes (projection bases follow it)
     double *h1_64 = nullptr, *h2b64 = nullptr;
     float *h1_32 = nullptr, *h2b32 = nullptr;
     // Krylov work space, allocated on the first solve
