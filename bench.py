@@ -230,6 +230,43 @@ def sweep(sem, torch, SI, orders, sizes, applies: int = 20):
     return rows
 
 
+def projection_section(sem, torch, SI, nel=(24, 24, 48), N: int = 7, solves: int = 6, vectors: int = 8):
+    """Successive right-hand sides b_t = mass(sin(pi (x + 0.02 t)) sin(pi y) sin(pi z)),
+    t = 0..solves-1, on a smaller pipe: FP64 solves to 1e-10 with projection
+    onto previous solutions against the same solves from zero."""
+    mesh = sem.pipe_mesh(*nel, N=N)
+    xyz = torch.from_numpy(mesh.export_coords()).cuda()
+    bs = []
+    for t in range(solves):
+        f = (torch.sin(np.pi * (xyz[0] + 0.02 * t)) * torch.sin(np.pi * xyz[1]) * torch.sin(np.pi * xyz[2]))
+        bs.append(mesh.mass(f.contiguous()))
+    del xyz
+    out = {"mesh": f"pipe {nel[0]}x{nel[1]}x{nel[2]} N={N}", "n_global": mesh.n_global, "solves": solves,
+           "max_vectors": vectors}
+    mesh.solve(bs[0], tol=1e-10)   # warm-up (graph capture)
+    for name in ("plain", "projected"):
+        P = sem.Projection(mesh, vectors) if name == "projected" else None
+        its, t_all = [], 0.0
+        for b in bs:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if P is None:
+                _, r = mesh.solve(b, tol=1e-10, poll_every=25)
+            else:
+                _, r = P.solve(b, tol=1e-10, poll_every=25)
+            torch.cuda.synchronize()
+            t_all += time.perf_counter() - t0
+            its.append(r.iterations)
+        if P is not None:
+            P.close()
+        out[name] = {"iterations": its, "seconds": t_all}
+    out["speedup"] = out["plain"]["seconds"] / out["projected"]["seconds"]
+    log(f"projection: iterations plain {out['plain']['iterations']} vs projected {out['projected']['iterations']}; "
+        f"{out['plain']['seconds']:.2f} s vs {out['projected']['seconds']:.2f} s ({out['speedup']:.2f}x)")
+    mesh.close()
+    return out
+
+
 def batched_section(sem, torch, SI):
     """64 independent jittered box meshes (seeds 100+i) solved together,
     FP64 and mixed, after the autotuner; aggregate throughput."""
@@ -308,6 +345,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-mesh solves")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
     ap.add_argument("--no-helm", action="store_true", help="skip the Helmholtz-form timing")
+    ap.add_argument("--no-proj", action="store_true", help="skip the successive-RHS projection timing")
     ap.add_argument("--serve-rates", default="10,100,1000")
     ap.add_argument("--serve-duration", type=float, default=5.0)
     ap.add_argument("--serve-drain", type=float, default=20.0)
@@ -465,6 +503,10 @@ def main():
     # ---- Helmholtz form (h1-weighted stiffness + h2 B) on the same mesh ------
     if not args.no_helm:
         out["helmholtz"] = helmholtz_section(mesh, b, args, torch, SI, stream)
+
+    # ---- successive right-hand sides with projection onto previous solutions ----
+    if not args.no_proj:
+        out["projection"] = projection_section(sem, torch, SI)
 
     # ---- batched: 64 jittered boxes, E log-uniform in [8, 4096], N in {5,7,9} ----
     if not args.no_batch:
