@@ -421,7 +421,7 @@ def main():
     ax_bytes = bytes_per_point(N, "ax_pcg") * nL
     roof = {"bound": "hbm", "kernel": f"ax_kernel<double,{N},cg>",
             "achieved": ax_bytes / (ax_ms / 1e3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "traffic": measured_traffic(f"ax_kernel<double, {N}, 2>", (nx, ny, nz), N, nL),
+            "traffic": measured_traffic(f"ax_kernel<double, {N}, 2, false>", (nx, ny, nz), N, nL),
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)"}
     roof["frac"] = roof["achieved"] / roof["peak"]
     step_bytes = ax_bytes + gs_bytes(info) + bytes_per_point(N, "update") * nL
