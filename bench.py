@@ -145,6 +145,73 @@ def cpu_baseline(seconds_target: float = 15.0):
     }
 
 
+def axgs_timing(mesh, info, N, torch, SI, stream, applies: int):
+    """Stand-alone Ax+gs applies in FP64 and FP32 (events around each launch)."""
+    nL, nG = mesh.n_local, mesh.n_global
+    res = {}
+    for name, dt, eb in (("fp64", torch.float64, 8), ("fp32", torch.float32, 4)):
+        u = torch.from_numpy(SI.random_local(nL, 3)).to(device="cuda", dtype=dt)
+        w = torch.empty_like(u)
+        for _ in range(3):
+            mesh.ax(u, w)
+            mesh.gs(w)
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(3 * applies)]
+        torch.cuda.synchronize()
+        tA = time.perf_counter()
+        for q in range(applies):
+            evs[3 * q].record(stream)
+            mesh.ax(u, w)
+            evs[3 * q + 1].record(stream)
+            mesh.gs(w)
+            evs[3 * q + 2].record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - tA
+        t_ax = np.mean([evs[3 * q].elapsed_time(evs[3 * q + 1]) for q in range(applies)]) / 1e3
+        t_gs = np.mean([evs[3 * q + 1].elapsed_time(evs[3 * q + 2]) for q in range(applies)]) / 1e3
+        tot = evs[0].elapsed_time(evs[-1]) / 1e3 / applies
+        byt = bytes_per_point(N, "ax", eb) * nL + gs_bytes(info, eb)
+        res[name] = {"gdofs": nG / tot / 1e9, "ms_per_apply": tot * 1e3, "ms_ax": t_ax * 1e3,
+                     "ms_gs": t_gs * 1e3, "ax_gbs": bytes_per_point(N, "ax", eb) * nL / t_ax / 1e9,
+                     "gs_gbs": gs_bytes(info, eb) / t_gs / 1e9,
+                     "hbm_frac": byt / tot / 1e9 / HBM_PEAK_GBS,
+                     "ax_tflops": flops_per_point(N) * nL / t_ax / 1e12,
+                     "algorithmic_bytes": byt, "applies": applies, "wall_s": wall}
+        del u, w
+    return res
+
+
+def n9_section(sem, torch, SI, stream, args, nel=(48, 48, 48)):
+    """The same pipe at N=9 (110,592 elements, 110.6M points): Ax+gs applies
+    and profiled FP64 PCG iterations."""
+    mesh = sem.pipe_mesh(*nel, N=9, with_fp32=True)
+    info = mesh.info
+    out = {"mesh": f"pipe {nel[0]}x{nel[1]}x{nel[2]} N=9", "E": mesh.E, "n_local": mesh.n_local,
+           "n_global": mesh.n_global}
+    out["ax_gs"] = axgs_timing(mesh, info, 9, torch, SI, stream, max(10, args.applies // 2))
+    vg = torch.from_numpy(SI.uniform_global_values(mesh.n_global, 2)).cuda()
+    b = mesh.scatter(vg)
+    del vg
+    x = mesh.zeros()
+    mesh.solve(b, x, fixed_iters=max(1, args.warmup), profile=True, initial_guess=False)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    steps = max(10, args.steps // 2)
+    e0.record(stream)
+    _, res = mesh.solve(b, x, fixed_iters=steps, profile=True, initial_guess=False)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / steps
+    ax_ms = res.ms_operator / max(1, res.operator_launches)
+    out["pcg"] = {"ms_per_iteration": t * 1e3, "gdofs": mesh.n_global / t / 1e9, "ms_operator": ax_ms,
+                  "operator_gbs": bytes_per_point(9, "ax_pcg") * mesh.n_local / ax_ms / 1e6}
+    a64, a32 = out["ax_gs"]["fp64"], out["ax_gs"]["fp32"]
+    log(f"N=9 pipe: ax+gs fp64 {a64['gdofs']:.2f} GDOF/s ({a64['hbm_frac'] * 100:.1f}% HBM, ax "
+        f"{a64['ax_gbs']:.0f} GB/s), fp32 {a32['gdofs']:.2f} GDOF/s; pcg {t * 1e3:.3f} ms/iteration "
+        f"({out['pcg']['gdofs']:.2f} GDOF/s), operator {out['pcg']['operator_gbs']:.0f} GB/s")
+    mesh.close()
+    return out
+
+
 def helmholtz_section(mesh, b, args, torch, SI, stream):
     """Helmholtz form (seeded h1 in [0.5, 2), h2 in [0, 3) per local point):
     stand-alone Ax+gs applies and profiled PCG iterations; the Poisson form is
@@ -346,6 +413,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
     ap.add_argument("--no-helm", action="store_true", help="skip the Helmholtz-form timing")
     ap.add_argument("--no-proj", action="store_true", help="skip the successive-RHS projection timing")
+    ap.add_argument("--no-n9", action="store_true", help="skip the N=9 pipe (48x48x48)")
     ap.add_argument("--serve-rates", default="10,100,1000")
     ap.add_argument("--serve-duration", type=float, default=5.0)
     ap.add_argument("--serve-drain", type=float, default=20.0)
@@ -442,38 +510,12 @@ def main():
 
     # ---- stand-alone Ax+gs applies (FP64 and FP32) ---------------------------
     if not args.no_axgs:
-        axgs = {}
-        for name, dt, eb in (("fp64", torch.float64, 8), ("fp32", torch.float32, 4)):
-            u = torch.from_numpy(SI.random_local(nL, 3)).to(device="cuda", dtype=dt)
-            w = torch.empty_like(u)
-            for _ in range(3):
-                mesh.ax(u, w)
-                mesh.gs(w)
-            evs = [torch.cuda.Event(enable_timing=True) for _ in range(3 * args.applies)]
-            torch.cuda.synchronize()
-            tA = time.perf_counter()
-            for q in range(args.applies):
-                evs[3 * q].record(stream)
-                mesh.ax(u, w)
-                evs[3 * q + 1].record(stream)
-                mesh.gs(w)
-                evs[3 * q + 2].record(stream)
-            torch.cuda.synchronize()
-            wall = time.perf_counter() - tA
-            t_ax = np.mean([evs[3 * q].elapsed_time(evs[3 * q + 1]) for q in range(args.applies)]) / 1e3
-            t_gs = np.mean([evs[3 * q + 1].elapsed_time(evs[3 * q + 2]) for q in range(args.applies)]) / 1e3
-            tot = evs[0].elapsed_time(evs[-1]) / 1e3 / args.applies
-            byt = bytes_per_point(N, "ax", eb) * nL + gs_bytes(info, eb)
-            axgs[name] = {"gdofs": nG / tot / 1e9, "ms_per_apply": tot * 1e3, "ms_ax": t_ax * 1e3,
-                          "ms_gs": t_gs * 1e3, "ax_gbs": bytes_per_point(N, "ax", eb) * nL / t_ax / 1e9,
-                          "gs_gbs": gs_bytes(info, eb) / t_gs / 1e9,
-                          "hbm_frac": byt / tot / 1e9 / HBM_PEAK_GBS,
-                          "ax_tflops": flops_per_point(N) * nL / t_ax / 1e12,
-                          "algorithmic_bytes": byt, "applies": args.applies, "wall_s": wall}
-            log(f"ax+gs {name}: {axgs[name]['gdofs']:.2f} GDOF/s, {axgs[name]['ms_per_apply']:.3f} ms/apply, "
-                f"ax {t_ax * 1e3:.3f} ms ({axgs[name]['ax_gbs']:.0f} GB/s), gs {t_gs * 1e3:.3f} ms, "
-                f"HBM {axgs[name]['hbm_frac'] * 100:.1f}%")
-            del u, w
+        axgs = axgs_timing(mesh, info, N, torch, SI, stream, args.applies)
+        for name in ("fp64", "fp32"):
+            a = axgs[name]
+            log(f"ax+gs {name}: {a['gdofs']:.2f} GDOF/s, {a['ms_per_apply']:.3f} ms/apply, "
+                f"ax {a['ms_ax']:.3f} ms ({a['ax_gbs']:.0f} GB/s), gs {a['ms_gs']:.3f} ms, "
+                f"HBM {a['hbm_frac'] * 100:.1f}%")
         out["ax_gs"] = axgs
 
     # ---- full solves to 1e-10: FP64 and mixed --------------------------------
@@ -507,6 +549,12 @@ def main():
     # ---- successive right-hand sides with projection onto previous solutions ----
     if not args.no_proj:
         out["projection"] = projection_section(sem, torch, SI)
+
+    # ---- the pipe at N=9 (48x48x48) ------------------------------------------
+    if not args.no_n9:
+        del b
+        mesh.close()
+        out["pipe_n9"] = n9_section(sem, torch, SI, stream, args)
 
     # ---- batched: 64 jittered boxes, E log-uniform in [8, 4096], N in {5,7,9} ----
     if not args.no_batch:

@@ -145,11 +145,15 @@ sem_status sem_host_setup(const sem_mesh_desc *desc, sem_mesh_info *info, int64_
 sem_status sem_load_geometry(sem_mesh *mesh, const double *G, const double *B, void *stream);
 
 /* Launch configuration of the local operator on this mesh: elements per
- * workgroup (1 <= epw, epw (N+1)^2 <= 256) and the number of persistent
+ * workgroup (1 <= epw, epw (N+1)^2 <= 512, its LDS 3 epw (N+1)^3 values
+ * within the device's per-workgroup limit, else the operator calls fail with
+ * SEM_EHIP) and the number of persistent
  * workgroups (grid > 0; 0 keeps the default of 16 per compute unit).  Results
  * of sem_ax / sem_axgs do not depend on it; CG dot products do at rounding
- * level (their partial sums follow the workgroups).  The autotuner sets it;
- * sem_get_operator_config reads it. */
+ * level (their partial sums follow the workgroups).  Setting it applies to
+ * the FP64 and FP32 operators; by default each precision has its own count
+ * (the one that fills 64-lane waves best).  sem_get_operator_config reads the
+ * FP64 one. */
 sem_status sem_set_operator_config(sem_mesh *mesh, int epw, int grid);
 sem_status sem_get_operator_config(const sem_mesh *mesh, int *epw, int *grid);
 
@@ -304,7 +308,7 @@ sem_status sem_batch_free(sem_batch *batch);
  * each candidate elements-per-workgroup and keep the fastest; then choose the
  * persistent grid size.  The batch must have no admitted slots. */
 sem_status sem_batch_tune(sem_batch *batch, sem_mesh *const *meshes, int n, void *stream);
-/* Elements per operator workgroup for order N (epw (N+1)^2 <= 256; 0 restores
+/* Elements per operator workgroup for order N (epw (N+1)^2 <= 512; 0 restores
  * the default).  The batch must have no admitted slots (SEM_EINVAL). */
 sem_status sem_batch_set_epw(sem_batch *batch, int N, int epw);
 sem_status sem_batch_get_epw(const sem_batch *batch, int N, int *epw);

@@ -69,23 +69,29 @@ static void upload(void *dst, const void *src, size_t bytes, hipStream_t s)
     SEM_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
 }
 
-// Elements per workgroup of the operator: the smallest count that keeps the
-// 64-wide waves at least ~94% populated, within 256 lanes.
-static int default_epw(int N)
+// Elements per workgroup of the operator: the count that fills the 64-wide
+// waves best (ties: the smaller count), within 150 KB of LDS and a lane
+// budget -- FP64: 512 (256 from N = 10 on, where the kernel runs one wave
+// per SIMD); FP32 (lighter kernels, more waves per SIMD): 256.
+int default_operator_epw(int N, bool fp32)
 {
-    const int P2 = (N + 1) * (N + 1);
+    const int P2 = (N + 1) * (N + 1), P3 = P2 * (N + 1);
+    const int max_lanes = (fp32 || N >= 10) ? 256 : 512;
     int best = 1;
     double best_fill = 0.0;
-    for (int epw = 1; epw * P2 <= 256; ++epw) {
+    for (int epw = 1; epw * P2 <= max_lanes; ++epw) {
+        if ((size_t)3 * epw * P3 * sizeof(double) > 150 * 1024) break;
         const int t = epw * P2, tr = (t + 63) / 64 * 64;
         const double fill = (double)t / tr;
-        if (fill > best_fill + 0.06) {
+        if (fill > best_fill + 0.005) {
             best_fill = fill;
             best = epw;
         }
     }
     return best;
 }
+
+static int default_epw(int N, bool fp32 = false) { return default_operator_epw(N, fp32); }
 
 // Derivative matrices of every order in the kernels' constant table, once
 // per device.
@@ -194,7 +200,7 @@ static void enqueue_ax(sem_mesh *m, int mode, const T *in, T *out, hipStream_t s
 {
     AxParams<T> a{};
     a.E = m->h.E;
-    a.epw = m->ax_epw;
+    a.epw = sizeof(T) == 8 ? m->ax_epw : m->ax_epw32;
     a.grid_cap = m->ax_grid_cap;
     a.G = Prec<T>::G(m);
     a.in = in;
@@ -259,7 +265,7 @@ template <typename T>
 static void enqueue_iterations(sem_mesh *m, int k, hipStream_t s, Profiler *prof = nullptr)
 {
     PcgState *st = Prec<T>::st(m);
-    const int64_t axb = ax_grid(m->h.E, m->ax_epw, m->ax_grid_cap);
+    const int64_t axb = ax_grid(m->h.E, sizeof(T) == 8 ? m->ax_epw : m->ax_epw32, m->ax_grid_cap);
     const int64_t nL = m->h.nL;
     for (int it = 0; it < k; ++it) {
         if (prof) prof->mark(s);
@@ -284,7 +290,8 @@ static void run_iterations(sem_mesh *m, int k, bool use_graph, hipStream_t s, Pr
         return;
     }
     const int slot = sizeof(T) == 8 ? 0 : 1;
-    if (!m->graph[slot] || m->graph_k[slot] != k || m->graph_epw[slot] != m->ax_epw ||
+    const int epw = slot == 0 ? m->ax_epw : m->ax_epw32;
+    if (!m->graph[slot] || m->graph_k[slot] != k || m->graph_epw[slot] != epw ||
         m->graph_grid[slot] != m->ax_grid_cap) {
         if (m->graph[slot]) {
             SEM_HIP(hipGraphExecDestroy(m->graph[slot]));
@@ -307,7 +314,7 @@ static void run_iterations(sem_mesh *m, int k, bool use_graph, hipStream_t s, Pr
         SEM_HIP(e);
         m->graph[slot] = ex;
         m->graph_k[slot] = k;
-        m->graph_epw[slot] = m->ax_epw;
+        m->graph_epw[slot] = epw;
         m->graph_grid[slot] = m->ax_grid_cap;
     }
     SEM_HIP(hipGraphLaunch(m->graph[slot], s));
@@ -550,6 +557,7 @@ sem_status sem_setup(const sem_mesh_desc *desc, void *stream, sem_mesh **out)
             SEM_HIP(hipGetDevice(&m->device));
             m->with_fp32 = (desc->precision_flags & SEM_WITH_FP32) ? 1 : 0;
             m->ax_epw = default_epw(h.N);
+            m->ax_epw32 = default_epw(h.N, true);
             const int64_t nL = h.nL;
             ensure_dtables(s);
             m->G64 = dalloc<double>(m, 6 * nL);
@@ -780,11 +788,12 @@ sem_status sem_set_operator_config(sem_mesh *m, int epw, int grid)
     return guarded([&]() -> sem_status {
         if (!m) fail(SEM_EINVAL, "sem_set_operator_config: null mesh");
         const int P2 = m->h.P * m->h.P;
-        if (epw < 1 || epw * P2 > 256) fail(SEM_EINVAL, "sem_set_operator_config: epw out of range");
+        if (epw < 1 || epw * P2 > 512) fail(SEM_EINVAL, "sem_set_operator_config: epw out of range");
         if (grid < 0) fail(SEM_EINVAL, "sem_set_operator_config: negative grid");
         const int cap = grid > 0 ? grid : persistent_grid_cap();
         if (cap > m->n_partials - 64) fail(SEM_EINVAL, "sem_set_operator_config: grid larger than the partials buffer");
         m->ax_epw = epw;
+        m->ax_epw32 = epw;
         m->ax_grid_cap = cap;
         return SEM_OK;
     });
@@ -869,7 +878,9 @@ sem_status sem_ax(sem_mesh *m, int dtype, const void *u, void *w, double *opt_do
         const int mode = opt_dot ? 1 : 0;
         if (dtype == SEM_FP64) enqueue_ax<double>(m, mode, (const double *)u, (double *)w, s);
         else enqueue_ax<float>(m, mode, (const float *)u, (float *)w, s);
-        if (opt_dot) SEM_HIP(launch_reduce_scalar(m->partials, ax_grid(m->h.E, m->ax_epw, m->ax_grid_cap), opt_dot, s));
+        if (opt_dot)
+            SEM_HIP(launch_reduce_scalar(
+                m->partials, ax_grid(m->h.E, dtype == SEM_FP64 ? m->ax_epw : m->ax_epw32, m->ax_grid_cap), opt_dot, s));
         return SEM_OK;
     });
 }

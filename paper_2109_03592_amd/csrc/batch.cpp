@@ -125,22 +125,9 @@ static void *balloc(sem_batch *B, size_t bytes)
     return p;
 }
 
-// elements per operator tile: fill whole waves, preferring small tiles
-static int default_batch_epw(int N)
-{
-    const int P2 = (N + 1) * (N + 1);
-    int best = 1;
-    double best_fill = 0.0;
-    for (int e = 1; e * P2 <= 256; ++e) {
-        const int t = e * P2, tr = (t + 63) / 64 * 64;
-        const double fill = (double)t / tr;
-        if (fill > best_fill + 0.06) {
-            best_fill = fill;
-            best = e;
-        }
-    }
-    return best;
-}
+// elements per operator tile: the single-mesh rule (fill whole waves)
+int default_operator_epw(int N, bool fp32);
+static int default_batch_epw(int N) { return default_operator_epw(N, false); }
 
 static int batch_epw(const sem_batch *B, int N) { return B->epw[N] > 0 ? B->epw[N] : default_batch_epw(N); }
 
@@ -819,7 +806,9 @@ sem_status sem_batch_tune(sem_batch *B, sem_mesh *const *meshes, int n, void *st
                 for (int id : ids)
                     if (B->h_desc[id].N == N) grp.push_back(id);
                 if (grp.empty()) continue;
-                const int P2 = (N + 1) * (N + 1), emax = 256 / P2;
+                const int P2 = (N + 1) * (N + 1), P3 = P2 * (N + 1);
+                int emax = (N >= 10 ? 256 : 512) / P2;
+                while (emax > 1 && (size_t)3 * emax * P3 * sizeof(double) > 150 * 1024) --emax;
                 double best = 1e300;
                 int best_e = default_batch_epw(N);
                 for (int e = 1; e <= emax; ++e) {
@@ -874,7 +863,7 @@ sem_status sem_batch_set_epw(sem_batch *B, int N, int epw)
     return bguard([&]() -> sem_status {
         if (!B || N < 1 || N > SEM_MAX_ORDER) fail(SEM_EINVAL, "sem_batch_set_epw: bad order");
         const int P2 = (N + 1) * (N + 1);
-        if (epw < 0 || epw * P2 > 256) fail(SEM_EINVAL, "sem_batch_set_epw: epw out of range");
+        if (epw < 0 || epw * P2 > 512) fail(SEM_EINVAL, "sem_batch_set_epw: epw out of range");
         for (int id = 0; id < B->max_slots; ++id)
             if (B->slots[id].phase != PH_FREE) fail(SEM_EINVAL, "sem_batch_set_epw: the batch must be empty");
         B->epw[N] = epw;

@@ -45,7 +45,7 @@ static inline int prec_of_host() { return sizeof(T) == 8 ? 0 : 1; }
 // p.Ap partials.  A workgroup is epw elements x (N+1)^2 lanes, as in the
 // single-mesh kernel; the derivative rows are loaded once per workgroup.
 template <typename T, int N, int MODE>
-__global__ __launch_bounds__(256) void batch_ax_kernel(const SlotDesc *slots_, GroupDev g, int epw)
+__global__ __launch_bounds__(512) void batch_ax_kernel(const SlotDesc *slots_, GroupDev g, int epw)
 {
     constexpr int P = N + 1, P2 = P * P, P3 = P2 * P;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -408,7 +408,7 @@ static hipError_t batch_ax_order(int N, const SlotDesc *slots, const GroupDev &g
 {
     const int epw = L.epw[N];
     const int threads = ax_block_threads(N, epw);
-    if (epw < 1 || threads > 256) return hipErrorInvalidConfiguration;
+    if (epw < 1 || threads > 512) return hipErrorInvalidConfiguration;
     const size_t lds = batch_ax_lds(N, epw, prec_of_host<T>());
     switch (N) {
 #define SEM_BCASE(n) \

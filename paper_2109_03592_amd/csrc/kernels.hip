@@ -22,7 +22,7 @@ namespace sem {
 // Single mesh, persistent: each workgroup walks element tiles blockIdx.x,
 // blockIdx.x + gridDim.x, ... and stores its dot partial (modes 1, 2).
 template <typename T, int N, int MODE, bool HELM>
-__global__ __launch_bounds__(256) void ax_kernel(AxParams<T> a)
+__global__ __launch_bounds__(512) void ax_kernel(AxParams<T> a)
 {
     constexpr int P = N + 1, P2 = P * P, P3 = P2 * P;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -408,13 +408,24 @@ int64_t ax_grid(int64_t E, int epw, int cap)
     return tiles < cap ? tiles : cap;
 }
 
+// dynamic LDS a workgroup may request on the current device
+static size_t max_dynamic_lds()
+{
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 65536;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+        return 65536;
+    return (size_t)v - 4096;  // static LDS of the kernel (reduction, D copy)
+}
+
 template <typename T, int MODE, bool HELM>
 static hipError_t launch_ax_mode(int N, const AxParams<T> &a, hipStream_t s)
 {
+    static const size_t lds_cap = max_dynamic_lds();
     const int threads = ax_block_threads(N, a.epw);
     const size_t lds = ax_lds_bytes(N, a.epw, sizeof(T));
     const int64_t blocks = ax_grid(a.E, a.epw, a.grid_cap);
-    if (threads > 256 || blocks < 1 || blocks > INT32_MAX) return hipErrorInvalidConfiguration;
+    if (threads > 512 || lds > lds_cap || blocks < 1 || blocks > INT32_MAX) return hipErrorInvalidConfiguration;
     switch (N) {
 #define SEM_AX_CASE(n) \
     case n: hipLaunchKernelGGL((ax_kernel<T, n, MODE, HELM>), dim3((unsigned)blocks), dim3(threads), lds, s, a); break;

@@ -112,7 +112,8 @@ struct sem_mesh {
     int64_t n_partials = 0;
     sem::PcgState *state = nullptr;  // [2]: FP64 solve, FP32 inner solve
     double *scal = nullptr;          // small device scratch for norms
-    int ax_epw = 1;                  // elements per workgroup of the operator
+    int ax_epw = 1;                  // elements per workgroup of the FP64 operator
+    int ax_epw32 = 1;                // ... of the FP32 operator
     int ax_grid_cap = 4096;          // persistent operator grid
     std::vector<hipEvent_t> events;  // profiling event pool
     hipStream_t capture_stream = nullptr;

@@ -110,7 +110,7 @@ def test_tuner_and_budget(semlib, cases):
     B.tune(meshes)
     for m in meshes:
         e = B.epw(m.N)
-        assert 1 <= e and e * (m.N + 1) ** 2 <= 256
+        assert 1 <= e and e * (m.N + 1) ** 2 <= 512
     bs = [torch.from_numpy(c[2]).cuda() for c in cases]
     xs, res = B.solve(meshes, bs, tol=1e-10)
     assert all(r.ok for r in res)

@@ -95,6 +95,27 @@ def test_pcg_high_order(semlib, oracle_mod, N, nel):
             assert abs(res.iterations - ro.iterations) <= max(3, 0.05 * ro.iterations), (res, ro)
 
 
+@pytest.mark.parametrize("N,epws", [(5, (1, 3, 7, 14)), (7, (1, 2, 4, 8)), (9, (1, 2, 5)), (3, (1, 4, 32))])
+def test_operator_config_does_not_change_results(semlib, oracle_mod, N, epws):
+    """Elements per workgroup (up to 512 lanes) change the launch, not the
+    bits of A_L u; a configuration beyond the lane limit is refused."""
+    nel = (5, 3, 2)
+    print(f"case: operator configs N={N} epw={epws}", flush=True)
+    m, om = _box(semlib, oracle_mod, N, nel, seed=3 + N)
+    u = _dev(SI.random_local(om.nloc, 70 + N))
+    outs = []
+    for e in epws:
+        m.set_operator_config(e, 0)
+        assert m.operator_config()[0] == e
+        outs.append(_host(m.ax(u)))
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    e2, _ = _relerr(outs[0], om.ax(_host(u)))
+    assert e2 <= 1e-12
+    with pytest.raises(semlib.SemError):
+        m.set_operator_config(512 // (N + 1) ** 2 + 1, 0)
+
+
 def test_ax_dot_and_fp32(semlib, oracle_mod):
     print("case: ax dot + fp32, box 4x4x4 N=7", flush=True)
     m, om = _box(semlib, oracle_mod, 7, (4, 4, 4), with_fp32=True)
