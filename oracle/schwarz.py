@@ -31,6 +31,7 @@ from __future__ import annotations
 from typing import List, Tuple
 
 import numpy as np
+from scipy.linalg import cho_factor, cho_solve
 
 INTERIOR, DIRICHLET, NEUMANN = 0, 1, 2
 
@@ -155,9 +156,9 @@ class SchwarzOracle:
             if e not in self._chol:
                 A, ids = self.local_system(e)
                 assert np.all(ids >= 0)
-                self._chol[e] = (np.linalg.cholesky(A), ids)
-            Lc, ids = self._chol[e]
-            y = np.linalg.solve(Lc.T, np.linalg.solve(Lc, rg[ids]))
+                self._chol[e] = (cho_factor(A), ids)
+            cf, ids = self._chol[e]
+            y = cho_solve(cf, rg[ids])
             np.add.at(zg, ids, y)
         zg[gm == 1] = 0.0
         return zg[self.gid]
