@@ -414,6 +414,8 @@ def main():
     ap.add_argument("--no-helm", action="store_true", help="skip the Helmholtz-form timing")
     ap.add_argument("--no-proj", action="store_true", help="skip the successive-RHS projection timing")
     ap.add_argument("--no-n9", action="store_true", help="skip the N=9 pipe (48x48x48)")
+    ap.add_argument("--operator-kernel", choices=("column", "node"), default=None,
+                    help="thread layout of the operator on the N=7 pipe (default: the library's)")
     ap.add_argument("--serve-rates", default="10,100,1000")
     ap.add_argument("--serve-duration", type=float, default=5.0)
     ap.add_argument("--serve-drain", type=float, default=20.0)
@@ -453,6 +455,8 @@ def main():
     N = args.order
     t0 = time.perf_counter()
     mesh = sem.pipe_mesh(nx, ny, nz, N=N, with_fp32=True)
+    if args.operator_kernel:
+        mesh.set_operator_kernel(args.operator_kernel)
     info = mesh.info
     log(f"setup: E={mesh.E} N={N} n_local={mesh.n_local} n_global={mesh.n_global} "
         f"({time.perf_counter() - t0:.1f} s, {info.device_bytes / 2**30:.1f} GiB on device)")

@@ -157,6 +157,20 @@ sem_status sem_load_geometry(sem_mesh *mesh, const double *G, const double *B, v
 sem_status sem_set_operator_config(sem_mesh *mesh, int epw, int grid);
 sem_status sem_get_operator_config(const sem_mesh *mesh, int *epw, int *grid);
 
+/* Thread layout of the local operator:
+ *   SEM_OPK_COLUMN -- one lane per (i,j) column of an element, the column in
+ *     registers and the t-derivative without LDS (any N; uses the
+ *     elements-per-workgroup of sem_set_operator_config);
+ *   SEM_OPK_NODE   -- one lane per node, as in Algorithm 1's thread layout,
+ *     with the element and the three weighted derivatives in LDS (N <= 7;
+ *     whole elements fill up to 512 lanes).
+ * Both compute Algorithm 1 with the same sums in the same order; results may
+ * differ in the last bit where the compiler fuses multiply-adds differently.
+ * Errors: SEM_EINVAL (unknown kind, SEM_OPK_NODE with N > 7). */
+enum { SEM_OPK_COLUMN = 0, SEM_OPK_NODE = 1 };
+sem_status sem_set_operator_kernel(sem_mesh *mesh, int kind);
+sem_status sem_get_operator_kernel(const sem_mesh *mesh, int *kind);
+
 /* Helmholtz form of the operator (Eq. 4 with the variable coefficient h1 of
  * Algorithm 1): afterwards sem_ax, sem_axgs and sem_pcg_solve apply
  *   A_L u = sum_q h1_q (grad phi)^T G_q (grad u) + h2 B u

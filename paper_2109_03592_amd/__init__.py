@@ -148,6 +148,16 @@ class Mesh:
         """Elements per workgroup and persistent grid size of the operator (0 = default)."""
         L.check(self._lib.sem_set_operator_config(self._h, int(epw), int(grid)), "sem_set_operator_config")
 
+    def set_operator_kernel(self, kind: str):
+        """'column' (lane per (i,j) column) or 'node' (lane per node, N <= 7)."""
+        k = {"column": 0, "node": 1}[kind]
+        L.check(self._lib.sem_set_operator_kernel(self._h, k), "sem_set_operator_kernel")
+
+    def operator_kernel(self) -> str:
+        k = C.c_int()
+        L.check(self._lib.sem_get_operator_kernel(self._h, C.byref(k)), "sem_get_operator_kernel")
+        return ("column", "node")[k.value]
+
     def operator_config(self):
         e, g = C.c_int(), C.c_int()
         L.check(self._lib.sem_get_operator_config(self._h, C.byref(e), C.byref(g)), "sem_get_operator_config")

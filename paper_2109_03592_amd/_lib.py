@@ -67,6 +67,8 @@ SIGNATURES = {
     "sem_set_operator_config": (_i, [_vp, _i, _i]),
     "sem_get_operator_config": (_i, [_vp, C.POINTER(_i), C.POINTER(_i)]),
     "sem_set_helmholtz": (_i, [_vp, _vp, _vp, _vp]),
+    "sem_set_operator_kernel": (_i, [_vp, _i]),
+    "sem_get_operator_kernel": (_i, [_vp, C.POINTER(_i)]),
     "sem_proj_create": (_i, [_vp, _i, C.POINTER(_vp)]),
     "sem_proj_free": (_i, [_vp]),
     "sem_proj_reset": (_i, [_vp]),

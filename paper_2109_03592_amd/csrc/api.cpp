@@ -195,12 +195,21 @@ struct Prec<float> {
     static const float *h2b(sem_mesh *m) { return m->helm ? m->h2b32 : nullptr; }
 };
 
+// elements per workgroup of the operator kernel in use for precision T
+template <typename T>
+static int op_epw(const sem_mesh *m)
+{
+    if (m->op_kind == 1) return node_epw(m->h.N);
+    return sizeof(T) == 8 ? m->ax_epw : m->ax_epw32;
+}
+
 template <typename T>
 static void enqueue_ax(sem_mesh *m, int mode, const T *in, T *out, hipStream_t s)
 {
     AxParams<T> a{};
     a.E = m->h.E;
-    a.epw = sizeof(T) == 8 ? m->ax_epw : m->ax_epw32;
+    a.epw = op_epw<T>(m);
+    a.kind = m->op_kind;
     a.grid_cap = m->ax_grid_cap;
     a.G = Prec<T>::G(m);
     a.in = in;
@@ -265,7 +274,7 @@ template <typename T>
 static void enqueue_iterations(sem_mesh *m, int k, hipStream_t s, Profiler *prof = nullptr)
 {
     PcgState *st = Prec<T>::st(m);
-    const int64_t axb = ax_grid(m->h.E, sizeof(T) == 8 ? m->ax_epw : m->ax_epw32, m->ax_grid_cap);
+    const int64_t axb = ax_grid(m->h.E, op_epw<T>(m), m->ax_grid_cap);
     const int64_t nL = m->h.nL;
     for (int it = 0; it < k; ++it) {
         if (prof) prof->mark(s);
@@ -290,7 +299,7 @@ static void run_iterations(sem_mesh *m, int k, bool use_graph, hipStream_t s, Pr
         return;
     }
     const int slot = sizeof(T) == 8 ? 0 : 1;
-    const int epw = slot == 0 ? m->ax_epw : m->ax_epw32;
+    const int epw = op_epw<T>(m) + 1024 * m->op_kind;  // graph key: tile shape and kernel
     if (!m->graph[slot] || m->graph_k[slot] != k || m->graph_epw[slot] != epw ||
         m->graph_grid[slot] != m->ax_grid_cap) {
         if (m->graph[slot]) {
@@ -799,6 +808,27 @@ sem_status sem_set_operator_config(sem_mesh *m, int epw, int grid)
     });
 }
 
+sem_status sem_set_operator_kernel(sem_mesh *m, int kind)
+{
+    return guarded([&]() -> sem_status {
+        if (!m) fail(SEM_EINVAL, "sem_set_operator_kernel: null mesh");
+        if (kind != SEM_OPK_COLUMN && kind != SEM_OPK_NODE) fail(SEM_EINVAL, "sem_set_operator_kernel: unknown kind");
+        if (kind == SEM_OPK_NODE && m->h.N > kMaxNodeOrder)
+            fail(SEM_EINVAL, "sem_set_operator_kernel: the lane-per-node operator takes N <= 7");
+        m->op_kind = kind;
+        return SEM_OK;
+    });
+}
+
+sem_status sem_get_operator_kernel(const sem_mesh *m, int *kind)
+{
+    return guarded([&]() -> sem_status {
+        if (!m || !kind) fail(SEM_EINVAL, "sem_get_operator_kernel: null argument");
+        *kind = m->op_kind;
+        return SEM_OK;
+    });
+}
+
 sem_status sem_get_operator_config(const sem_mesh *m, int *epw, int *grid)
 {
     return guarded([&]() -> sem_status {
@@ -880,7 +910,8 @@ sem_status sem_ax(sem_mesh *m, int dtype, const void *u, void *w, double *opt_do
         else enqueue_ax<float>(m, mode, (const float *)u, (float *)w, s);
         if (opt_dot)
             SEM_HIP(launch_reduce_scalar(
-                m->partials, ax_grid(m->h.E, dtype == SEM_FP64 ? m->ax_epw : m->ax_epw32, m->ax_grid_cap), opt_dot, s));
+                m->partials, ax_grid(m->h.E, dtype == SEM_FP64 ? op_epw<double>(m) : op_epw<float>(m), m->ax_grid_cap),
+                opt_dot, s));
         return SEM_OK;
     });
 }

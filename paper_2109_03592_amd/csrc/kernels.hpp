@@ -37,7 +37,11 @@ struct AxParams {
     const PcgState *st;    // mode 2: alpha, beta and the done flag
     const T *h1;           // Helmholtz: h1 per local point (nullptr: Poisson)
     const T *h2b;          // Helmholtz: h2*B per local point (with h1)
+    int kind;              // 0: lane per (i,j) column; 1: lane per node (N <= 7)
 };
+
+constexpr int kMaxNodeOrder = 7;   // the lane-per-node operator: (N+1)^3 <= 512
+int node_epw(int N);              // elements per workgroup of the lane-per-node operator
 
 int ax_block_threads(int N, int epw);
 size_t ax_lds_bytes(int N, int epw, size_t elem);

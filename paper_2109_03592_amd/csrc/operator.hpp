@@ -304,4 +304,96 @@ __device__ inline void ax_tile(const LaneRows<T, N> &R, const T *__restrict__ D,
 }
 
 
+// ---------------------------------------------------------------------------
+// Local operator, one lane per node (the paper's thread layout): lane (el,
+// i, j, k) owns node (i,j,k) of element tile*epw + el.  The element and the
+// three weighted derivatives live in LDS (4 (N+1)^3 values per element); the
+// lane's rows D[i][.], D[j][.], D[k][.] sit in VGPRs, the columns come from
+// the LDS copy sD of D.  Few registers per lane, so many waves per SIMD hide
+// the HBM latency.  Same MODE/HELM meaning as ax_tile; every vector access is
+// one coalesced load or store per lane.  The caller ends each tile's work
+// with the barrier inside (the LDS of a tile is reused by the next).
+template <typename T, int N>
+struct NodeRows {
+    static constexpr int P = N + 1;
+    T Di[P], Dj[P], Dk[P];
+    __device__ inline void load(const T *__restrict__ D, int i, int j, int k)
+    {
+#pragma unroll
+        for (int l = 0; l < P; ++l) {
+            Di[l] = D[i * P + l];
+            Dj[l] = D[j * P + l];
+            Dk[l] = D[k * P + l];
+        }
+    }
+};
+
+template <typename T, int N, int MODE, bool HELM>
+__device__ inline void ax_node_tile(const NodeRows<T, N> &R, const T *__restrict__ sD, T *su, int64_t e, bool active,
+                                    bool inblk, int i, int j, int k, const T *__restrict__ G, const T *__restrict__ in,
+                                    T *__restrict__ out, const T *__restrict__ invdiag, T *__restrict__ p, T beta,
+                                    T *__restrict__ x, T alpha, double &dot, const T *__restrict__ h1,
+                                    const T *__restrict__ h2b)
+{
+    constexpr int P = N + 1, P2 = P * P, P3 = P2 * P;
+    T *sr = su + P3;
+    T *ss = sr + P3;
+    T *st = ss + P3;
+    const int pt = i + P * j + P2 * k;
+    const int64_t o = (active ? e : 0) * P3 + pt;
+    T v = 0;
+    if (active) {
+        if (MODE == 2) {
+            const T pold = p[o];
+            // the previous iteration's x step, deferred to here where p is read anyway
+            x[o] = x[o] + alpha * pold;
+            v = invdiag[o] * in[o] + beta * pold;
+            p[o] = v;
+        } else {
+            v = in[o];
+        }
+    }
+    if (inblk) su[pt] = v;
+    T g1 = 0, g2 = 0, g3 = 0, g4 = 0, g5 = 0, g6 = 0, h = 0;
+    if (active) {
+        const T *g = G + (active ? e : 0) * 6 * P3 + pt;
+        g1 = g[0 * P3]; g2 = g[1 * P3]; g3 = g[2 * P3];
+        g4 = g[3 * P3]; g5 = g[4 * P3]; g6 = g[5 * P3];
+        if (HELM) h = h1[o];
+    }
+    __syncthreads();
+    T ur = 0, us = 0, ut = 0;
+#pragma unroll
+    for (int l = 0; l < P; ++l) {
+        ur += R.Di[l] * su[l + P * j + P2 * k];
+        us += R.Dj[l] * su[i + P * l + P2 * k];
+        ut += R.Dk[l] * su[i + P * j + P2 * l];
+    }
+    T wr = g1 * ur + g4 * us + g5 * ut;
+    T ws = g2 * us + g4 * ur + g6 * ut;
+    T wt = g3 * ut + g5 * ur + g6 * us;
+    if (HELM) {
+        wr *= h;
+        ws *= h;
+        wt *= h;
+    }
+    if (inblk) {
+        sr[pt] = wr;
+        ss[pt] = ws;
+        st[pt] = wt;
+    }
+    __syncthreads();
+    T acc = 0;
+#pragma unroll
+    for (int l = 0; l < P; ++l)
+        acc += sD[l * P + i] * sr[l + P * j + P2 * k] + sD[l * P + j] * ss[i + P * l + P2 * k] +
+               sD[l * P + k] * st[i + P * j + P2 * l];
+    if (active) {
+        if (HELM) acc += h2b[o] * v;
+        out[o] = acc;
+    }
+    if (MODE != 0) dot += (double)v * (double)acc;
+    __syncthreads();  // the LDS of this tile is rewritten by the next
+}
+
 }  // namespace sem

@@ -114,6 +114,7 @@ struct sem_mesh {
     double *scal = nullptr;          // small device scratch for norms
     int ax_epw = 1;                  // elements per workgroup of the FP64 operator
     int ax_epw32 = 1;                // ... of the FP32 operator
+    int op_kind = 0;                 // 0: lane per (i,j) column, 1: lane per node (N <= 7)
     int ax_grid_cap = 4096;          // persistent operator grid
     std::vector<hipEvent_t> events;  // profiling event pool
     hipStream_t capture_stream = nullptr;

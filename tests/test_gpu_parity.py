@@ -116,6 +116,55 @@ def test_operator_config_does_not_change_results(semlib, oracle_mod, N, epws):
         m.set_operator_config(512 // (N + 1) ** 2 + 1, 0)
 
 
+@pytest.mark.parametrize("N", list(range(1, 8)))
+def test_node_operator_kernel(semlib, oracle_mod, N):
+    """The lane-per-node operator (N <= 7): FP64 and FP32 against the oracle,
+    and against the column kernel, plain and Helmholtz."""
+    nel = (3, 2, 3)
+    print(f"case: node operator N={N}", flush=True)
+    m, om = _box(semlib, oracle_mod, N, nel, seed=40 + N, with_fp32=True)
+    u = SI.random_local(om.nloc, 80 + N)
+    col = _host(m.ax(_dev(u)))
+    m.set_operator_kernel("node")
+    assert m.operator_kernel() == "node"
+    nod = _host(m.ax(_dev(u)))
+    ref = om.ax(u)
+    e2, einf = _relerr(nod, ref)
+    assert e2 <= 1e-12 and einf <= 1e-12, (e2, einf)
+    assert np.linalg.norm(nod - col) <= 1e-14 * np.linalg.norm(col)
+    u32 = u.astype(np.float32)
+    e2, einf = _relerr(_host(m.ax(_dev(u32, torch.float32))), om.ax(u32.astype(np.float64)))
+    assert e2 <= 2e-6 and einf <= 2e-5, (e2, einf)
+    w, dot = m.ax(_dev(u), dot=True)
+    assert abs(float(dot.item()) - float(u @ ref)) <= 1e-12 * np.abs(u * ref).sum()
+    h1 = SI.uniform_local(om.nloc, 90 + N, 0.5, 2.0)
+    h2 = SI.uniform_local(om.nloc, 91 + N, 0.0, 3.0)
+    m.set_helmholtz(_dev(h1), _dev(h2))
+    e2, _ = _relerr(_host(m.ax(_dev(u))), om.ax(u, h1=h1, h2=h2))
+    assert e2 <= 1e-12
+    m.close()
+
+
+def test_node_operator_pcg(semlib, oracle_mod):
+    print("case: pcg with the node operator, box 4x4x4 N=7", flush=True)
+    m, om = _box(semlib, oracle_mod, 7, (4, 4, 4), with_fp32=True)
+    m.set_operator_kernel("node")
+    x, y, z = om.coords()
+    b = om.mass(SI.sin3_forcing(x, y, z))
+    _, ro = om.pcg(b, tol=1e-10)
+    for prec in ("fp64", "mixed"):
+        xg, res = m.solve(_dev(b), tol=1e-10, precision=prec)
+        assert res.ok and om.true_residual(b, _host(xg)) <= 1e-10, (prec, res)
+        if prec == "fp64":
+            assert abs(res.iterations - ro.iterations) <= max(3, 0.05 * ro.iterations)
+    # N > 7 is refused
+    m9, _ = _box(semlib, oracle_mod, 9, (1, 1, 1))
+    with pytest.raises(semlib.SemError):
+        m9.set_operator_kernel("node")
+    m9.close()
+    m.close()
+
+
 def test_ax_dot_and_fp32(semlib, oracle_mod):
     print("case: ax dot + fp32, box 4x4x4 N=7", flush=True)
     m, om = _box(semlib, oracle_mod, 7, (4, 4, 4), with_fp32=True)
