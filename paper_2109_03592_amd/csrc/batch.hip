@@ -138,17 +138,17 @@ __global__ __launch_bounds__(kBatchBlock) void batch_update_kernel(const SlotDes
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int64_t q = min(q0 + u * kBatchBlock + threadIdx.x, qlast);
-                rv[u] = r[q];
-                wv[u] = w[q];
-                ivv[u] = iv[q];
-                mv[u] = sd.mult[q];
+                rv[u] = ld_stream(r + q);
+                wv[u] = ld_stream(w + q);
+                ivv[u] = ld_stream(iv + q);
+                mv[u] = ld_stream(sd.mult + q);
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int64_t q = q0 + u * kBatchBlock + threadIdx.x;
                 if (q > qlast) break;
                 const T rq = rv[u] - alpha * wv[u];
-                r[q] = rq;
+                st_stream(rq, r + q);
                 const double rd = (double)rq, im = inv_mult_b(mv[u]);
                 rr += rd * rd * im;
                 rz += rd * (double)(ivv[u] * rq) * im;

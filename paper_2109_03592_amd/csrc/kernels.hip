@@ -241,7 +241,8 @@ __global__ __launch_bounds__(256) void pcg_update_kernel(int64_t n, const PcgSta
         for (int u = 0; u < U; ++u) {
             const int64_t q = q0 + u * S;
             if (q < n2) {
-                rv[u] = r2[q]; wv[u] = w2[q]; iv[u] = i2[q]; mm[u] = m2[q];
+                rv[u] = ld_stream(r2 + q); wv[u] = ld_stream(w2 + q); iv[u] = ld_stream(i2 + q);
+                mm[u] = ld_stream(m2 + q);
             }
         }
 #pragma unroll
@@ -250,7 +251,7 @@ __global__ __launch_bounds__(256) void pcg_update_kernel(int64_t n, const PcgSta
             if (q >= n2) break;
             rv[u].x = rv[u].x - alpha * wv[u].x;
             rv[u].y = rv[u].y - alpha * wv[u].y;
-            r2[q] = rv[u];
+            st_stream(rv[u], r2 + q);
             const double ima = inv_mult((uint8_t)(mm[u] & 0xff)), imb = inv_mult((uint8_t)(mm[u] >> 8));
             const double ra = (double)rv[u].x, rb = (double)rv[u].y;
             rr += ra * ra * ima + rb * rb * imb;

@@ -35,6 +35,45 @@ __device__ inline void block_reduce_store(double (&v)[NV], double *dst, int stri
 }
 
 // ---------------------------------------------------------------------------
+// Streaming accesses: data read or written once per launch bypass the caches
+// (non-temporal), which keeps them from evicting what is reused.
+template <typename T>
+__device__ inline T ld_stream(const T *p) { return __builtin_nontemporal_load(p); }
+template <typename T>
+__device__ inline void st_stream(T v, T *p) { __builtin_nontemporal_store(v, p); }
+// pairs go through the compiler's native two-element vectors
+typedef double native_double2 __attribute__((ext_vector_type(2)));
+typedef float native_float2 __attribute__((ext_vector_type(2)));
+template <>
+__device__ inline double2 ld_stream(const double2 *p)
+{
+    const native_double2 v = __builtin_nontemporal_load(reinterpret_cast<const native_double2 *>(p));
+    return double2(v.x, v.y);
+}
+template <>
+__device__ inline float2 ld_stream(const float2 *p)
+{
+    const native_float2 v = __builtin_nontemporal_load(reinterpret_cast<const native_float2 *>(p));
+    return float2(v.x, v.y);
+}
+template <>
+__device__ inline void st_stream(double2 v, double2 *p)
+{
+    native_double2 w;
+    w.x = v.x;
+    w.y = v.y;
+    __builtin_nontemporal_store(w, reinterpret_cast<native_double2 *>(p));
+}
+template <>
+__device__ inline void st_stream(float2 v, float2 *p)
+{
+    native_float2 w;
+    w.x = v.x;
+    w.y = v.y;
+    __builtin_nontemporal_store(w, reinterpret_cast<native_float2 *>(p));
+}
+
+// ---------------------------------------------------------------------------
 // Direct-stiffness summation of one global id t of a plan (offsets `off` into
 // local indices `idx`, every id has at least one copy): ids below n_sum get
 // the sum of their copies, added in ascending local index starting from 0,
@@ -47,7 +86,7 @@ template <typename T>
 __device__ inline void gs_id(int64_t t, int64_t n_sum, const int32_t *__restrict__ off,
                              const int32_t *__restrict__ idx, T *__restrict__ v)
 {
-    const int32_t q0 = off[t], q1 = off[t + 1];
+    const int32_t q0 = ld_stream(off + t), q1 = ld_stream(off + t + 1);
     const int32_t last = q1 - 1, cnt = q1 - q0;
     int32_t ix[8];
 #pragma unroll
@@ -239,17 +278,17 @@ __device__ inline void ax_tile(const LaneRows<T, N> &R, const T *__restrict__ D,
             T v = 0;
             if (active) {
                 const int64_t o = eb + ci.off(k);
-                const T pold = p[o];
+                const T pold = ld_stream(p + o);
                 // the previous iteration's x step, deferred to here where p is read anyway
-                x[o] = x[o] + alpha * pold;
-                v = invdiag[o] * in[o] + beta * pold;
-                p[o] = v;
+                st_stream(ld_stream(x + o) + alpha * pold, x + o);
+                v = ld_stream(invdiag + o) * ld_stream(in + o) + beta * pold;
+                st_stream(v, p + o);
             }
             uc[k] = v;
         }
     } else {
 #pragma unroll
-        for (int k = 0; k < P; ++k) uc[k] = active ? in[eb + ci.off(k)] : T(0);
+        for (int k = 0; k < P; ++k) uc[k] = active ? ld_stream(in + eb + ci.off(k)) : T(0);
     }
     if (inblk) {
 #pragma unroll
@@ -271,14 +310,14 @@ __device__ inline void ax_tile(const LaneRows<T, N> &R, const T *__restrict__ D,
         T g1 = 0, g2 = 0, g3 = 0, g4 = 0, g5 = 0, g6 = 0;
         if (active) {
             const T *g = Ge + k * P2;
-            g1 = g[0 * P3]; g2 = g[1 * P3]; g3 = g[2 * P3];
-            g4 = g[3 * P3]; g5 = g[4 * P3]; g6 = g[5 * P3];
+            g1 = ld_stream(g + 0 * P3); g2 = ld_stream(g + 1 * P3); g3 = ld_stream(g + 2 * P3);
+            g4 = ld_stream(g + 3 * P3); g5 = ld_stream(g + 4 * P3); g6 = ld_stream(g + 5 * P3);
         }
         T wr = g1 * ur + g4 * us + g5 * ut;
         T ws = g2 * us + g4 * ur + g6 * ut;
         wt[k] = g3 * ut + g5 * ur + g6 * us;
         if (HELM) {
-            const T h = active ? h1[eb + ci.off(k)] : T(0);
+            const T h = active ? ld_stream(h1 + eb + ci.off(k)) : T(0);
             wr *= h;
             ws *= h;
             wt[k] *= h;
@@ -296,8 +335,8 @@ __device__ inline void ax_tile(const LaneRows<T, N> &R, const T *__restrict__ D,
 #pragma unroll
         for (int l = 0; l < P; ++l)
             acc += R.dti(l) * sr[k * P2 + j * P + l] + R.dtj(l) * ss[k * P2 + l * P + i] + R.dk(D, l, k) * wt[l];
-        if (HELM && active) acc += h2b[eb + ci.off(k)] * uc[k];
-        if (active) out[eb + ci.off(k)] = acc;
+        if (HELM && active) acc += ld_stream(h2b + eb + ci.off(k)) * uc[k];
+        if (active) st_stream(acc, out + eb + ci.off(k));
         if (MODE != 0) dot += (double)uc[k] * (double)acc;
     }
     __syncthreads();  // the LDS slot is rewritten by the next tile
@@ -344,22 +383,22 @@ __device__ inline void ax_node_tile(const NodeRows<T, N> &R, const T *__restrict
     T v = 0;
     if (active) {
         if (MODE == 2) {
-            const T pold = p[o];
+            const T pold = ld_stream(p + o);
             // the previous iteration's x step, deferred to here where p is read anyway
-            x[o] = x[o] + alpha * pold;
-            v = invdiag[o] * in[o] + beta * pold;
-            p[o] = v;
+            st_stream(ld_stream(x + o) + alpha * pold, x + o);
+            v = ld_stream(invdiag + o) * ld_stream(in + o) + beta * pold;
+            st_stream(v, p + o);
         } else {
-            v = in[o];
+            v = ld_stream(in + o);
         }
     }
     if (inblk) su[pt] = v;
     T g1 = 0, g2 = 0, g3 = 0, g4 = 0, g5 = 0, g6 = 0, h = 0;
     if (active) {
         const T *g = G + (active ? e : 0) * 6 * P3 + pt;
-        g1 = g[0 * P3]; g2 = g[1 * P3]; g3 = g[2 * P3];
-        g4 = g[3 * P3]; g5 = g[4 * P3]; g6 = g[5 * P3];
-        if (HELM) h = h1[o];
+        g1 = ld_stream(g + 0 * P3); g2 = ld_stream(g + 1 * P3); g3 = ld_stream(g + 2 * P3);
+        g4 = ld_stream(g + 3 * P3); g5 = ld_stream(g + 4 * P3); g6 = ld_stream(g + 5 * P3);
+        if (HELM) h = ld_stream(h1 + o);
     }
     __syncthreads();
     T ur = 0, us = 0, ut = 0;
@@ -389,8 +428,8 @@ __device__ inline void ax_node_tile(const NodeRows<T, N> &R, const T *__restrict
         acc += sD[l * P + i] * sr[l + P * j + P2 * k] + sD[l * P + j] * ss[i + P * l + P2 * k] +
                sD[l * P + k] * st[i + P * j + P2 * l];
     if (active) {
-        if (HELM) acc += h2b[o] * v;
-        out[o] = acc;
+        if (HELM) acc += ld_stream(h2b + o) * v;
+        st_stream(acc, out + o);
     }
     if (MODE != 0) dot += (double)v * (double)acc;
     __syncthreads();  // the LDS of this tile is rewritten by the next
