@@ -354,7 +354,8 @@ def batched_section(sem, torch, SI):
     res = {"meshes": len(meshes), "elements": int(sum(m.E for m in meshes)),
            "local_nodes": int(sum(m.n_local for m in meshes)), "global_nodes": int(sum(m.n_global for m in meshes)),
            "orders": sorted({m.N for m in meshes}), "setup_s": t_setup, "tune_s": t_tune,
-           "epw": {int(N): B.epw(N) for N in sorted({m.N for m in meshes})}}
+           "epw": {int(N): B.epw(N) for N in sorted({m.N for m in meshes})},
+           "epw_fp32": {int(N): B.epw(N, "fp32") for N in sorted({m.N for m in meshes})}}
     for prec in ("fp64", "mixed"):
         B.solve(meshes, bs, tol=1e-10, precision=prec, poll_every=16)   # warm-up (graph capture)
         torch.cuda.synchronize()

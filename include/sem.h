@@ -318,14 +318,17 @@ typedef struct sem_batch sem_batch;
 sem_status sem_batch_create(int max_slots, size_t device_budget, void *stream, sem_batch **out);
 sem_status sem_batch_free(sem_batch *batch);
 
-/* Autotuner: for every order among `meshes`, time the batched operator for
- * each candidate elements-per-workgroup and keep the fastest; then choose the
- * persistent grid size.  The batch must have no admitted slots. */
+/* Autotuner: for every order among `meshes` and each precision they carry,
+ * time the batched CG operator for each candidate elements-per-workgroup and
+ * keep the fastest.  The batch must have no admitted slots. */
 sem_status sem_batch_tune(sem_batch *batch, sem_mesh *const *meshes, int n, void *stream);
 /* Elements per operator workgroup for order N (epw (N+1)^2 <= 512; 0 restores
- * the default).  The batch must have no admitted slots (SEM_EINVAL). */
+ * the default), for the FP64 and the FP32 operator alike (the autotuner picks
+ * each precision's own).  The batch must have no admitted slots (SEM_EINVAL).
+ * sem_batch_get_epw reads the count in use for `precision` (SEM_FP64 or
+ * SEM_FP32). */
 sem_status sem_batch_set_epw(sem_batch *batch, int N, int epw);
-sem_status sem_batch_get_epw(const sem_batch *batch, int N, int *epw);
+sem_status sem_batch_get_epw(const sem_batch *batch, int N, int precision, int *epw);
 
 /* One-shot: solve A_i x_i = b_i for i < n together (b_i, x_i device FP64
  * E-vectors of mesh i; opts as for sem_pcg_solve, shared by all; stats: n

@@ -318,16 +318,18 @@ class Batch:
             pass
 
     def tune(self, meshes, stream=None):
-        """Autotune elements per workgroup per order (and the operator grid) on these meshes."""
+        """Autotune elements per workgroup per order and precision on these meshes."""
         arr = (C.c_void_p * len(meshes))(*[m._h.value for m in meshes])
         L.check(self._lib.sem_batch_tune(self._h, arr, len(meshes), _stream_handle(stream)), "sem_batch_tune")
 
     def set_epw(self, N: int, epw: int):
         L.check(self._lib.sem_batch_set_epw(self._h, int(N), int(epw)), "sem_batch_set_epw")
 
-    def epw(self, N: int) -> int:
+    def epw(self, N: int, precision: str = "fp64") -> int:
+        """Elements per operator workgroup in use for order N and precision ('fp64' or 'fp32')."""
         e = C.c_int()
-        L.check(self._lib.sem_batch_get_epw(self._h, int(N), C.byref(e)), "sem_batch_get_epw")
+        p = SEM_FP32 if precision == "fp32" else SEM_FP64
+        L.check(self._lib.sem_batch_get_epw(self._h, int(N), p, C.byref(e)), "sem_batch_get_epw")
         return e.value
 
     def solve(self, meshes, bs, xs=None, stream=None, raise_on_error: bool = True, **kw):

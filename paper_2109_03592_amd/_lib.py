@@ -85,7 +85,7 @@ SIGNATURES = {
     "sem_batch_free": (_i, [_vp]),
     "sem_batch_tune": (_i, [_vp, C.POINTER(_vp), _i, _vp]),
     "sem_batch_set_epw": (_i, [_vp, _i, _i]),
-    "sem_batch_get_epw": (_i, [_vp, _i, C.POINTER(_i)]),
+    "sem_batch_get_epw": (_i, [_vp, _i, _i, C.POINTER(_i)]),
     "sem_batch_solve": (_i, [_vp, C.POINTER(_vp), _i, C.POINTER(_vp), C.POINTER(_vp), C.POINTER(SolveOpts),
                              _vp, _vp]),
     "sem_batch_admit": (_i, [_vp, _vp, _vp, _vp, C.POINTER(SolveOpts), C.POINTER(_i), _vp]),

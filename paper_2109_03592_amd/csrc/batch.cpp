@@ -58,6 +58,7 @@ struct Group {
     std::vector<Item> h_ax, h_gs, h_vec;
     std::vector<int64_t> h_axf, h_axc, h_vf, h_vc;
     unsigned orders = 0;          // orders present in the tables
+    int prec = 0;                 // precision of the operator launches (tile sizes follow it)
     hipGraphExec_t graph = nullptr;
     int graph_k = 0;
     unsigned graph_orders = 0;    // orders the cached graph launches
@@ -91,7 +92,7 @@ struct sem_batch {
     sem::PcgState *d_state = nullptr;   // 2 per slot
     double *d_scal = nullptr;           // 2 per slot
     sem::Group g64, g32, gres;          // CG64, CG32, residual
-    int epw[SEM_MAX_ORDER + 1] = {0};   // elements per operator tile, per order
+    int epw[2][SEM_MAX_ORDER + 1] = {};  // elements per operator tile, per precision and order (0: default)
     sem::BatchLaunch L{};
     hipStream_t capture = nullptr;
     std::vector<void *> allocations;
@@ -127,12 +128,15 @@ static void *balloc(sem_batch *B, size_t bytes)
 
 // elements per operator tile: the single-mesh rule (fill whole waves)
 int default_operator_epw(int N, bool fp32);
-static int default_batch_epw(int N) { return default_operator_epw(N, false); }
 
-static int batch_epw(const sem_batch *B, int N) { return B->epw[N] > 0 ? B->epw[N] : default_batch_epw(N); }
-
-static void group_alloc(sem_batch *B, Group &g)
+static int batch_epw(const sem_batch *B, int N, int prec)
 {
+    return B->epw[prec][N] > 0 ? B->epw[prec][N] : default_operator_epw(N, prec == 1);
+}
+
+static void group_alloc(sem_batch *B, Group &g, int prec)
+{
+    g.prec = prec;
     const int ms = B->max_slots;
     g.slots = (int32_t *)balloc(B, sizeof(int32_t) * ms);
     g.counts = (int64_t *)balloc(B, sizeof(int64_t) * kCountSize);
@@ -195,7 +199,8 @@ static void group_build(sem_batch *B, Group &g, const std::vector<int> &ids, hip
         for (int id : ids) {
             const SlotDesc &d = B->h_desc[id];
             if (d.N != N) continue;
-            const int64_t nt = (d.E + d.epw - 1) / d.epw;
+            const int epw = batch_epw(B, N, g.prec);
+            const int64_t nt = (d.E + epw - 1) / epw;
             g.h_axf[id] = (int64_t)g.h_ax.size();
             g.h_axc[id] = nt;
             for (int64_t t = 0; t < nt; ++t) g.h_ax.push_back(Item{id, (int32_t)t});
@@ -232,15 +237,15 @@ static void group_build(sem_batch *B, Group &g, const std::vector<int> &ids, hip
     SEM_HIP(hipStreamSynchronize(s));
 }
 
-static BatchLaunch launch_for(sem_batch *B, unsigned orders)
+static BatchLaunch launch_for(sem_batch *B, unsigned orders, int prec)
 {
     BatchLaunch L = B->L;
     L.orders = orders;
-    for (int N = 0; N <= SEM_MAX_ORDER; ++N) L.epw[N] = N >= 1 ? batch_epw(B, N) : 1;
+    for (int N = 0; N <= SEM_MAX_ORDER; ++N) L.epw[N] = N >= 1 ? batch_epw(B, N, prec) : 1;
     return L;
 }
 
-static BatchLaunch launch_for(sem_batch *B, const Group &g) { return launch_for(B, g.orders); }
+static BatchLaunch launch_for(sem_batch *B, const Group &g) { return launch_for(B, g.orders, g.prec); }
 
 static void upload_desc(sem_batch *B, int id, hipStream_t s)
 {
@@ -251,7 +256,7 @@ static void upload_desc(sem_batch *B, int id, hipStream_t s)
 static void enqueue_batch_iters(sem_batch *B, Group &g, int prec, int k, unsigned orders, hipStream_t s)
 {
     const GroupDev gd = g.dev();
-    const BatchLaunch L = launch_for(B, orders);
+    const BatchLaunch L = launch_for(B, orders, g.prec);
     for (int it = 0; it < k; ++it) {
         SEM_HIP(batch_ax(prec, 2, B->d_desc, gd, L, s));
         SEM_HIP(batch_gs(prec, 1, B->d_desc, gd, L, s));
@@ -554,7 +559,6 @@ static int admit_slot(sem_batch *B, sem_mesh *m, const double *b, double *x, con
     std::memset(&d, 0, sizeof(d));
     const HostMesh &hm = m->h;
     d.N = hm.N;
-    d.epw = batch_epw(B, hm.N);
     d.E = hm.E;
     d.nL = hm.nL;
     d.G[0] = m->G64;
@@ -588,6 +592,9 @@ static int admit_slot(sem_batch *B, sem_mesh *m, const double *b, double *x, con
     d.st = B->d_state + 2 * id;
     d.scal = B->d_scal + 2 * id;
     SEM_HIP(hipMemsetAsync(d.st, 0, 2 * sizeof(PcgState), s));
+    // mixed slots start with a residual of the caller's x: zero it unless it
+    // is the initial guess (FP64 slots without a guess zero it themselves)
+    if (o.precision == SEM_PREC_MIXED && !o.x0_given) SEM_HIP(hipMemsetAsync(x, 0, sizeof(double) * hm.nL, s));
     upload_desc(B, id, s);
     return id;
 }
@@ -623,9 +630,9 @@ sem_status sem_batch_create(int max_slots, size_t device_budget, void *stream, s
             B->d_state = (PcgState *)balloc(B, sizeof(PcgState) * 2 * max_slots);
             B->d_scal = (double *)balloc(B, sizeof(double) * 2 * max_slots);
             SEM_HIP(hipMemsetAsync(B->d_state, 0, sizeof(PcgState) * 2 * max_slots, s));
-            group_alloc(B, B->g64);
-            group_alloc(B, B->g32);
-            group_alloc(B, B->gres);
+            group_alloc(B, B->g64, 0);
+            group_alloc(B, B->g32, 1);
+            group_alloc(B, B->gres, 0);
             const int cap = persistent_grid_cap_public();
             B->L.ax_grid = cap;
             B->L.vec_grid = cap;
@@ -785,64 +792,66 @@ sem_status sem_batch_tune(sem_batch *B, sem_mesh *const *meshes, int n, void *st
             hipFree(zx);
         };
         try {
-            auto time_group = [&](const std::vector<int> &grp) {
+            // time the CG operator (MODE 2) of a set of slots in precision prec
+            // (the slots' CG states are zero: beta = alpha = 0, not done)
+            auto time_group = [&](const std::vector<int> &grp, int prec) {
                 Group &g = B->gres;
+                g.prec = prec;
                 group_build(B, g, grp, s);
                 const GroupDev gd = g.dev();
                 const BatchLaunch Lc = launch_for(B, g);
-                SEM_HIP(batch_ax(0, 0, B->d_desc, gd, Lc, s));
-                SEM_HIP(hipEventRecord(e0, s));
-                for (int r = 0; r < 3; ++r) SEM_HIP(batch_ax(0, 0, B->d_desc, gd, Lc, s));
-                SEM_HIP(hipEventRecord(e1, s));
-                SEM_HIP(hipEventSynchronize(e1));
-                float ms = 0;
-                SEM_HIP(hipEventElapsedTime(&ms, e0, e1));
-                return (double)ms;
+                SEM_HIP(batch_ax(prec, 2, B->d_desc, gd, Lc, s));
+                // best of three runs of five launches
+                double best = 1e300;
+                for (int run = 0; run < 3; ++run) {
+                    SEM_HIP(hipEventRecord(e0, s));
+                    for (int r = 0; r < 5; ++r) SEM_HIP(batch_ax(prec, 2, B->d_desc, gd, Lc, s));
+                    SEM_HIP(hipEventRecord(e1, s));
+                    SEM_HIP(hipEventSynchronize(e1));
+                    float ms = 0;
+                    SEM_HIP(hipEventElapsedTime(&ms, e0, e1));
+                    best = std::min(best, (double)ms);
+                }
+                g.prec = 0;
+                return best;
             };
-            for (int i = 0; i < n; ++i) ids.push_back(admit_slot(B, meshes[i], zb, zx, o, s));
-            // elements per tile, one order at a time
+            bool all32 = true;
+            for (int i = 0; i < n; ++i) {
+                sem_solve_opts oi = o;
+                oi.precision = meshes[i]->with_fp32 ? SEM_PREC_MIXED : SEM_PREC_FP64;
+                all32 = all32 && meshes[i]->with_fp32;
+                ids.push_back(admit_slot(B, meshes[i], zb, zx, oi, s));
+            }
+            // elements per tile, one order and precision at a time
             for (int N = 1; N <= SEM_MAX_ORDER; ++N) {
                 std::vector<int> grp;
+                bool grp32 = true;
                 for (int id : ids)
-                    if (B->h_desc[id].N == N) grp.push_back(id);
+                    if (B->h_desc[id].N == N) {
+                        grp.push_back(id);
+                        grp32 = grp32 && B->slots[id].mesh->with_fp32;
+                    }
                 if (grp.empty()) continue;
                 const int P2 = (N + 1) * (N + 1), P3 = P2 * (N + 1);
-                int emax = (N >= 10 ? 256 : 512) / P2;
-                while (emax > 1 && (size_t)3 * emax * P3 * sizeof(double) > 150 * 1024) --emax;
-                double best = 1e300;
-                int best_e = default_batch_epw(N);
-                for (int e = 1; e <= emax; ++e) {
-                    if (emax > 8 && e != 1 && e != emax && (e & (e - 1)) != 0) continue;
-                    B->epw[N] = e;
-                    for (int id : grp) {
-                        B->h_desc[id].epw = e;
-                        upload_desc(B, id, s);
+                for (int prec = 0; prec < (grp32 ? 2 : 1); ++prec) {
+                    int emax = (N >= 10 ? 256 : 512) / P2;
+                    while (emax > 1 && (size_t)3 * emax * P3 * sizeof(double) > 150 * 1024) --emax;
+                    double best = 1e300;
+                    int best_e = default_operator_epw(N, prec == 1);
+                    for (int e = 1; e <= emax; ++e) {
+                        if (emax > 8 && e != 1 && e != emax && (e & (e - 1)) != 0 && e != best_e) continue;
+                        B->epw[prec][N] = e;
+                        const double t = time_group(grp, prec);
+                        if (t < best * 0.995) {
+                            best = t;
+                            best_e = e;
+                        }
                     }
-                    const double t = time_group(grp);
-                    if (t < best * 0.995) {
-                        best = t;
-                        best_e = e;
-                    }
-                }
-                B->epw[N] = best_e;
-                for (int id : grp) {
-                    B->h_desc[id].epw = best_e;
-                    upload_desc(B, id, s);
+                    B->epw[prec][N] = best_e;
                 }
             }
-            // persistent grid of the operator over the whole set
-            const int cap = persistent_grid_cap_public();
-            double best = 1e300;
-            int best_g = B->L.ax_grid;
-            for (int gsz : {cap / 8, cap / 4, cap / 2, cap}) {
-                B->L.ax_grid = std::max(64, gsz);
-                const double t = time_group(ids);
-                if (t < best * 0.995) {
-                    best = t;
-                    best_g = B->L.ax_grid;
-                }
-            }
-            B->L.ax_grid = best_g;
+            // (the persistent grid stays at its default: a grid tuned on one
+            // precision's launches underfills the GPU for the other's)
             for (Group *g : {&B->g64, &B->g32})
                 if (g->graph) {
                     hipGraphExecDestroy(g->graph);
@@ -866,7 +875,8 @@ sem_status sem_batch_set_epw(sem_batch *B, int N, int epw)
         if (epw < 0 || epw * P2 > 512) fail(SEM_EINVAL, "sem_batch_set_epw: epw out of range");
         for (int id = 0; id < B->max_slots; ++id)
             if (B->slots[id].phase != PH_FREE) fail(SEM_EINVAL, "sem_batch_set_epw: the batch must be empty");
-        B->epw[N] = epw;
+        B->epw[0][N] = epw;
+        B->epw[1][N] = epw;
         for (Group *g : {&B->g64, &B->g32})
             if (g->graph) {
                 hipGraphExecDestroy(g->graph);
@@ -876,11 +886,12 @@ sem_status sem_batch_set_epw(sem_batch *B, int N, int epw)
     });
 }
 
-sem_status sem_batch_get_epw(const sem_batch *B, int N, int *epw)
+sem_status sem_batch_get_epw(const sem_batch *B, int N, int precision, int *epw)
 {
     return bguard([&]() -> sem_status {
-        if (!B || !epw || N < 1 || N > SEM_MAX_ORDER) fail(SEM_EINVAL, "sem_batch_get_epw: bad arguments");
-        *epw = B->epw[N] > 0 ? B->epw[N] : default_batch_epw(N);
+        if (!B || !epw || N < 1 || N > SEM_MAX_ORDER || (precision != SEM_FP64 && precision != SEM_FP32))
+            fail(SEM_EINVAL, "sem_batch_get_epw: bad arguments");
+        *epw = batch_epw(B, N, precision == SEM_FP32 ? 1 : 0);
         return SEM_OK;
     });
 }

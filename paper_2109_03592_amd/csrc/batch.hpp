@@ -28,7 +28,7 @@ struct Item {
 
 struct SlotDesc {
     int N;
-    int epw;            // elements per operator tile
+    int pad;
     int64_t E, nL;
     const void *G[2];   // [0] FP64, [1] FP32 geometric factors [E][6][P^3]
     const void *inv[2]; // inverse assembled diagonal

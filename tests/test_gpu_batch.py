@@ -103,6 +103,23 @@ def test_continuous_batching(semlib, cases, oracle_mod):
     B.close()
 
 
+def test_batch_ignores_garbage_x_without_guess(semlib, cases, oracle_mod):
+    """Without an initial guess a slot starts from x = 0 whatever x holds
+    (FP64 and mixed)."""
+    print("case: batch x without initial guess", flush=True)
+    B = semlib.Batch(max_slots=2)
+    m, om, b = cases[1]
+    for prec in ("fp64", "mixed"):
+        x = torch.full((om.nloc,), float("nan"), dtype=torch.float64, device="cuda")
+        s = B.admit(m, torch.from_numpy(b).cuda(), x, tol=1e-10, precision=prec)
+        while s not in B.finished():
+            B.step(8)
+        xr, r = B.retire(s)
+        assert r.ok, (prec, r)
+        assert om.true_residual(b, xr.cpu().numpy()) <= 1e-10
+    B.close()
+
+
 def test_tuner_and_budget(semlib, cases):
     print("case: batch tuner and budget", flush=True)
     B = semlib.Batch(max_slots=16)
