@@ -247,7 +247,7 @@ void sem_solve_opts_default(sem_solve_opts *opts);
 
 /* Jacobi-PCG on the masked assembled system A x = b (section 2 Eq. 5 solved
  * by a preconditioned Krylov method; the preconditioner is the inverse
- * assembled diagonal).  b: device FP64 E-vector, continuous (all copies of a
+ * assembled diagonal, plus the coarse term of sem_set_coarse when set).  b: device FP64 E-vector, continuous (all copies of a
  * global node equal) and masked.  x: device FP64 E-vector, in/out.
  * FP64: dot products, alpha and beta stay on the device; the host reads the
  * residual every poll_every iterations.  When the recursive residual meets
@@ -260,6 +260,53 @@ void sem_solve_opts_default(sem_solve_opts *opts);
  * last iterate), SEM_EBREAKDOWN, SEM_EINVAL, SEM_EHIP. */
 sem_status sem_pcg_solve(sem_mesh *mesh, const double *b, double *x, const sem_solve_opts *opts,
                          sem_solve_stats *stats, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Two-level preconditioner (Eq. 6: a coarse term plus local solves; the local
+ * solves here are single nodes, i.e. Jacobi).  With a coarse space set, FP64
+ * solves (sem_pcg_solve, sem_proj_solve) use
+ *   M^{-1} r = D^{-1} r + P C(A0) P^T r
+ * where
+ *   - P holds the trilinear hat functions of the element vertices at the
+ *     GLL nodes (element reference coordinates), 0 at Dirichlet nodes;
+ *     periodic images of a vertex are one vertex;
+ *   - A0 = P^T A P (the masked assembled operator of the mesh's current form,
+ *     Poisson or Helmholtz), assembled from element blocks P_e^T A_e P_e;
+ *     vertices whose masked hat function is 0 are not coarse unknowns;
+ *   - C(A0) is `chebyshev_steps` steps of Chebyshev iteration for
+ *     D0^-1 A0 z = D0^-1 r0 from z = 0, D0 = diag(A0), on [a, b] with b the
+ *     largest absolute row sum of D0^-1 A0 and a = fraction * b: a fixed
+ *     polynomial, so M is symmetric positive definite.
+ * The coarse term runs inside the CG iteration: restriction, Chebyshev and
+ * the coarse part of <r, z> after the residual update, the prolongation in
+ * the operator's prologue (the column kernel; SEM_OPK_NODE is not used while
+ * a coarse space is set).  Mixed-precision solves fail with SEM_EUNSUPPORTED
+ * while it is set.
+ */
+typedef struct {
+    int64_t n_vertices;   /* element vertices (periodic images merged)          */
+    int64_t n_coarse;     /* coarse unknowns (vertices with a non-zero hat)      */
+    int64_t nnz;          /* stored entries of A0 (rows of coarse unknowns)      */
+    int chebyshev_steps;  /* 0: no coarse space (Jacobi only)                   */
+    double a, b;          /* Chebyshev interval of D0^-1 A0                      */
+} sem_coarse_info;
+
+/* Build (chebyshev_steps 1..1000, fraction in (0, 1)) or remove
+ * (chebyshev_steps 0) the coarse space of `mesh`.  The build applies the
+ * local operator to the 8 masked corner hat functions (FP64, on `stream`),
+ * assembles A0 on the host in a fixed order and keeps it on the device;
+ * sem_set_helmholtz and sem_load_geometry rebuild it for the new operator.
+ * Device memory: about 130 bytes per element and 380 per vertex, plus two
+ * temporary FP64 E-vectors during the build.  Synchronises `stream`.
+ * Errors: SEM_EINVAL (steps or fraction out of range, a zero coarse
+ * operator), SEM_EUNSUPPORTED (8 E >= 2^31), SEM_ENOMEM, SEM_EHIP. */
+sem_status sem_set_coarse(sem_mesh *mesh, int chebyshev_steps, double fraction, void *stream);
+sem_status sem_get_coarse_info(const sem_mesh *mesh, sem_coarse_info *info);
+
+/* z = M^{-1} r with the mesh's FP64 preconditioner (Jacobi, plus the coarse
+ * term when set).  r, z: distinct device FP64 E-vectors, r continuous; z is
+ * continuous and masked.  Asynchronous on `stream`. */
+sem_status sem_precond_apply(sem_mesh *mesh, const double *r, double *z, void *stream);
 
 /* ---------------------------------------------------------------------------
  * Projection onto previous solutions (section 2: successive solves of a time

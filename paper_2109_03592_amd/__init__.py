@@ -173,6 +173,27 @@ class Mesh:
                                             None if h2 is None else h2.data_ptr(), _stream_handle(stream)),
                 "sem_set_helmholtz")
 
+    def set_coarse(self, chebyshev_steps: int = 10, fraction: float = 0.01, stream=None):
+        """Add the coarse term of Eq. 6 to the FP64 preconditioner (Jacobi +
+        trilinear vertex space, A0 = P^T A P, chebyshev_steps Chebyshev steps
+        on [fraction b, b]); chebyshev_steps=0 removes it."""
+        L.check(self._lib.sem_set_coarse(self._h, int(chebyshev_steps), float(fraction), _stream_handle(stream)),
+                "sem_set_coarse")
+
+    def coarse_info(self) -> dict:
+        info = L.CoarseInfo()
+        L.check(self._lib.sem_get_coarse_info(self._h, C.byref(info)), "sem_get_coarse_info")
+        return {k: getattr(info, k) for k, _ in L.CoarseInfo._fields_}
+
+    def precond(self, r: torch.Tensor, z: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """z = M^-1 r (FP64 E-vectors): Jacobi, plus the coarse term when set."""
+        z = torch.empty_like(r) if z is None else z
+        pr, pz = self._vec(r, "r", torch.float64), self._vec(z, "z", torch.float64)
+        if pr == pz:
+            raise ValueError("precond: r and z must be distinct")
+        L.check(self._lib.sem_precond_apply(self._h, pr, pz, _stream_handle(stream)), "sem_precond_apply")
+        return z
+
     # -- operators -----------------------------------------------------------
     def ax(self, u: torch.Tensor, w: Optional[torch.Tensor] = None, dot: bool = False, stream=None):
         """w = A_L u (no gather-scatter); with dot=True also returns sum u.w (device scalar)."""

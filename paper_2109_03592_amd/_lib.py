@@ -50,6 +50,11 @@ class SolveStats(C.Structure):
                 ("operator_launches", C.c_int)]
 
 
+class CoarseInfo(C.Structure):
+    _fields_ = [("n_vertices", C.c_int64), ("n_coarse", C.c_int64), ("nnz", C.c_int64),
+                ("chebyshev_steps", C.c_int), ("a", C.c_double), ("b", C.c_double)]
+
+
 # name -> (restype, argtypes); kept in step with include/sem.h
 _vp, _i, _d = C.c_void_p, C.c_int, C.c_double
 SIGNATURES = {
@@ -68,6 +73,9 @@ SIGNATURES = {
     "sem_get_operator_config": (_i, [_vp, C.POINTER(_i), C.POINTER(_i)]),
     "sem_set_helmholtz": (_i, [_vp, _vp, _vp, _vp]),
     "sem_set_operator_kernel": (_i, [_vp, _i]),
+    "sem_set_coarse": (_i, [_vp, _i, _d, _vp]),
+    "sem_get_coarse_info": (_i, [_vp, C.POINTER(CoarseInfo)]),
+    "sem_precond_apply": (_i, [_vp, _vp, _vp, _vp]),
     "sem_get_operator_kernel": (_i, [_vp, C.POINTER(_i)]),
     "sem_proj_create": (_i, [_vp, _i, C.POINTER(_vp)]),
     "sem_proj_free": (_i, [_vp]),

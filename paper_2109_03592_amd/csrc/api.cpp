@@ -9,6 +9,7 @@
 #include <mutex>
 #include <new>
 
+#include "coarse.hpp"
 #include "kernels.hpp"
 #include "sem_internal.hpp"
 
@@ -203,13 +204,21 @@ static int op_epw(const sem_mesh *m)
     return sizeof(T) == 8 ? m->ax_epw : m->ax_epw32;
 }
 
+// the CG iteration of precision T runs the FP64 coarse-corrected operator (mode 3)
+template <typename T>
+static bool coarse_cg(const sem_mesh *m) { return sizeof(T) == 8 && m->coarse != nullptr; }
+
+// elements per workgroup of the CG operator launch (mode 3 runs the column kernel)
+template <typename T>
+static int cg_epw(const sem_mesh *m) { return coarse_cg<T>(m) ? m->ax_epw : op_epw<T>(m); }
+
 template <typename T>
 static void enqueue_ax(sem_mesh *m, int mode, const T *in, T *out, hipStream_t s)
 {
     AxParams<T> a{};
     a.E = m->h.E;
-    a.epw = op_epw<T>(m);
-    a.kind = m->op_kind;
+    a.epw = mode == 3 ? m->ax_epw : op_epw<T>(m);
+    a.kind = mode == 3 ? 0 : m->op_kind;
     a.grid_cap = m->ax_grid_cap;
     a.G = Prec<T>::G(m);
     a.in = in;
@@ -217,11 +226,18 @@ static void enqueue_ax(sem_mesh *m, int mode, const T *in, T *out, hipStream_t s
     a.partial = m->partials;
     a.h1 = Prec<T>::h1(m);
     a.h2b = Prec<T>::h2b(m);
-    if (mode == 2) {
+    if (mode >= 2) {
         a.invdiag = Prec<T>::inv(m);
         a.p = Prec<T>::p(m);
         a.x = Prec<T>::x(m);
         a.st = Prec<T>::st(m);
+    }
+    if constexpr (sizeof(T) == 8) {
+        if (mode == 3) {
+            a.evert = m->coarse->evert;
+            a.z0 = m->coarse->z0;
+            a.cq = m->coarse->qw;
+        }
     }
     SEM_HIP(launch_ax<T>(m->h.N, mode, a, s));
 }
@@ -274,18 +290,28 @@ template <typename T>
 static void enqueue_iterations(sem_mesh *m, int k, hipStream_t s, Profiler *prof = nullptr)
 {
     PcgState *st = Prec<T>::st(m);
-    const int64_t axb = ax_grid(m->h.E, op_epw<T>(m), m->ax_grid_cap);
+    const bool coarse = coarse_cg<T>(m);
+    const int64_t axb = ax_grid(m->h.E, cg_epw<T>(m), m->ax_grid_cap);
     const int64_t nL = m->h.nL;
+    const int64_t ub = update_blocks(nL);
     for (int it = 0; it < k; ++it) {
         if (prof) prof->mark(s);
-        enqueue_ax<T>(m, 2, Prec<T>::r(m), Prec<T>::w(m), s);
+        enqueue_ax<T>(m, coarse ? 3 : 2, Prec<T>::r(m), Prec<T>::w(m), s);
         if (prof) prof->mark(s);
         enqueue_gs<T>(m, Prec<T>::w(m), st, s);
         if (prof) prof->mark(s);
         SEM_HIP(launch_reduce_sigma(m->partials, axb, st, s));
         SEM_HIP(launch_pcg_update<T>(nL, st, Prec<T>::r(m), Prec<T>::w(m), Prec<T>::inv(m), m->mult, m->partials,
                                      s));
-        SEM_HIP(launch_reduce_rho(m->partials, update_blocks(nL), st, s));
+        int64_t pairs = ub;
+        if constexpr (sizeof(T) == 8) {
+            if (coarse) {
+                // <r, P z0> = <P^T r, z0>: the coarse solve's pairs follow the update's
+                coarse_enqueue(m, m->r64, m->partials + 2 * ub, st, s);
+                pairs += m->coarse->dot_blocks;
+            }
+        }
+        SEM_HIP(launch_reduce_rho(m->partials, pairs, st, s));
         if (prof) prof->mark(s);
     }
     if (prof) prof->flush(s);
@@ -299,7 +325,8 @@ static void run_iterations(sem_mesh *m, int k, bool use_graph, hipStream_t s, Pr
         return;
     }
     const int slot = sizeof(T) == 8 ? 0 : 1;
-    const int epw = op_epw<T>(m) + 1024 * m->op_kind;  // graph key: tile shape and kernel
+    // graph key: tile shape and kernel (a change of the coarse space drops the graphs)
+    const int epw = cg_epw<T>(m) + 1024 * (coarse_cg<T>(m) ? 2 : m->op_kind);
     if (!m->graph[slot] || m->graph_k[slot] != k || m->graph_epw[slot] != epw ||
         m->graph_grid[slot] != m->ax_grid_cap) {
         if (m->graph[slot]) {
@@ -329,6 +356,29 @@ static void run_iterations(sem_mesh *m, int k, bool use_graph, hipStream_t s, Pr
     SEM_HIP(hipGraphLaunch(m->graph[slot], s));
 }
 
+// cached CG graphs launch the operator and preconditioner they were captured with
+static void drop_graphs(sem_mesh *m, hipStream_t s)
+{
+    for (int q = 0; q < 2; ++q)
+        if (m->graph[q]) {
+            SEM_HIP(hipStreamSynchronize(s));
+            SEM_HIP(hipGraphExecDestroy(m->graph[q]));
+            m->graph[q] = nullptr;
+        }
+}
+
+// the coarse space follows the operator: rebuilt with the same parameters
+static void rebuild_coarse(sem_mesh *m, hipStream_t s)
+{
+    if (!m->coarse) return;
+    drop_graphs(m, s);
+    const int k = m->coarse->k;
+    const double frac = m->coarse->frac;
+    coarse_free(m->coarse);
+    m->coarse = nullptr;
+    m->coarse = coarse_build(m, k, frac, s);
+}
+
 static PcgState read_state(const PcgState *st, hipStream_t s)
 {
     PcgState h;
@@ -356,13 +406,31 @@ static void true_residual(sem_mesh *m, const double *b, hipStream_t s, int slot)
 
 // Plain CG loop on precision T from the current r (x, p set by the caller);
 // returns the final device state.
+// CG start from the current r: rho = <r, M^-1 r>, rr, flags; p = 0
+template <typename T>
+static void pcg_start(sem_mesh *m, double stop2, int limit, hipStream_t s)
+{
+    const int64_t nL = m->h.nL;
+    if constexpr (sizeof(T) == 8) {
+        if (coarse_cg<T>(m)) {
+            const int64_t vb = vec_blocks(nL);
+            SEM_HIP(launch_pcg_init_partials(nL, m->r64, m->inv64, m->mult, m->partials, s));
+            coarse_enqueue(m, m->r64, m->partials + 2 * vb, nullptr, s);
+            SEM_HIP(launch_reduce_init(m->partials, vb + m->coarse->dot_blocks, m->state, stop2, limit, s));
+            SEM_HIP(hipMemsetAsync(m->p64, 0, sizeof(double) * nL, s));
+            return;
+        }
+    }
+    SEM_HIP(launch_pcg_init<T>(nL, Prec<T>::r(m), Prec<T>::inv(m), m->mult, m->partials, Prec<T>::st(m), stop2,
+                               limit, s));
+    SEM_HIP(hipMemsetAsync(Prec<T>::p(m), 0, sizeof(T) * nL, s));
+}
+
 template <typename T>
 static PcgState cg_loop(sem_mesh *m, double stop2, int limit, int poll, bool graph, hipStream_t s,
                         Profiler *prof = nullptr)
 {
-    SEM_HIP(launch_pcg_init<T>(m->h.nL, Prec<T>::r(m), Prec<T>::inv(m), m->mult, m->partials, Prec<T>::st(m), stop2,
-                               limit, s));
-    SEM_HIP(hipMemsetAsync(Prec<T>::p(m), 0, sizeof(T) * m->h.nL, s));
+    pcg_start<T>(m, stop2, limit, s);
     PcgState hs = read_state(Prec<T>::st(m), s);
     while (!hs.done) {
         run_iterations<T>(m, poll, graph, s, prof);
@@ -388,8 +456,7 @@ static sem_status solve_fp64(sem_mesh *m, const double *b, double *x, const sem_
         // throughput mode: exactly fixed_iters iterations from the current x
         if (o.x0_given) true_residual(m, b, s, 1);
         else SEM_HIP(hipMemcpyAsync(m->r64, b, sizeof(double) * nL, hipMemcpyDeviceToDevice, s));
-        SEM_HIP(launch_pcg_init<double>(nL, m->r64, m->inv64, m->mult, m->partials, m->state, -1.0, o.fixed_iters, s));
-        SEM_HIP(hipMemsetAsync(m->p64, 0, sizeof(double) * nL, s));
+        pcg_start<double>(m, -1.0, o.fixed_iters, s);
         int left = o.fixed_iters;
         Profiler prof;
         prof.m = m;
@@ -475,6 +542,8 @@ static sem_status solve_mixed(sem_mesh *m, const double *b, double *x, const sem
                               hipStream_t s)
 {
     if (!m->with_fp32) fail(SEM_EINVAL, "sem_pcg_solve: mixed precision needs SEM_WITH_FP32 at set-up");
+    if (m->coarse)
+        fail(SEM_EUNSUPPORTED, "sem_pcg_solve: the coarse term applies to FP64 solves (remove it for mixed precision)");
     const int64_t nL = m->h.nL;
     ensure_solve_space(m, true);
     SEM_HIP(launch_dot_unique<double>(nL, b, b, m->mult, m->partials, m->scal, s));
@@ -579,8 +648,10 @@ sem_status sem_setup(const sem_mesh_desc *desc, void *stream, sem_mesh **out)
             m->gs_off = dalloc<int32_t>(m, h.gs_off.size());
             m->gs_idx = dalloc<int32_t>(m, h.gs_idx.size());
             m->ax_grid_cap = persistent_grid_cap();
+            // + room for the coarse dot's pairs behind the CG partial pairs
             const int64_t np = std::max<int64_t>(std::max<int64_t>(m->ax_grid_cap, 65536),
-                                                2 * (int64_t)std::max(vec_blocks(nL), update_blocks(nL))) + 64;
+                                                2 * (int64_t)std::max(vec_blocks(nL), update_blocks(nL))) +
+                               2 * kMaxCoarseDotBlocks + 64;
             m->partials = dalloc<double>(m, np);
             m->n_partials = np;
             m->state = dalloc<PcgState>(m, 2);
@@ -622,6 +693,7 @@ sem_status sem_free(sem_mesh *m)
     for (int q = 0; q < 2; ++q)
         if (m->graph[q]) hipGraphExecDestroy(m->graph[q]);
     if (m->capture_stream) hipStreamDestroy(m->capture_stream);
+    coarse_free(m->coarse);
     for (hipEvent_t e : m->events) hipEventDestroy(e);
     for (void *p : m->allocations) hipFree(p);
     delete m;
@@ -781,13 +853,10 @@ sem_status sem_load_geometry(sem_mesh *m, const double *G, const double *B, void
         m->op_version++;
         if (m->helm) {
             // h2*B was formed with the old B: back to the Poisson form
-            for (int q = 0; q < 2; ++q)
-                if (m->graph[q]) {
-                    SEM_HIP(hipGraphExecDestroy(m->graph[q]));
-                    m->graph[q] = nullptr;
-                }
+            drop_graphs(m, s);
             m->helm = 0;
         }
+        rebuild_coarse(m, s);
         return SEM_OK;
     });
 }
@@ -845,13 +914,7 @@ sem_status sem_set_helmholtz(sem_mesh *m, const double *h1, const double *h2, vo
         if (!m) fail(SEM_EINVAL, "sem_set_helmholtz: null mesh");
         hipStream_t s = (hipStream_t)stream;
         const int64_t nL = m->h.nL;
-        // cached CG graphs launch the operator of the current form
-        for (int q = 0; q < 2; ++q)
-            if (m->graph[q]) {
-                SEM_HIP(hipStreamSynchronize(s));
-                SEM_HIP(hipGraphExecDestroy(m->graph[q]));
-                m->graph[q] = nullptr;
-            }
+        drop_graphs(m, s);
         const bool helm = h1 || h2;
         if (helm && !m->h1_64) {
             m->h1_64 = dalloc<double>(m, nL);
@@ -888,6 +951,7 @@ sem_status sem_set_helmholtz(sem_mesh *m, const double *h1, const double *h2, vo
         SEM_HIP(hipFree(diag));
         m->helm = helm ? 1 : 0;
         m->op_version++;
+        rebuild_coarse(m, s);
         return SEM_OK;
     });
 }
@@ -954,6 +1018,50 @@ sem_status sem_scatter(sem_mesh *m, const double *v_global, double *u_local, voi
         SEM_HIP(launch_scatter(m->h.nL, m->gid, v_global, u_local, s));
         // masked ids only: every copy set to 0
         SEM_HIP(launch_gs<double>(m->gsplan, m->gs_off, m->gs_idx, u_local, true, nullptr, s));
+        return SEM_OK;
+    });
+}
+
+sem_status sem_set_coarse(sem_mesh *m, int steps, double fraction, void *stream)
+{
+    return guarded([&]() -> sem_status {
+        if (!m) fail(SEM_EINVAL, "sem_set_coarse: null mesh");
+        if (steps < 0 || steps > 1000) fail(SEM_EINVAL, "sem_set_coarse: chebyshev_steps must be 0..1000");
+        if (steps > 0 && !(fraction > 0.0 && fraction < 1.0))
+            fail(SEM_EINVAL, "sem_set_coarse: fraction must be in (0, 1)");
+        hipStream_t s = (hipStream_t)stream;
+        drop_graphs(m, s);
+        SEM_HIP(hipStreamSynchronize(s));
+        coarse_free(m->coarse);
+        m->coarse = nullptr;
+        if (steps > 0) m->coarse = coarse_build(m, steps, fraction, s);
+        return SEM_OK;
+    });
+}
+
+sem_status sem_get_coarse_info(const sem_mesh *m, sem_coarse_info *info)
+{
+    return guarded([&]() -> sem_status {
+        if (!m || !info) fail(SEM_EINVAL, "sem_get_coarse_info: null argument");
+        std::memset(info, 0, sizeof(*info));
+        if (const CoarseSpace *C = m->coarse) {
+            info->n_vertices = C->nvert;
+            info->n_coarse = C->n_coarse;
+            info->nnz = C->nnz;
+            info->chebyshev_steps = C->k;
+            info->a = C->a;
+            info->b = C->b;
+        }
+        return SEM_OK;
+    });
+}
+
+sem_status sem_precond_apply(sem_mesh *m, const double *r, double *z, void *stream)
+{
+    return guarded([&]() -> sem_status {
+        if (!m || !r || !z) fail(SEM_EINVAL, "sem_precond_apply: null argument");
+        if (r == z) fail(SEM_EINVAL, "sem_precond_apply: r and z must be distinct");
+        precond_apply(m, r, z, (hipStream_t)stream);
         return SEM_OK;
     });
 }

@@ -1,0 +1,444 @@
+// coarse.hip -- the coarse term of Eq. 6 on the GPU: a two-level
+// preconditioner M^{-1} r = D^{-1} r + P C(A0) P^T r for FP64 CG.
+//
+//  * P: trilinear hat functions of the element vertices at the GLL nodes (in
+//    each element's reference coordinates), zero at Dirichlet nodes.
+//  * A0 = P^T A P, assembled on the host from per-element 8x8 blocks
+//    P_e^T A_e P_e; each block column is the local operator applied to one
+//    masked hat function, tested against the eight hats.
+//  * C(A0): k steps of Chebyshev iteration for D0^-1 A0 z = D0^-1 r0 from 0
+//    on [frac b, b], b the largest absolute row sum of D0^-1 A0 -- a fixed
+//    polynomial, so M stays linear and symmetric positive definite.
+//  * Restriction P^T r: per element, eight weighted sums over its nodes
+//    (1/mult for unique-node sums), then per vertex the sum of its element
+//    corners in a fixed order.  Prolongation: folded into the CG operator's
+//    prologue (p = D^-1 r + P z0 + beta p), or added to a vector.
+//  * The coarse part of <r, z> is r0 . z0, appended to the CG partials.
+// Dirichlet nodes are the nodes whose inverse diagonal is 0.
+#include <algorithm>
+#include <cmath>
+#include <utility>
+#include <vector>
+
+#include "coarse.hpp"
+#include "kernels.hpp"
+#include "operator.hpp"
+
+namespace sem {
+
+// ---------------------------------------------------------------------------
+// device kernels
+
+// node q of an element: (i, j, k) and the eight hat weights
+__device__ inline void hat_weights(const double *__restrict__ qw, int P, int q, double (&phi)[8])
+{
+    const int i = q % P, j = (q / P) % P, k = q / (P * P);
+    const double ai[2] = {qw[i], qw[P + i]}, aj[2] = {qw[j], qw[P + j]}, ak[2] = {qw[k], qw[P + k]};
+#pragma unroll
+    for (int c = 0; c < 8; ++c) phi[c] = ai[c & 1] * aj[(c >> 1) & 1] * ak[(c >> 2) & 1];
+}
+
+// u = masked hat function of corner c on every element (element-local vector)
+__global__ __launch_bounds__(256) void hat_kernel(int64_t E, int P, const double *__restrict__ qw, int c,
+                                                  const double *__restrict__ inv, double *__restrict__ u)
+{
+    const int P3 = P * P * P;
+    const int64_t n = E * P3;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+        double phi[8];
+        hat_weights(qw, P, (int)(q % P3), phi);
+        u[q] = inv[q] > 0.0 ? phi[c] : 0.0;
+    }
+}
+
+// One wavefront per element: s[c] = sum over the element's live nodes of
+// phi_c * f (f = the element's slice of a vector, scaled by w when given);
+// every lane ends with the eight totals (butterfly, fixed order).
+__device__ inline void wave_hat_sums(int P, const double *__restrict__ sqw, const double *__restrict__ f,
+                                     const uint8_t *__restrict__ mult, const double *__restrict__ inv,
+                                     double (&s)[8])
+{
+    const int P3 = P * P * P, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) s[c] = 0.0;
+    for (int q = lane; q < P3; q += 64) {
+        double v = inv[q] > 0.0 ? f[q] : 0.0;
+        if (mult) v /= (double)mult[q];
+        double phi[8];
+        hat_weights(sqw, P, q, phi);
+#pragma unroll
+        for (int c = 0; c < 8; ++c) s[c] += phi[c] * v;
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+        for (int off = 32; off > 0; off >>= 1) s[c] += __shfl_xor(s[c], off, 64);
+}
+
+__device__ inline double pick8(const double (&s)[8], int c)
+{
+    double out = s[0];
+#pragma unroll
+    for (int q = 1; q < 8; ++q)
+        if (c == q) out = s[q];
+    return out;
+}
+
+// E8[e][c'][c] = sum over element e's live nodes of phi_c' * w, w = A_e u_c
+__global__ __launch_bounds__(256) void elem_coarse_kernel(int64_t E, int P, const double *__restrict__ w,
+                                                          const double *__restrict__ qw,
+                                                          const double *__restrict__ inv, int c,
+                                                          double *__restrict__ E8)
+{
+    __shared__ double sqw[2 * (SEM_MAX_ORDER + 1)];
+    if (threadIdx.x < 2 * P) sqw[threadIdx.x] = qw[threadIdx.x];
+    __syncthreads();
+    const int P3 = P * P * P, lane = threadIdx.x & 63;
+    for (int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); e < E; e += (int64_t)gridDim.x * 4) {
+        double s[8];
+        wave_hat_sums(P, sqw, w + e * P3, nullptr, inv + e * P3, s);
+        const double v = pick8(s, lane);
+        if (lane < 8) E8[e * 64 + lane * 8 + c] = v;
+    }
+}
+
+// partial8[e*8 + c] = sum over element e's live nodes of phi_c r / mult
+__global__ __launch_bounds__(256) void restrict_elem_kernel(int64_t E, int P, const double *__restrict__ r,
+                                                            const uint8_t *__restrict__ mult,
+                                                            const double *__restrict__ inv,
+                                                            const double *__restrict__ qw,
+                                                            double *__restrict__ partial8,
+                                                            const PcgState *__restrict__ st)
+{
+    if (st && st->done) return;
+    __shared__ double sqw[2 * (SEM_MAX_ORDER + 1)];
+    if (threadIdx.x < 2 * P) sqw[threadIdx.x] = qw[threadIdx.x];
+    __syncthreads();
+    const int P3 = P * P * P, lane = threadIdx.x & 63;
+    for (int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); e < E; e += (int64_t)gridDim.x * 4) {
+        double s[8];
+        wave_hat_sums(P, sqw, r + e * P3, mult + e * P3, inv + e * P3, s);
+        const double v = pick8(s, lane);
+        if (lane < 8) partial8[e * 8 + lane] = v;
+    }
+}
+
+// r0[v] = sum of v's element corners (ascending element, corner); then the
+// Chebyshev start: z = 0, res = r0, d = D0^-1 r0 / theta
+__global__ __launch_bounds__(256) void restrict_vert_kernel(int64_t nv, const int32_t *__restrict__ v_off,
+                                                            const int32_t *__restrict__ v_idx,
+                                                            const double *__restrict__ partial8,
+                                                            const double *__restrict__ d0inv, double inv_theta,
+                                                            double *__restrict__ r0, double *__restrict__ z,
+                                                            double *__restrict__ res, double *__restrict__ d,
+                                                            const PcgState *__restrict__ st)
+{
+    if (st && st->done) return;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int32_t q = v_off[v]; q < v_off[v + 1]; ++q) s += partial8[v_idx[q]];
+        r0[v] = s;
+        z[v] = 0.0;
+        res[v] = s;
+        d[v] = s * d0inv[v] * inv_theta;
+    }
+}
+
+__global__ __launch_bounds__(256) void spmv_kernel(int64_t nv, const int32_t *__restrict__ off,
+                                                   const int32_t *__restrict__ col, const double *__restrict__ val,
+                                                   const double *__restrict__ x, double *__restrict__ y,
+                                                   const PcgState *__restrict__ st)
+{
+    if (st && st->done) return;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int32_t q = off[v]; q < off[v + 1]; ++q) s += val[q] * x[col[q]];
+        y[v] = s;
+    }
+}
+
+// z += d; res -= A0 d; d = c1 d + c2 D0^-1 res
+__global__ __launch_bounds__(256) void cheb_step_kernel(int64_t nv, double c1, double c2,
+                                                        const double *__restrict__ d0inv,
+                                                        const double *__restrict__ Ad, double *__restrict__ z,
+                                                        double *__restrict__ res, double *__restrict__ d,
+                                                        const PcgState *__restrict__ st)
+{
+    if (st && st->done) return;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x) {
+        const double dv = d[v];
+        z[v] += dv;
+        const double rv = res[v] - Ad[v];
+        res[v] = rv;
+        d[v] = c1 * dv + c2 * rv * d0inv[v];
+    }
+}
+
+// pairs (0, sum r0 z0) per workgroup, appended to the CG partials
+__global__ __launch_bounds__(256) void coarse_dot_kernel(int64_t nv, const double *__restrict__ r0,
+                                                         const double *__restrict__ z,
+                                                         double *__restrict__ partial,
+                                                         const PcgState *__restrict__ st)
+{
+    if (st && st->done) return;
+    double s = 0.0;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x)
+        s += r0[v] * z[v];
+    double p[2] = {0.0, s};
+    block_reduce_store<2>(p, partial, 2);
+}
+
+// z += masked P z0
+__global__ __launch_bounds__(256) void prolong_add_kernel(int64_t E, int P, const int32_t *__restrict__ evert,
+                                                          const double *__restrict__ z0,
+                                                          const double *__restrict__ qw,
+                                                          const double *__restrict__ inv, double *__restrict__ z)
+{
+    const int P3 = P * P * P;
+    const int64_t n = E * P3;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+        if (!(inv[q] > 0.0)) continue;
+        const int64_t e = q / P3;
+        double phi[8];
+        hat_weights(qw, P, (int)(q - e * P3), phi);
+        double s = 0.0;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) s += phi[c] * z0[evert[e * 8 + c]];
+        z[q] += s;
+    }
+}
+
+__global__ void jacobi_kernel(int64_t n, const double *__restrict__ inv, const double *__restrict__ r,
+                              double *__restrict__ z)
+{
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
+        z[q] = inv[q] * r[q];
+}
+
+// ---------------------------------------------------------------------------
+// host side
+
+static int cgrid(int64_t n, int cap) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, cap)); }
+
+template <typename X>
+static X *cmalloc(CoarseSpace *C, size_t count)
+{
+    void *p = nullptr;
+    SEM_HIP(hipMalloc(&p, std::max<size_t>(count * sizeof(X), 16)));
+    C->allocations.push_back(p);
+    return static_cast<X *>(p);
+}
+
+void coarse_free(CoarseSpace *C)
+{
+    if (!C) return;
+    for (void *p : C->allocations) hipFree(p);
+    delete C;
+}
+
+CoarseSpace *coarse_build(sem_mesh *m, int k, double frac, hipStream_t s)
+{
+    const HostMesh &h = m->h;
+    const int N = h.N, P = N + 1;
+    const int64_t E = h.E, P3 = (int64_t)P * P * P, nL = h.nL;
+    if (k < 1 || k > 1000) fail(SEM_EINVAL, "sem_set_coarse: chebyshev_steps must be 1..1000");
+    if (!(frac > 0.0 && frac < 1.0)) fail(SEM_EINVAL, "sem_set_coarse: fraction must be in (0, 1)");
+    if (E * 8 >= INT32_MAX) fail(SEM_EUNSUPPORTED, "sem_set_coarse: too many elements");
+    CoarseSpace *C = new CoarseSpace();
+    try {
+        C->k = k;
+        C->frac = frac;
+        const int nx = h.nel[0], ny = h.nel[1], nz = h.nel[2];
+        const int vd[3] = {nx + 1 - h.periodic[0], ny + 1 - h.periodic[1], nz + 1 - h.periodic[2]};
+        C->nvert = (int64_t)vd[0] * vd[1] * vd[2];
+        // element corners -> vertices
+        std::vector<int32_t> evert((size_t)E * 8);
+        for (int64_t e = 0; e < E; ++e) {
+            const int64_t ex = e % nx, ey = (e / nx) % ny, ez = e / ((int64_t)nx * ny);
+            for (int c = 0; c < 8; ++c) {
+                const int64_t a = (ex + (c & 1)) % vd[0], b = (ey + ((c >> 1) & 1)) % vd[1],
+                              cc = (ez + ((c >> 2) & 1)) % vd[2];
+                evert[e * 8 + c] = (int32_t)(a + vd[0] * (b + (int64_t)vd[1] * cc));
+            }
+        }
+        // vertex -> (element, corner) entries, ascending
+        std::vector<int32_t> v_off((size_t)C->nvert + 1, 0), v_idx((size_t)E * 8);
+        for (int64_t q = 0; q < E * 8; ++q) v_off[evert[q] + 1]++;
+        for (int64_t v = 0; v < C->nvert; ++v) v_off[v + 1] += v_off[v];
+        {
+            std::vector<int32_t> cur(v_off.begin(), v_off.end() - 1);
+            for (int64_t q = 0; q < E * 8; ++q) v_idx[cur[evert[q]]++] = (int32_t)q;
+        }
+        // 1-D hat weights at the GLL nodes
+        std::vector<double> qw(2 * P);
+        for (int i = 0; i < P; ++i) {
+            qw[i] = 0.5 * (1.0 - h.xi[i]);
+            qw[P + i] = 0.5 * (1.0 + h.xi[i]);
+        }
+        C->evert = cmalloc<int32_t>(C, evert.size());
+        C->v_off = cmalloc<int32_t>(C, v_off.size());
+        C->v_idx = cmalloc<int32_t>(C, v_idx.size());
+        C->qw = cmalloc<double>(C, qw.size());
+        SEM_HIP(hipMemcpyAsync(C->evert, evert.data(), sizeof(int32_t) * evert.size(), hipMemcpyHostToDevice, s));
+        SEM_HIP(hipMemcpyAsync(C->v_off, v_off.data(), sizeof(int32_t) * v_off.size(), hipMemcpyHostToDevice, s));
+        SEM_HIP(hipMemcpyAsync(C->v_idx, v_idx.data(), sizeof(int32_t) * v_idx.size(), hipMemcpyHostToDevice, s));
+        SEM_HIP(hipMemcpyAsync(C->qw, qw.data(), sizeof(double) * qw.size(), hipMemcpyHostToDevice, s));
+        // element blocks P_e^T A_e P_e with the mesh's current operator
+        std::vector<double> E8((size_t)E * 64);
+        {
+            double *u = nullptr, *w = nullptr, *dE8 = nullptr;
+            SEM_HIP(hipMalloc(&u, sizeof(double) * nL));
+            SEM_HIP(hipMalloc(&w, sizeof(double) * nL));
+            SEM_HIP(hipMalloc(&dE8, sizeof(double) * E * 64));
+            try {
+                for (int c = 0; c < 8; ++c) {
+                    hipLaunchKernelGGL(hat_kernel, dim3(vec_blocks(nL)), dim3(256), 0, s, E, P, C->qw, c, m->inv64, u);
+                    SEM_HIP(hipGetLastError());
+                    const sem_status st = sem_ax(m, SEM_FP64, u, w, nullptr, s);
+                    if (st != SEM_OK) fail(st, "sem_set_coarse: operator apply failed");
+                    hipLaunchKernelGGL(elem_coarse_kernel, dim3(cgrid(E * 64, 8192)), dim3(256), 0, s, E, P, w,
+                                       C->qw, m->inv64, c, dE8);
+                    SEM_HIP(hipGetLastError());
+                }
+                SEM_HIP(hipMemcpyAsync(E8.data(), dE8, sizeof(double) * E * 64, hipMemcpyDeviceToHost, s));
+                SEM_HIP(hipStreamSynchronize(s));
+            } catch (...) {
+                hipFree(u);
+                hipFree(w);
+                hipFree(dE8);
+                throw;
+            }
+            SEM_HIP(hipFree(u));
+            SEM_HIP(hipFree(w));
+            SEM_HIP(hipFree(dE8));
+        }
+        // A0 rows: sum of the element blocks of the vertex's corners, ascending
+        std::vector<int32_t> off((size_t)C->nvert + 1, 0), col;
+        std::vector<double> val, diag((size_t)C->nvert, 0.0);
+        col.reserve((size_t)C->nvert * 27);
+        val.reserve((size_t)C->nvert * 27);
+        // entries of a row are summed in the order of its element corners
+        std::vector<std::pair<int32_t, double>> row;
+        row.reserve(64);
+        for (int64_t v = 0; v < C->nvert; ++v) {
+            row.clear();
+            for (int32_t q = v_off[v]; q < v_off[v + 1]; ++q) {
+                const int64_t e = v_idx[q] / 8, cr = v_idx[q] % 8;
+                for (int c = 0; c < 8; ++c) row.emplace_back(evert[e * 8 + c], E8[e * 64 + cr * 8 + c]);
+            }
+            std::stable_sort(row.begin(), row.end(),
+                             [](const std::pair<int32_t, double> &x, const std::pair<int32_t, double> &y) {
+                                 return x.first < y.first;
+                             });
+            const size_t start = col.size();
+            for (size_t q = 0; q < row.size(); ++q) {
+                if (q == 0 || row[q].first != row[q - 1].first) {
+                    col.push_back(row[q].first);
+                    val.push_back(row[q].second);
+                } else {
+                    val.back() += row[q].second;
+                }
+                if (row[q].first == (int32_t)v) diag[v] = val.back();
+            }
+            if (!(diag[v] > 0.0)) {  // not a coarse unknown: empty row
+                col.resize(start);
+                val.resize(start);
+            }
+            off[v + 1] = (int32_t)col.size();
+        }
+        // vertices whose masked hat is zero are not coarse unknowns: drop their columns
+        std::vector<double> d0inv((size_t)C->nvert, 0.0);
+        for (int64_t v = 0; v < C->nvert; ++v)
+            if (diag[v] > 0.0) d0inv[v] = 1.0 / diag[v];
+        double bmax = 0.0;
+        for (int64_t v = 0; v < C->nvert; ++v) {
+            if (!(diag[v] > 0.0)) continue;
+            double sabs = 0.0;
+            for (int32_t q = off[v]; q < off[v + 1]; ++q) {
+                if (!(diag[col[q]] > 0.0)) val[q] = 0.0;
+                sabs += std::fabs(val[q]);
+            }
+            bmax = std::max(bmax, sabs * d0inv[v]);
+        }
+        if (!(bmax > 0.0)) fail(SEM_EINVAL, "sem_set_coarse: the coarse operator is zero");
+        C->b = bmax;
+        C->a = frac * bmax;
+        C->n_coarse = 0;
+        for (int64_t v = 0; v < C->nvert; ++v) C->n_coarse += diag[v] > 0.0;
+        C->nnz = (int64_t)col.size();
+        C->a_off = cmalloc<int32_t>(C, off.size());
+        C->a_col = cmalloc<int32_t>(C, std::max<size_t>(col.size(), 1));
+        C->a_val = cmalloc<double>(C, std::max<size_t>(val.size(), 1));
+        C->d0inv = cmalloc<double>(C, d0inv.size());
+        SEM_HIP(hipMemcpyAsync(C->a_off, off.data(), sizeof(int32_t) * off.size(), hipMemcpyHostToDevice, s));
+        if (!col.empty()) {
+            SEM_HIP(hipMemcpyAsync(C->a_col, col.data(), sizeof(int32_t) * col.size(), hipMemcpyHostToDevice, s));
+            SEM_HIP(hipMemcpyAsync(C->a_val, val.data(), sizeof(double) * val.size(), hipMemcpyHostToDevice, s));
+        }
+        SEM_HIP(hipMemcpyAsync(C->d0inv, d0inv.data(), sizeof(double) * d0inv.size(), hipMemcpyHostToDevice, s));
+        // Chebyshev coefficients
+        const double theta = 0.5 * (C->b + C->a), delta = 0.5 * (C->b - C->a), sigma = theta / delta;
+        C->inv_theta = 1.0 / theta;
+        double rho = 1.0 / sigma;
+        C->c1.resize(k);
+        C->c2.resize(k);
+        for (int j = 0; j < k; ++j) {
+            const double rho_new = 1.0 / (2.0 * sigma - rho);
+            C->c1[j] = rho_new * rho;
+            C->c2[j] = 2.0 * rho_new / delta;
+            rho = rho_new;
+        }
+        C->r0 = cmalloc<double>(C, C->nvert);
+        C->z0 = cmalloc<double>(C, C->nvert);
+        C->res = cmalloc<double>(C, C->nvert);
+        C->d = cmalloc<double>(C, C->nvert);
+        C->tmp = cmalloc<double>(C, C->nvert);
+        C->partial8 = cmalloc<double>(C, (size_t)E * 8);
+        C->dot_blocks = cgrid(C->nvert, kMaxCoarseDotBlocks);
+        SEM_HIP(hipMemsetAsync(C->z0, 0, sizeof(double) * C->nvert, s));
+        SEM_HIP(hipStreamSynchronize(s));
+    } catch (...) {
+        coarse_free(C);
+        throw;
+    }
+    return C;
+}
+
+void coarse_enqueue(sem_mesh *m, const double *r, double *partial_pairs, const PcgState *st, hipStream_t s)
+{
+    CoarseSpace *C = m->coarse;
+    const int64_t E = m->h.E, nv = C->nvert;
+    const int P = m->h.N + 1;
+    hipLaunchKernelGGL(restrict_elem_kernel, dim3(cgrid(E * 64, 8192)), dim3(256), 0, s, E, P, r, m->mult, m->inv64,
+                       C->qw, C->partial8, st);
+    SEM_HIP(hipGetLastError());
+    const int vg = cgrid(nv, 4096);
+    hipLaunchKernelGGL(restrict_vert_kernel, dim3(vg), dim3(256), 0, s, nv, C->v_off, C->v_idx, C->partial8, C->d0inv,
+                       C->inv_theta, C->r0, C->z0, C->res, C->d, st);
+    SEM_HIP(hipGetLastError());
+    for (int j = 0; j < C->k; ++j) {
+        hipLaunchKernelGGL(spmv_kernel, dim3(vg), dim3(256), 0, s, nv, C->a_off, C->a_col, C->a_val, C->d, C->tmp, st);
+        hipLaunchKernelGGL(cheb_step_kernel, dim3(vg), dim3(256), 0, s, nv, C->c1[j], C->c2[j], C->d0inv, C->tmp,
+                           C->z0, C->res, C->d, st);
+    }
+    SEM_HIP(hipGetLastError());
+    if (partial_pairs) {
+        hipLaunchKernelGGL(coarse_dot_kernel, dim3(C->dot_blocks), dim3(256), 0, s, nv, C->r0, C->z0, partial_pairs,
+                           st);
+        SEM_HIP(hipGetLastError());
+    }
+}
+
+void precond_apply(sem_mesh *m, const double *r, double *z, hipStream_t s)
+{
+    CoarseSpace *C = m->coarse;
+    const int64_t nL = m->h.nL;
+    hipLaunchKernelGGL(jacobi_kernel, dim3(vec_blocks(nL)), dim3(256), 0, s, nL, m->inv64, r, z);
+    SEM_HIP(hipGetLastError());
+    if (!C) return;
+    coarse_enqueue(m, r, nullptr, nullptr, s);
+    hipLaunchKernelGGL(prolong_add_kernel, dim3(vec_blocks(nL)), dim3(256), 0, s, m->h.E, m->h.N + 1, C->evert, C->z0,
+                       C->qw, m->inv64, z);
+    SEM_HIP(hipGetLastError());
+}
+
+}  // namespace sem

@@ -1,0 +1,48 @@
+// coarse.hpp -- the coarse term of Eq. 6 (coarse.hip): vertex space, the
+// assembled coarse operator and its Chebyshev solve, on the device.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "sem_internal.hpp"
+
+namespace sem {
+
+constexpr int kMaxCoarseDotBlocks = 1024;  // partial pairs of the coarse dot, at most
+
+struct CoarseSpace {
+    int k = 0;               // Chebyshev steps
+    double frac = 0.0;       // a = frac * b
+    double a = 0.0, b = 0.0; // Chebyshev interval of D0^-1 A0
+    double inv_theta = 0.0;
+    std::vector<double> c1, c2;  // per-step Chebyshev coefficients
+    int64_t nvert = 0;       // element vertices (periodic images merged)
+    int64_t n_coarse = 0;    // vertices with a non-zero masked hat function
+    int64_t nnz = 0;
+    int dot_blocks = 0;      // workgroups of the coarse dot (partial pairs)
+    // device
+    int32_t *evert = nullptr;   // [E][8] vertex of each element corner
+    int32_t *v_off = nullptr;   // [nvert+1] vertex -> element-corner entries
+    int32_t *v_idx = nullptr;   //   e*8 + c, ascending
+    double *qw = nullptr;       // [2][N+1] 1-D hat weights at the GLL nodes
+    int32_t *a_off = nullptr, *a_col = nullptr;  // A0, CSR
+    double *a_val = nullptr;
+    double *d0inv = nullptr;    // [nvert] 1/diag(A0), 0 where the vertex is not a coarse unknown
+    double *partial8 = nullptr; // [E][8] element restriction sums
+    double *r0 = nullptr, *z0 = nullptr, *res = nullptr, *d = nullptr, *tmp = nullptr;
+    std::vector<void *> allocations;
+};
+
+// Builds the coarse space of the mesh's current operator (synchronises s).
+CoarseSpace *coarse_build(sem_mesh *m, int k, double frac, hipStream_t s);
+void coarse_free(CoarseSpace *C);
+// z0 = C(A0) P^T r, and when partial_pairs is given, (0, r0.z0) pairs per
+// workgroup there (C->dot_blocks of them); kernels skip when st->done.
+void coarse_enqueue(sem_mesh *m, const double *r, double *partial_pairs, const PcgState *st, hipStream_t s);
+// z = D^-1 r (+ P C(A0) P^T r when the coarse space is set)
+void precond_apply(sem_mesh *m, const double *r, double *z, hipStream_t s);
+
+}  // namespace sem

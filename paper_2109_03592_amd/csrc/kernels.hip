@@ -28,7 +28,7 @@ __global__ __launch_bounds__(512) void ax_kernel(AxParams<T> a)
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *sm = reinterpret_cast<T *>(smem_raw);
 
-    if (MODE == 2 && a.st->done) return;
+    if (MODE >= 2 && a.st->done) return;
 
     const int tid = threadIdx.x;
     const int el = tid / P2;
@@ -42,7 +42,7 @@ __global__ __launch_bounds__(512) void ax_kernel(AxParams<T> a)
     LaneRows<T, N> R;
     R.load(D, i, j, sDt);
     T beta = 0, alpha = 0;
-    if (MODE == 2) {
+    if (MODE >= 2) {
         beta = (T)a.st->beta;
         alpha = (T)a.st->alpha;
     }
@@ -53,7 +53,7 @@ __global__ __launch_bounds__(512) void ax_kernel(AxParams<T> a)
         const int64_t e = tile * a.epw + el;
         const bool active = inblk && e < a.E;
         ax_tile<T, N, MODE, 0, HELM>(R, D, su, e, active, inblk, i, j, a.G, a.in, a.out, a.invdiag, a.p, beta, a.x,
-                                     alpha, dot, a.h1, a.h2b);
+                                     alpha, dot, a.h1, a.h2b, a.evert, a.z0, a.cq);
     }
     if (MODE != 0) {
         double v[1] = {dot};
@@ -498,7 +498,12 @@ static hipError_t launch_ax_node(int N, const AxParams<T> &a, hipStream_t s)
 template <typename T, int MODE, bool HELM>
 static hipError_t launch_ax_mode(int N, const AxParams<T> &a, hipStream_t s)
 {
-    if (a.kind == 1) return launch_ax_node<T, MODE, HELM>(N, a, s);
+    if constexpr (MODE == 3) {
+        // the coarse correction runs in the FP64 column kernel only
+        if (sizeof(T) != 8 || a.kind != 0 || !a.evert || !a.z0 || !a.cq) return hipErrorInvalidValue;
+    } else {
+        if (a.kind == 1) return launch_ax_node<T, MODE, HELM>(N, a, s);
+    }
     static const size_t lds_cap = max_dynamic_lds();
     const int threads = ax_block_threads(N, a.epw);
     const size_t lds = ax_lds_bytes(N, a.epw, sizeof(T));
@@ -518,6 +523,13 @@ static hipError_t launch_ax_mode(int N, const AxParams<T> &a, hipStream_t s)
 template <typename T>
 hipError_t launch_ax(int N, int mode, const AxParams<T> &a, hipStream_t s)
 {
+    if (mode == 3) {
+        if constexpr (sizeof(T) == 8) {
+            if (a.h1) return launch_ax_mode<T, 3, true>(N, a, s);
+            return launch_ax_mode<T, 3, false>(N, a, s);
+        }
+        return hipErrorInvalidValue;
+    }
     if (a.h1) {
         if (mode == 0) return launch_ax_mode<T, 0, true>(N, a, s);
         if (mode == 1) return launch_ax_mode<T, 1, true>(N, a, s);
@@ -633,6 +645,18 @@ hipError_t launch_pcg_init(int64_t n, const T *r, const T *inv, const uint8_t *m
 }
 template hipError_t launch_pcg_init<double>(int64_t, const double *, const double *, const uint8_t *, double *,
                                             PcgState *, double, int, hipStream_t);
+hipError_t launch_pcg_init_partials(int64_t n, const double *r, const double *inv, const uint8_t *mult,
+                                    double *partial, hipStream_t s)
+{
+    hipLaunchKernelGGL((pcg_init_kernel<double>), dim3(vec_blocks(n)), dim3(256), 0, s, n, r, inv, mult, partial);
+    return hipGetLastError();
+}
+hipError_t launch_reduce_init(const double *partial, int64_t pairs, PcgState *st, double stop2, int limit,
+                              hipStream_t s)
+{
+    hipLaunchKernelGGL(reduce_init_kernel, dim3(1), dim3(1024), 0, s, partial, pairs, st, stop2, limit);
+    return hipGetLastError();
+}
 template hipError_t launch_pcg_init<float>(int64_t, const float *, const float *, const uint8_t *, double *,
                                            PcgState *, double, int, hipStream_t);
 

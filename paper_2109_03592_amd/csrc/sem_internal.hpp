@@ -82,6 +82,8 @@ struct DeviceBuf {
     size_t bytes = 0;
 };
 
+struct CoarseSpace;  // coarse.hpp
+
 }  // namespace sem
 
 struct sem_mesh {
@@ -105,6 +107,8 @@ struct sem_mesh {
     int op_version = 0;  // bumped whenever the operator changes (projection bases follow it)
     double *h1_64 = nullptr, *h2b64 = nullptr;
     float *h1_32 = nullptr, *h2b32 = nullptr;
+    // coarse term of the FP64 preconditioner (sem_set_coarse); nullptr: Jacobi
+    sem::CoarseSpace *coarse = nullptr;
     // Krylov work space, allocated on the first solve
     double *x64 = nullptr, *r64 = nullptr, *p64 = nullptr, *w64 = nullptr;
     float *x32 = nullptr, *r32 = nullptr, *p32 = nullptr, *w32 = nullptr;
