@@ -259,6 +259,62 @@ def helmholtz_section(mesh, b, args, torch, SI, stream):
     return r
 
 
+def coarse_section(mesh, b, args, torch, stream, jacobi_solve=None):
+    """Two-level preconditioner (Jacobi + the coarse term of Eq. 6) on the
+    same mesh and right-hand side: coarse-space build time, profiled PCG
+    iterations and a full FP64 solve to 1e-10 per (Chebyshev steps, interval
+    fraction) setting; the mesh is back on Jacobi afterwards."""
+    nG = mesh.n_global
+    rows = []
+    for item in args.coarse.split(","):
+        k, frac = item.split(":")
+        k, frac = int(k), float(frac)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mesh.set_coarse(k, frac)
+        t_build = time.perf_counter() - t0
+        info = mesh.coarse_info()
+        x = mesh.zeros()
+        mesh.solve(b, x, fixed_iters=max(1, args.warmup), profile=True, initial_guess=False)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        _, res = mesh.solve(b, x, fixed_iters=args.steps, profile=True, initial_guess=False)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t_it = e0.elapsed_time(e1) / 1e3 / args.steps
+        n = max(1, res.operator_launches)
+        e0.record(stream)
+        mesh.solve(b, x, fixed_iters=args.steps, use_graph=True, poll_every=25, initial_guess=False)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t_graph = e0.elapsed_time(e1) / 1e3 / args.steps
+        x = mesh.zeros()
+        torch.cuda.synchronize()
+        tS = time.perf_counter()
+        _, r = mesh.solve(b, x, tol=1e-10, max_iter=40000, poll_every=50, initial_guess=False,
+                          raise_on_error=False)
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - tS
+        row = {"chebyshev_steps": k, "fraction": frac, "n_vertices": info["n_vertices"],
+               "n_coarse": info["n_coarse"], "nnz": info["nnz"], "cheb_a": info["a"], "cheb_b": info["b"],
+               "build_s": t_build, "ms_per_iteration": t_it * 1e3, "ms_per_iteration_graph": t_graph * 1e3,
+               "ms_operator": res.ms_operator / n, "ms_gather_scatter": res.ms_gather_scatter / n,
+               "ms_update_and_coarse": res.ms_update / n,
+               "solve": {"status": r.status, "iterations": r.iterations, "rel_residual": r.rel_residual,
+                         "seconds": ts}}
+        if jacobi_solve:
+            row["speedup_vs_jacobi"] = jacobi_solve["seconds"] / ts
+            row["iteration_ratio_vs_jacobi"] = jacobi_solve["iterations"] / max(1, r.iterations)
+        log(f"coarse k={k} a={frac}b: build {t_build:.2f} s, {info['n_coarse']} coarse unknowns; "
+            f"{t_it * 1e3:.3f} ms/iteration ({t_graph * 1e3:.3f} graph; operator {row['ms_operator']:.3f}, "
+            f"update+coarse {row['ms_update_and_coarse']:.3f}); solve status={r.status} iters={r.iterations} "
+            f"rel_res={r.rel_residual:.2e} {ts:.2f} s")
+        rows.append(row)
+    mesh.set_coarse(0)
+    return rows
+
+
 def sweep(sem, torch, SI, orders, sizes, applies: int = 20):
     """Ax+gs apply rate against order N and element count E on jittered boxes
     (the analogue of the paper's Nekbone sweeps, section 3): FP64 and FP32,
@@ -413,6 +469,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-mesh solves")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
     ap.add_argument("--no-helm", action="store_true", help="skip the Helmholtz-form timing")
+    ap.add_argument("--coarse", default="10:0.01,30:0.002",
+                    help="two-level preconditioner settings steps:fraction[,...] ('' skips)")
     ap.add_argument("--no-proj", action="store_true", help="skip the successive-RHS projection timing")
     ap.add_argument("--no-n9", action="store_true", help="skip the N=9 pipe (48x48x48)")
     ap.add_argument("--operator-kernel", choices=("column", "node"), default=None,
@@ -546,6 +604,11 @@ def main():
                 sol[prec]["rel_diff_vs_fp64"] = err
         sol["mixed_speedup"] = sol["fp64"]["seconds"] / sol["mixed"]["seconds"]
         out["solve"] = sol
+
+    # ---- Jacobi + coarse term of Eq. 6 on the same mesh and right-hand side ----
+    if args.coarse:
+        out["coarse"] = coarse_section(mesh, b, args, torch, stream,
+                                       out.get("solve", {}).get("fp64"))
 
     # ---- Helmholtz form (h1-weighted stiffness + h2 B) on the same mesh ------
     if not args.no_helm:

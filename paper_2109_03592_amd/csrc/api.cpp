@@ -301,16 +301,18 @@ static void enqueue_iterations(sem_mesh *m, int k, hipStream_t s, Profiler *prof
         enqueue_gs<T>(m, Prec<T>::w(m), st, s);
         if (prof) prof->mark(s);
         SEM_HIP(launch_reduce_sigma(m->partials, axb, st, s));
-        SEM_HIP(launch_pcg_update<T>(nL, st, Prec<T>::r(m), Prec<T>::w(m), Prec<T>::inv(m), m->mult, m->partials,
-                                     s));
         int64_t pairs = ub;
         if constexpr (sizeof(T) == 8) {
             if (coarse) {
-                // <r, P z0> = <P^T r, z0>: the coarse solve's pairs follow the update's
-                coarse_enqueue(m, m->r64, m->partials + 2 * ub, st, s);
-                pairs += m->coarse->dot_blocks;
+                // restriction fused into the update; <r, P z0> = <P^T r, z0>: the
+                // coarse solve's pairs follow the update's
+                pairs = coarse_update(m, st, m->partials, s);
+                pairs += coarse_solve(m, m->partials + 2 * pairs, st, s);
             }
         }
+        if (!coarse)
+            SEM_HIP(launch_pcg_update<T>(nL, st, Prec<T>::r(m), Prec<T>::w(m), Prec<T>::inv(m), m->mult, m->partials,
+                                         s));
         SEM_HIP(launch_reduce_rho(m->partials, pairs, st, s));
         if (prof) prof->mark(s);
     }
@@ -415,8 +417,9 @@ static void pcg_start(sem_mesh *m, double stop2, int limit, hipStream_t s)
         if (coarse_cg<T>(m)) {
             const int64_t vb = vec_blocks(nL);
             SEM_HIP(launch_pcg_init_partials(nL, m->r64, m->inv64, m->mult, m->partials, s));
-            coarse_enqueue(m, m->r64, m->partials + 2 * vb, nullptr, s);
-            SEM_HIP(launch_reduce_init(m->partials, vb + m->coarse->dot_blocks, m->state, stop2, limit, s));
+            coarse_restrict(m, m->r64, s);
+            const int64_t cb = coarse_solve(m, m->partials + 2 * vb, nullptr, s);
+            SEM_HIP(launch_reduce_init(m->partials, vb + cb, m->state, stop2, limit, s));
             SEM_HIP(hipMemsetAsync(m->p64, 0, sizeof(double) * nL, s));
             return;
         }

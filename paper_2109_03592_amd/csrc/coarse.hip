@@ -101,25 +101,98 @@ __global__ __launch_bounds__(256) void elem_coarse_kernel(int64_t E, int P, cons
     }
 }
 
-// partial8[e*8 + c] = sum over element e's live nodes of phi_c r / mult
-__global__ __launch_bounds__(256) void restrict_elem_kernel(int64_t E, int P, const double *__restrict__ r,
+// Hat-function sums at compile-time order: node q = i + P j + P^2 k of an
+// element adds v phi_c(q) to s[c], phi_c = a[cx][i] a[cy][j] a[cz][k]
+// (c = cx + 2 cy + 4 cz, a[side][.] the 1-D weights in LDS).
+template <int N>
+__device__ inline void hat_add(const double *__restrict__ sqw, int q, double v, double (&s)[8])
+{
+    constexpr int P = N + 1, P2 = P * P;
+    const int i = q % P, j = (q / P) % P, k = q / P2;
+    const double ai0 = sqw[i], ai1 = sqw[P + i];
+    const double aj0 = sqw[j], aj1 = sqw[P + j], ak0 = sqw[k], ak1 = sqw[P + k];
+    const double t00 = aj0 * ak0 * v, t10 = aj1 * ak0 * v, t01 = aj0 * ak1 * v, t11 = aj1 * ak1 * v;
+    s[0] += ai0 * t00; s[1] += ai1 * t00; s[2] += ai0 * t10; s[3] += ai1 * t10;
+    s[4] += ai0 * t01; s[5] += ai1 * t01; s[6] += ai0 * t11; s[7] += ai1 * t11;
+}
+
+// butterfly over the wavefront: every lane ends with the eight totals
+__device__ inline void wave_sum8(double (&s)[8])
+{
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+        for (int off = 32; off > 0; off >>= 1) s[c] += __shfl_xor(s[c], off, 64);
+}
+
+// partial8[e*8 + c] = sum over element e's live nodes of phi_c r / mult;
+// one wavefront per element
+template <int N>
+__global__ __launch_bounds__(256) void restrict_elem_kernel(int64_t E, const double *__restrict__ r,
                                                             const uint8_t *__restrict__ mult,
                                                             const double *__restrict__ inv,
                                                             const double *__restrict__ qw,
-                                                            double *__restrict__ partial8,
-                                                            const PcgState *__restrict__ st)
+                                                            double *__restrict__ partial8)
 {
-    if (st && st->done) return;
-    __shared__ double sqw[2 * (SEM_MAX_ORDER + 1)];
+    constexpr int P = N + 1, P3 = P * P * P;
+    __shared__ double sqw[2 * P];
     if (threadIdx.x < 2 * P) sqw[threadIdx.x] = qw[threadIdx.x];
     __syncthreads();
-    const int P3 = P * P * P, lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63;
     for (int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); e < E; e += (int64_t)gridDim.x * 4) {
-        double s[8];
-        wave_hat_sums(P, sqw, r + e * P3, mult + e * P3, inv + e * P3, s);
-        const double v = pick8(s, lane);
-        if (lane < 8) partial8[e * 8 + lane] = v;
+        double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        const int64_t base = e * P3;
+#pragma unroll
+        for (int q = lane; q < P3; q += 64) {
+            const double iv = ld_stream(inv + base + q);
+            const double v = iv > 0.0 ? ld_stream(r + base + q) / (double)mult[base + q] : 0.0;
+            hat_add<N>(sqw, q, v, s);
+        }
+        wave_sum8(s);
+        const double out = pick8(s, lane);
+        if (lane < 8) partial8[e * 8 + lane] = out;
     }
+}
+
+// CG update with the coarse restriction fused in (FP64): r -= alpha w, the
+// partial pairs of <r,r> and <r, invdiag r> per workgroup, and the element
+// restriction sums of the new r; one wavefront per element.
+template <int N>
+__global__ __launch_bounds__(256) void update_restrict_kernel(int64_t E, const PcgState *__restrict__ st,
+                                                              double *__restrict__ r, const double *__restrict__ w,
+                                                              const double *__restrict__ inv,
+                                                              const uint8_t *__restrict__ mult,
+                                                              const double *__restrict__ qw,
+                                                              double *__restrict__ partial,
+                                                              double *__restrict__ partial8)
+{
+    constexpr int P = N + 1, P3 = P * P * P;
+    if (st->done) return;
+    __shared__ double sqw[2 * P];
+    if (threadIdx.x < 2 * P) sqw[threadIdx.x] = qw[threadIdx.x];
+    __syncthreads();
+    const double alpha = st->alpha;
+    const int lane = threadIdx.x & 63;
+    double rr = 0.0, rz = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); e < E; e += (int64_t)gridDim.x * 4) {
+        double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        const int64_t base = e * P3;
+#pragma unroll
+        for (int q = lane; q < P3; q += 64) {
+            const int64_t o = base + q;
+            const double rv = ld_stream(r + o) - alpha * ld_stream(w + o);
+            st_stream(rv, r + o);
+            const double iv = ld_stream(inv + o);
+            const double im = 1.0 / (double)ld_stream(mult + o);
+            rr += rv * rv * im;
+            rz += rv * (iv * rv) * im;
+            hat_add<N>(sqw, q, iv > 0.0 ? rv * im : 0.0, s);
+        }
+        wave_sum8(s);
+        const double out = pick8(s, lane);
+        if (lane < 8) partial8[e * 8 + lane] = out;
+    }
+    double v[2] = {rr, rz};
+    block_reduce_store<2>(v, partial, 2);
 }
 
 // r0[v] = sum of v's element corners (ascending element, corner); then the
@@ -143,48 +216,46 @@ __global__ __launch_bounds__(256) void restrict_vert_kernel(int64_t nv, const in
     }
 }
 
-__global__ __launch_bounds__(256) void spmv_kernel(int64_t nv, const int32_t *__restrict__ off,
+// One Chebyshev step, eight lanes per row of A0 (its entries read
+// contiguously, summed by a fixed butterfly):
+//   z += d_in; res -= A0 d_in; d_out = c1 d_in + c2 D0^-1 res.
+// LAST: no d_out; (0, sum r0 z) pairs per workgroup into `partial` when given.
+template <bool LAST>
+__global__ __launch_bounds__(256) void cheb_kernel(int64_t nv, const int32_t *__restrict__ off,
                                                    const int32_t *__restrict__ col, const double *__restrict__ val,
-                                                   const double *__restrict__ x, double *__restrict__ y,
+                                                   double c1, double c2, const double *__restrict__ d0inv,
+                                                   const double *__restrict__ din, double *__restrict__ dout,
+                                                   double *__restrict__ z, double *__restrict__ res,
+                                                   const double *__restrict__ r0, double *__restrict__ partial,
                                                    const PcgState *__restrict__ st)
 {
     if (st && st->done) return;
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x) {
+    const int sub = threadIdx.x & 7;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    double dot = 0.0;
+    // wave-uniform trip count: the butterfly runs on full wavefronts
+    for (int64_t t0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); t0 < nv * 8; t0 += stride) {
+        const int64_t v = (t0 + (threadIdx.x & 63)) >> 3;
         double s = 0.0;
-        for (int32_t q = off[v]; q < off[v + 1]; ++q) s += val[q] * x[col[q]];
-        y[v] = s;
+        if (v < nv)
+            for (int32_t q = off[v] + sub; q < off[v + 1]; q += 8) s += val[q] * din[col[q]];
+        s += __shfl_xor(s, 4, 64);
+        s += __shfl_xor(s, 2, 64);
+        s += __shfl_xor(s, 1, 64);
+        if (v < nv && sub == 0) {
+            const double dv = din[v];
+            const double zv = z[v] + dv;
+            z[v] = zv;
+            const double rv = res[v] - s;
+            res[v] = rv;
+            if (!LAST) dout[v] = c1 * dv + c2 * rv * d0inv[v];
+            else dot += r0[v] * zv;
+        }
     }
-}
-
-// z += d; res -= A0 d; d = c1 d + c2 D0^-1 res
-__global__ __launch_bounds__(256) void cheb_step_kernel(int64_t nv, double c1, double c2,
-                                                        const double *__restrict__ d0inv,
-                                                        const double *__restrict__ Ad, double *__restrict__ z,
-                                                        double *__restrict__ res, double *__restrict__ d,
-                                                        const PcgState *__restrict__ st)
-{
-    if (st && st->done) return;
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x) {
-        const double dv = d[v];
-        z[v] += dv;
-        const double rv = res[v] - Ad[v];
-        res[v] = rv;
-        d[v] = c1 * dv + c2 * rv * d0inv[v];
+    if (LAST && partial) {
+        double p[2] = {0.0, dot};
+        block_reduce_store<2>(p, partial, 2);
     }
-}
-
-// pairs (0, sum r0 z0) per workgroup, appended to the CG partials
-__global__ __launch_bounds__(256) void coarse_dot_kernel(int64_t nv, const double *__restrict__ r0,
-                                                         const double *__restrict__ z,
-                                                         double *__restrict__ partial,
-                                                         const PcgState *__restrict__ st)
-{
-    if (st && st->done) return;
-    double s = 0.0;
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x)
-        s += r0[v] * z[v];
-    double p[2] = {0.0, s};
-    block_reduce_store<2>(p, partial, 2);
 }
 
 // z += masked P z0
@@ -393,7 +464,7 @@ CoarseSpace *coarse_build(sem_mesh *m, int k, double frac, hipStream_t s)
         C->d = cmalloc<double>(C, C->nvert);
         C->tmp = cmalloc<double>(C, C->nvert);
         C->partial8 = cmalloc<double>(C, (size_t)E * 8);
-        C->dot_blocks = cgrid(C->nvert, kMaxCoarseDotBlocks);
+        C->dot_blocks = cgrid(C->nvert * 8, kMaxCoarseDotBlocks);
         SEM_HIP(hipMemsetAsync(C->z0, 0, sizeof(double) * C->nvert, s));
         SEM_HIP(hipStreamSynchronize(s));
     } catch (...) {
@@ -403,29 +474,64 @@ CoarseSpace *coarse_build(sem_mesh *m, int k, double frac, hipStream_t s)
     return C;
 }
 
-void coarse_enqueue(sem_mesh *m, const double *r, double *partial_pairs, const PcgState *st, hipStream_t s)
+// launches F<N> for the mesh's order
+#define SEM_COARSE_ORDER_SWITCH(N, CALL)                                                                  \
+    switch (N) {                                                                                       \
+    case 1: CALL(1); break;  case 2: CALL(2); break;   case 3: CALL(3); break;   case 4: CALL(4); break;  \
+    case 5: CALL(5); break;  case 6: CALL(6); break;   case 7: CALL(7); break;   case 8: CALL(8); break;  \
+    case 9: CALL(9); break;  case 10: CALL(10); break; case 11: CALL(11); break; case 12: CALL(12); break; \
+    default: fail(SEM_EUNSUPPORTED, "coarse term: order out of range");                               \
+    }
+
+static int elem_blocks(int64_t E) { return (int)std::max<int64_t>(1, std::min<int64_t>((E + 3) / 4, 8192)); }
+
+int coarse_update(sem_mesh *m, const PcgState *st, double *partial, hipStream_t s)
 {
     CoarseSpace *C = m->coarse;
-    const int64_t E = m->h.E, nv = C->nvert;
-    const int P = m->h.N + 1;
-    hipLaunchKernelGGL(restrict_elem_kernel, dim3(cgrid(E * 64, 8192)), dim3(256), 0, s, E, P, r, m->mult, m->inv64,
-                       C->qw, C->partial8, st);
+    const int64_t E = m->h.E;
+    const int blocks = elem_blocks(E);
+#define SEM_UPD(n)                                                                                                \
+    hipLaunchKernelGGL(update_restrict_kernel<n>, dim3(blocks), dim3(256), 0, s, E, st, m->r64, m->w64, m->inv64, \
+                       m->mult, C->qw, partial, C->partial8)
+    SEM_COARSE_ORDER_SWITCH(m->h.N, SEM_UPD)
+#undef SEM_UPD
     SEM_HIP(hipGetLastError());
-    const int vg = cgrid(nv, 4096);
-    hipLaunchKernelGGL(restrict_vert_kernel, dim3(vg), dim3(256), 0, s, nv, C->v_off, C->v_idx, C->partial8, C->d0inv,
-                       C->inv_theta, C->r0, C->z0, C->res, C->d, st);
+    return blocks;
+}
+
+void coarse_restrict(sem_mesh *m, const double *r, hipStream_t s)
+{
+    CoarseSpace *C = m->coarse;
+    const int64_t E = m->h.E;
+#define SEM_RES(n)                                                                                              \
+    hipLaunchKernelGGL(restrict_elem_kernel<n>, dim3(elem_blocks(E)), dim3(256), 0, s, E, r, m->mult, m->inv64, \
+                       C->qw, C->partial8)
+    SEM_COARSE_ORDER_SWITCH(m->h.N, SEM_RES)
+#undef SEM_RES
     SEM_HIP(hipGetLastError());
+}
+
+int coarse_solve(sem_mesh *m, double *dot_pairs, const PcgState *st, hipStream_t s)
+{
+    CoarseSpace *C = m->coarse;
+    const int64_t nv = C->nvert;
+    hipLaunchKernelGGL(restrict_vert_kernel, dim3(cgrid(nv, 4096)), dim3(256), 0, s, nv, C->v_off, C->v_idx,
+                       C->partial8, C->d0inv, C->inv_theta, C->r0, C->z0, C->res, C->d, st);
+    SEM_HIP(hipGetLastError());
+    double *din = C->d, *dout = C->tmp;
     for (int j = 0; j < C->k; ++j) {
-        hipLaunchKernelGGL(spmv_kernel, dim3(vg), dim3(256), 0, s, nv, C->a_off, C->a_col, C->a_val, C->d, C->tmp, st);
-        hipLaunchKernelGGL(cheb_step_kernel, dim3(vg), dim3(256), 0, s, nv, C->c1[j], C->c2[j], C->d0inv, C->tmp,
-                           C->z0, C->res, C->d, st);
+        if (j + 1 < C->k) {
+            hipLaunchKernelGGL(cheb_kernel<false>, dim3(C->dot_blocks), dim3(256), 0, s, nv, C->a_off, C->a_col,
+                               C->a_val, C->c1[j], C->c2[j], C->d0inv, din, dout, C->z0, C->res, C->r0, nullptr, st);
+            std::swap(din, dout);
+        } else {
+            hipLaunchKernelGGL(cheb_kernel<true>, dim3(C->dot_blocks), dim3(256), 0, s, nv, C->a_off, C->a_col,
+                               C->a_val, C->c1[j], C->c2[j], C->d0inv, din, dout, C->z0, C->res, C->r0, dot_pairs,
+                               st);
+        }
     }
     SEM_HIP(hipGetLastError());
-    if (partial_pairs) {
-        hipLaunchKernelGGL(coarse_dot_kernel, dim3(C->dot_blocks), dim3(256), 0, s, nv, C->r0, C->z0, partial_pairs,
-                           st);
-        SEM_HIP(hipGetLastError());
-    }
+    return C->dot_blocks;
 }
 
 void precond_apply(sem_mesh *m, const double *r, double *z, hipStream_t s)
@@ -435,7 +541,8 @@ void precond_apply(sem_mesh *m, const double *r, double *z, hipStream_t s)
     hipLaunchKernelGGL(jacobi_kernel, dim3(vec_blocks(nL)), dim3(256), 0, s, nL, m->inv64, r, z);
     SEM_HIP(hipGetLastError());
     if (!C) return;
-    coarse_enqueue(m, r, nullptr, nullptr, s);
+    coarse_restrict(m, r, s);
+    coarse_solve(m, nullptr, nullptr, s);
     hipLaunchKernelGGL(prolong_add_kernel, dim3(vec_blocks(nL)), dim3(256), 0, s, m->h.E, m->h.N + 1, C->evert, C->z0,
                        C->qw, m->inv64, z);
     SEM_HIP(hipGetLastError());

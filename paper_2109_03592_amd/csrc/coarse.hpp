@@ -39,9 +39,16 @@ struct CoarseSpace {
 // Builds the coarse space of the mesh's current operator (synchronises s).
 CoarseSpace *coarse_build(sem_mesh *m, int k, double frac, hipStream_t s);
 void coarse_free(CoarseSpace *C);
-// z0 = C(A0) P^T r, and when partial_pairs is given, (0, r0.z0) pairs per
-// workgroup there (C->dot_blocks of them); kernels skip when st->done.
-void coarse_enqueue(sem_mesh *m, const double *r, double *partial_pairs, const PcgState *st, hipStream_t s);
+// FP64 CG update with the restriction fused in: r -= alpha w, partial pairs
+// of <r,r>, <r, invdiag r> into `partial` (returns their count), element
+// restriction sums of the new r.  Skips when st->done.
+int coarse_update(sem_mesh *m, const PcgState *st, double *partial, hipStream_t s);
+// element restriction sums of r
+void coarse_restrict(sem_mesh *m, const double *r, hipStream_t s);
+// from the element sums: r0 = P^T r, z0 = C(A0) r0, and when dot_pairs is
+// given the (0, r0.z0) pairs there (returns their count, C->dot_blocks);
+// kernels skip when st->done.
+int coarse_solve(sem_mesh *m, double *dot_pairs, const PcgState *st, hipStream_t s);
 // z = D^-1 r (+ P C(A0) P^T r when the coarse space is set)
 void precond_apply(sem_mesh *m, const double *r, double *z, hipStream_t s);
 
