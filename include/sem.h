@@ -263,8 +263,9 @@ sem_status sem_pcg_solve(sem_mesh *mesh, const double *b, double *x, const sem_s
 
 /* ---------------------------------------------------------------------------
  * Two-level preconditioner (Eq. 6: a coarse term plus local solves; the local
- * solves here are single nodes, i.e. Jacobi).  With a coarse space set, FP64
- * solves (sem_pcg_solve, sem_proj_solve) use
+ * solves here are single nodes, i.e. Jacobi).  With a coarse space set, CG
+ * solves (sem_pcg_solve, sem_proj_solve; FP64, and the FP32 inner solves of
+ * SEM_PREC_MIXED) use
  *   M^{-1} r = D^{-1} r + P C(A0) P^T r
  * where
  *   - P holds the trilinear hat functions of the element vertices at the
@@ -280,8 +281,10 @@ sem_status sem_pcg_solve(sem_mesh *mesh, const double *b, double *x, const sem_s
  * The coarse term runs inside the CG iteration: restriction, Chebyshev and
  * the coarse part of <r, z> after the residual update, the prolongation in
  * the operator's prologue (the column kernel; SEM_OPK_NODE is not used while
- * a coarse space is set).  Mixed-precision solves fail with SEM_EUNSUPPORTED
- * while it is set.
+ * a coarse space is set).  The coarse data and the Chebyshev solve stay FP64
+ * in both precisions; an FP32 inner solve restricts its FP32 residual and adds
+ * the rounded correction.  Batched solves (sem_batch_*) do not take meshes
+ * with a coarse space (SEM_EUNSUPPORTED).
  */
 typedef struct {
     int64_t n_vertices;   /* element vertices (periodic images merged)          */

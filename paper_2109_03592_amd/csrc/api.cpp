@@ -204,20 +204,24 @@ static int op_epw(const sem_mesh *m)
     return sizeof(T) == 8 ? m->ax_epw : m->ax_epw32;
 }
 
-// the CG iteration of precision T runs the FP64 coarse-corrected operator (mode 3)
+// the CG iteration runs the coarse-corrected operator (mode 3)
 template <typename T>
-static bool coarse_cg(const sem_mesh *m) { return sizeof(T) == 8 && m->coarse != nullptr; }
+static bool coarse_cg(const sem_mesh *m) { return m->coarse != nullptr; }
+
+// elements per workgroup of the column kernel for precision T
+template <typename T>
+static int column_epw(const sem_mesh *m) { return sizeof(T) == 8 ? m->ax_epw : m->ax_epw32; }
 
 // elements per workgroup of the CG operator launch (mode 3 runs the column kernel)
 template <typename T>
-static int cg_epw(const sem_mesh *m) { return coarse_cg<T>(m) ? m->ax_epw : op_epw<T>(m); }
+static int cg_epw(const sem_mesh *m) { return coarse_cg<T>(m) ? column_epw<T>(m) : op_epw<T>(m); }
 
 template <typename T>
 static void enqueue_ax(sem_mesh *m, int mode, const T *in, T *out, hipStream_t s)
 {
     AxParams<T> a{};
     a.E = m->h.E;
-    a.epw = mode == 3 ? m->ax_epw : op_epw<T>(m);
+    a.epw = mode == 3 ? column_epw<T>(m) : op_epw<T>(m);
     a.kind = mode == 3 ? 0 : m->op_kind;
     a.grid_cap = m->ax_grid_cap;
     a.G = Prec<T>::G(m);
@@ -232,12 +236,10 @@ static void enqueue_ax(sem_mesh *m, int mode, const T *in, T *out, hipStream_t s
         a.x = Prec<T>::x(m);
         a.st = Prec<T>::st(m);
     }
-    if constexpr (sizeof(T) == 8) {
-        if (mode == 3) {
-            a.evert = m->coarse->evert;
-            a.z0 = m->coarse->z0;
-            a.cq = m->coarse->qw;
-        }
+    if (mode == 3) {
+        a.evert = m->coarse->evert;
+        a.z0 = m->coarse->z0;
+        a.cq = m->coarse->qw;
     }
     SEM_HIP(launch_ax<T>(m->h.N, mode, a, s));
 }
@@ -302,17 +304,15 @@ static void enqueue_iterations(sem_mesh *m, int k, hipStream_t s, Profiler *prof
         if (prof) prof->mark(s);
         SEM_HIP(launch_reduce_sigma(m->partials, axb, st, s));
         int64_t pairs = ub;
-        if constexpr (sizeof(T) == 8) {
-            if (coarse) {
-                // restriction fused into the update; <r, P z0> = <P^T r, z0>: the
-                // coarse solve's pairs follow the update's
-                pairs = coarse_update(m, st, m->partials, s);
-                pairs += coarse_solve(m, m->partials + 2 * pairs, st, s);
-            }
-        }
-        if (!coarse)
+        if (coarse) {
+            // restriction fused into the update; <r, P z0> = <P^T r, z0>: the
+            // coarse solve's pairs follow the update's
+            pairs = coarse_update<T>(m, Prec<T>::r(m), Prec<T>::w(m), Prec<T>::inv(m), st, m->partials, s);
+            pairs += coarse_solve(m, m->partials + 2 * pairs, st, s);
+        } else {
             SEM_HIP(launch_pcg_update<T>(nL, st, Prec<T>::r(m), Prec<T>::w(m), Prec<T>::inv(m), m->mult, m->partials,
                                          s));
+        }
         SEM_HIP(launch_reduce_rho(m->partials, pairs, st, s));
         if (prof) prof->mark(s);
     }
@@ -413,16 +413,14 @@ template <typename T>
 static void pcg_start(sem_mesh *m, double stop2, int limit, hipStream_t s)
 {
     const int64_t nL = m->h.nL;
-    if constexpr (sizeof(T) == 8) {
-        if (coarse_cg<T>(m)) {
-            const int64_t vb = vec_blocks(nL);
-            SEM_HIP(launch_pcg_init_partials(nL, m->r64, m->inv64, m->mult, m->partials, s));
-            coarse_restrict(m, m->r64, s);
-            const int64_t cb = coarse_solve(m, m->partials + 2 * vb, nullptr, s);
-            SEM_HIP(launch_reduce_init(m->partials, vb + cb, m->state, stop2, limit, s));
-            SEM_HIP(hipMemsetAsync(m->p64, 0, sizeof(double) * nL, s));
-            return;
-        }
+    if (coarse_cg<T>(m)) {
+        const int64_t vb = vec_blocks(nL);
+        SEM_HIP(launch_pcg_init_partials<T>(nL, Prec<T>::r(m), Prec<T>::inv(m), m->mult, m->partials, s));
+        coarse_restrict<T>(m, Prec<T>::r(m), Prec<T>::inv(m), s);
+        const int64_t cb = coarse_solve(m, m->partials + 2 * vb, nullptr, s);
+        SEM_HIP(launch_reduce_init(m->partials, vb + cb, Prec<T>::st(m), stop2, limit, s));
+        SEM_HIP(hipMemsetAsync(Prec<T>::p(m), 0, sizeof(T) * nL, s));
+        return;
     }
     SEM_HIP(launch_pcg_init<T>(nL, Prec<T>::r(m), Prec<T>::inv(m), m->mult, m->partials, Prec<T>::st(m), stop2,
                                limit, s));
@@ -545,8 +543,6 @@ static sem_status solve_mixed(sem_mesh *m, const double *b, double *x, const sem
                               hipStream_t s)
 {
     if (!m->with_fp32) fail(SEM_EINVAL, "sem_pcg_solve: mixed precision needs SEM_WITH_FP32 at set-up");
-    if (m->coarse)
-        fail(SEM_EUNSUPPORTED, "sem_pcg_solve: the coarse term applies to FP64 solves (remove it for mixed precision)");
     const int64_t nL = m->h.nL;
     ensure_solve_space(m, true);
     SEM_HIP(launch_dot_unique<double>(nL, b, b, m->mult, m->partials, m->scal, s));

@@ -126,10 +126,10 @@ __device__ inline void wave_sum8(double (&s)[8])
 
 // partial8[e*8 + c] = sum over element e's live nodes of phi_c r / mult;
 // one wavefront per element
-template <int N>
-__global__ __launch_bounds__(256) void restrict_elem_kernel(int64_t E, const double *__restrict__ r,
+template <typename T, int N>
+__global__ __launch_bounds__(256) void restrict_elem_kernel(int64_t E, const T *__restrict__ r,
                                                             const uint8_t *__restrict__ mult,
-                                                            const double *__restrict__ inv,
+                                                            const T *__restrict__ inv,
                                                             const double *__restrict__ qw,
                                                             double *__restrict__ partial8)
 {
@@ -143,8 +143,8 @@ __global__ __launch_bounds__(256) void restrict_elem_kernel(int64_t E, const dou
         const int64_t base = e * P3;
 #pragma unroll
         for (int q = lane; q < P3; q += 64) {
-            const double iv = ld_stream(inv + base + q);
-            const double v = iv > 0.0 ? ld_stream(r + base + q) / (double)mult[base + q] : 0.0;
+            const T iv = ld_stream(inv + base + q);
+            const double v = iv > T(0) ? (double)ld_stream(r + base + q) / (double)mult[base + q] : 0.0;
             hat_add<N>(sqw, q, v, s);
         }
         wave_sum8(s);
@@ -153,13 +153,14 @@ __global__ __launch_bounds__(256) void restrict_elem_kernel(int64_t E, const dou
     }
 }
 
-// CG update with the coarse restriction fused in (FP64): r -= alpha w, the
-// partial pairs of <r,r> and <r, invdiag r> per workgroup, and the element
-// restriction sums of the new r; one wavefront per element.
-template <int N>
+// CG update with the coarse restriction fused in: r -= alpha w, the partial
+// pairs of <r,r> and <r, invdiag r> per workgroup (FP64 sums, the products
+// as in the plain update), and the element restriction sums of the new r;
+// one wavefront per element.
+template <typename T, int N>
 __global__ __launch_bounds__(256) void update_restrict_kernel(int64_t E, const PcgState *__restrict__ st,
-                                                              double *__restrict__ r, const double *__restrict__ w,
-                                                              const double *__restrict__ inv,
+                                                              T *__restrict__ r, const T *__restrict__ w,
+                                                              const T *__restrict__ inv,
                                                               const uint8_t *__restrict__ mult,
                                                               const double *__restrict__ qw,
                                                               double *__restrict__ partial,
@@ -170,7 +171,7 @@ __global__ __launch_bounds__(256) void update_restrict_kernel(int64_t E, const P
     __shared__ double sqw[2 * P];
     if (threadIdx.x < 2 * P) sqw[threadIdx.x] = qw[threadIdx.x];
     __syncthreads();
-    const double alpha = st->alpha;
+    const T alpha = (T)st->alpha;
     const int lane = threadIdx.x & 63;
     double rr = 0.0, rz = 0.0;
     for (int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); e < E; e += (int64_t)gridDim.x * 4) {
@@ -179,13 +180,14 @@ __global__ __launch_bounds__(256) void update_restrict_kernel(int64_t E, const P
 #pragma unroll
         for (int q = lane; q < P3; q += 64) {
             const int64_t o = base + q;
-            const double rv = ld_stream(r + o) - alpha * ld_stream(w + o);
+            const T rv = ld_stream(r + o) - alpha * ld_stream(w + o);
             st_stream(rv, r + o);
-            const double iv = ld_stream(inv + o);
+            const T iv = ld_stream(inv + o);
             const double im = 1.0 / (double)ld_stream(mult + o);
-            rr += rv * rv * im;
-            rz += rv * (iv * rv) * im;
-            hat_add<N>(sqw, q, iv > 0.0 ? rv * im : 0.0, s);
+            const double rd = (double)rv;
+            rr += rd * rd * im;
+            rz += rd * (double)(iv * rv) * im;
+            hat_add<N>(sqw, q, iv > T(0) ? rd * im : 0.0, s);
         }
         wave_sum8(s);
         const double out = pick8(s, lane);
@@ -485,31 +487,39 @@ CoarseSpace *coarse_build(sem_mesh *m, int k, double frac, hipStream_t s)
 
 static int elem_blocks(int64_t E) { return (int)std::max<int64_t>(1, std::min<int64_t>((E + 3) / 4, 8192)); }
 
-int coarse_update(sem_mesh *m, const PcgState *st, double *partial, hipStream_t s)
+template <typename T>
+int coarse_update(sem_mesh *m, T *r, const T *w, const T *inv, const PcgState *st, double *partial, hipStream_t s)
 {
     CoarseSpace *C = m->coarse;
     const int64_t E = m->h.E;
     const int blocks = elem_blocks(E);
-#define SEM_UPD(n)                                                                                                \
-    hipLaunchKernelGGL(update_restrict_kernel<n>, dim3(blocks), dim3(256), 0, s, E, st, m->r64, m->w64, m->inv64, \
-                       m->mult, C->qw, partial, C->partial8)
+#define SEM_UPD(n)                                                                                              \
+    hipLaunchKernelGGL((update_restrict_kernel<T, n>), dim3(blocks), dim3(256), 0, s, E, st, r, w, inv, m->mult, \
+                       C->qw, partial, C->partial8)
     SEM_COARSE_ORDER_SWITCH(m->h.N, SEM_UPD)
 #undef SEM_UPD
     SEM_HIP(hipGetLastError());
     return blocks;
 }
+template int coarse_update<double>(sem_mesh *, double *, const double *, const double *, const PcgState *, double *,
+                                   hipStream_t);
+template int coarse_update<float>(sem_mesh *, float *, const float *, const float *, const PcgState *, double *,
+                                  hipStream_t);
 
-void coarse_restrict(sem_mesh *m, const double *r, hipStream_t s)
+template <typename T>
+void coarse_restrict(sem_mesh *m, const T *r, const T *inv, hipStream_t s)
 {
     CoarseSpace *C = m->coarse;
     const int64_t E = m->h.E;
-#define SEM_RES(n)                                                                                              \
-    hipLaunchKernelGGL(restrict_elem_kernel<n>, dim3(elem_blocks(E)), dim3(256), 0, s, E, r, m->mult, m->inv64, \
+#define SEM_RES(n)                                                                                                  \
+    hipLaunchKernelGGL((restrict_elem_kernel<T, n>), dim3(elem_blocks(E)), dim3(256), 0, s, E, r, m->mult, inv, \
                        C->qw, C->partial8)
     SEM_COARSE_ORDER_SWITCH(m->h.N, SEM_RES)
 #undef SEM_RES
     SEM_HIP(hipGetLastError());
 }
+template void coarse_restrict<double>(sem_mesh *, const double *, const double *, hipStream_t);
+template void coarse_restrict<float>(sem_mesh *, const float *, const float *, hipStream_t);
 
 int coarse_solve(sem_mesh *m, double *dot_pairs, const PcgState *st, hipStream_t s)
 {
@@ -541,7 +551,7 @@ void precond_apply(sem_mesh *m, const double *r, double *z, hipStream_t s)
     hipLaunchKernelGGL(jacobi_kernel, dim3(vec_blocks(nL)), dim3(256), 0, s, nL, m->inv64, r, z);
     SEM_HIP(hipGetLastError());
     if (!C) return;
-    coarse_restrict(m, r, s);
+    coarse_restrict<double>(m, r, m->inv64, s);
     coarse_solve(m, nullptr, nullptr, s);
     hipLaunchKernelGGL(prolong_add_kernel, dim3(vec_blocks(nL)), dim3(256), 0, s, m->h.E, m->h.N + 1, C->evert, C->z0,
                        C->qw, m->inv64, z);

@@ -39,12 +39,14 @@ struct CoarseSpace {
 // Builds the coarse space of the mesh's current operator (synchronises s).
 CoarseSpace *coarse_build(sem_mesh *m, int k, double frac, hipStream_t s);
 void coarse_free(CoarseSpace *C);
-// FP64 CG update with the restriction fused in: r -= alpha w, partial pairs
-// of <r,r>, <r, invdiag r> into `partial` (returns their count), element
-// restriction sums of the new r.  Skips when st->done.
-int coarse_update(sem_mesh *m, const PcgState *st, double *partial, hipStream_t s);
-// element restriction sums of r
-void coarse_restrict(sem_mesh *m, const double *r, hipStream_t s);
+// CG update (precision T) with the restriction fused in: r -= alpha w,
+// partial pairs of <r,r>, <r, inv r> into `partial` (returns their count),
+// element restriction sums of the new r.  Skips when st->done.
+template <typename T>
+int coarse_update(sem_mesh *m, T *r, const T *w, const T *inv, const PcgState *st, double *partial, hipStream_t s);
+// element restriction sums of r (live nodes: inv > 0)
+template <typename T>
+void coarse_restrict(sem_mesh *m, const T *r, const T *inv, hipStream_t s);
 // from the element sums: r0 = P^T r, z0 = C(A0) r0, and when dot_pairs is
 // given the (0, r0.z0) pairs there (returns their count, C->dot_blocks);
 // kernels skip when st->done.

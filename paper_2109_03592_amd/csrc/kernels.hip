@@ -499,8 +499,8 @@ template <typename T, int MODE, bool HELM>
 static hipError_t launch_ax_mode(int N, const AxParams<T> &a, hipStream_t s)
 {
     if constexpr (MODE == 3) {
-        // the coarse correction runs in the FP64 column kernel only
-        if (sizeof(T) != 8 || a.kind != 0 || !a.evert || !a.z0 || !a.cq) return hipErrorInvalidValue;
+        // the coarse correction runs in the column kernel only
+        if (a.kind != 0 || !a.evert || !a.z0 || !a.cq) return hipErrorInvalidValue;
     } else {
         if (a.kind == 1) return launch_ax_node<T, MODE, HELM>(N, a, s);
     }
@@ -524,11 +524,8 @@ template <typename T>
 hipError_t launch_ax(int N, int mode, const AxParams<T> &a, hipStream_t s)
 {
     if (mode == 3) {
-        if constexpr (sizeof(T) == 8) {
-            if (a.h1) return launch_ax_mode<T, 3, true>(N, a, s);
-            return launch_ax_mode<T, 3, false>(N, a, s);
-        }
-        return hipErrorInvalidValue;
+        if (a.h1) return launch_ax_mode<T, 3, true>(N, a, s);
+        return launch_ax_mode<T, 3, false>(N, a, s);
     }
     if (a.h1) {
         if (mode == 0) return launch_ax_mode<T, 0, true>(N, a, s);
@@ -645,12 +642,17 @@ hipError_t launch_pcg_init(int64_t n, const T *r, const T *inv, const uint8_t *m
 }
 template hipError_t launch_pcg_init<double>(int64_t, const double *, const double *, const uint8_t *, double *,
                                             PcgState *, double, int, hipStream_t);
-hipError_t launch_pcg_init_partials(int64_t n, const double *r, const double *inv, const uint8_t *mult,
-                                    double *partial, hipStream_t s)
+template <typename T>
+hipError_t launch_pcg_init_partials(int64_t n, const T *r, const T *inv, const uint8_t *mult, double *partial,
+                                    hipStream_t s)
 {
-    hipLaunchKernelGGL((pcg_init_kernel<double>), dim3(vec_blocks(n)), dim3(256), 0, s, n, r, inv, mult, partial);
+    hipLaunchKernelGGL((pcg_init_kernel<T>), dim3(vec_blocks(n)), dim3(256), 0, s, n, r, inv, mult, partial);
     return hipGetLastError();
 }
+template hipError_t launch_pcg_init_partials<double>(int64_t, const double *, const double *, const uint8_t *,
+                                                     double *, hipStream_t);
+template hipError_t launch_pcg_init_partials<float>(int64_t, const float *, const float *, const uint8_t *, double *,
+                                                    hipStream_t);
 hipError_t launch_reduce_init(const double *partial, int64_t pairs, PcgState *st, double stop2, int limit,
                               hipStream_t s)
 {

@@ -38,10 +38,10 @@ struct AxParams {
     const T *h1;           // Helmholtz: h1 per local point (nullptr: Poisson)
     const T *h2b;          // Helmholtz: h2*B per local point (with h1)
     int kind;              // 0: lane per (i,j) column; 1: lane per node (N <= 7)
-    // mode 3 (FP64 only): mode 2 plus the coarse correction in the prologue
+    // mode 3: mode 2 plus the coarse correction in the prologue (FP64 coarse data)
     const int32_t *evert;  // [E][8] vertex of each element corner
-    const T *z0;           // coarse solution per vertex
-    const T *cq;           // [2][N+1] 1-D hat weights at the GLL nodes
+    const double *z0;      // coarse solution per vertex
+    const double *cq;      // [2][N+1] 1-D hat weights at the GLL nodes
 };
 
 constexpr int kMaxNodeOrder = 7;   // the lane-per-node operator: (N+1)^3 <= 512
@@ -71,10 +71,11 @@ hipError_t launch_dot_unique(int64_t n, const T *a, const T *b, const uint8_t *m
 template <typename T>
 hipError_t launch_pcg_init(int64_t n, const T *r, const T *inv, const uint8_t *mult, double *partial,
                            PcgState *st, double stop2, int limit, hipStream_t s);
-// the two halves of launch_pcg_init (FP64): vec_blocks(n) partial pairs, and
-// the reduction of `pairs` pairs into the CG start state
-hipError_t launch_pcg_init_partials(int64_t n, const double *r, const double *inv, const uint8_t *mult,
-                                    double *partial, hipStream_t s);
+// the two halves of launch_pcg_init: vec_blocks(n) partial pairs, and the
+// reduction of `pairs` pairs into the CG start state
+template <typename T>
+hipError_t launch_pcg_init_partials(int64_t n, const T *r, const T *inv, const uint8_t *mult, double *partial,
+                                    hipStream_t s);
 hipError_t launch_reduce_init(const double *partial, int64_t pairs, PcgState *st, double stop2, int limit,
                               hipStream_t s);
 template <typename T>

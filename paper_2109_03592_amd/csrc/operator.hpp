@@ -258,7 +258,7 @@ struct ColumnIndex {
 // HELM: Helmholtz form -- the three products of the combine step are scaled
 // by h1 at the point (Algorithm 1's h1) and h2*B*u is added to the output
 // (the h2 term of Eq. 4); h2b holds h2*B per point.
-// MODE 3 (FP64 CG with the coarse term of Eq. 6): MODE 2 with the coarse
+// MODE 3 (CG with the coarse term of Eq. 6): MODE 2 with the coarse
 // correction added to the preconditioned residual, p <- invdiag*r +
 // sum_c phi_c z0[evert[e][c]] + beta*p at live nodes (invdiag > 0), phi_c the
 // trilinear hat of corner c (c = cx + 2cy + 4cz) with 1-D weights cq[side][i].
@@ -268,7 +268,7 @@ __device__ inline void ax_tile(const LaneRows<T, N> &R, const T *__restrict__ D,
                                T *__restrict__ out, const T *__restrict__ invdiag, T *__restrict__ p, T beta,
                                T *__restrict__ x, T alpha, double &dot, const T *__restrict__ h1 = nullptr,
                                const T *__restrict__ h2b = nullptr, const int32_t *__restrict__ evert = nullptr,
-                               const T *__restrict__ z0 = nullptr, const T *__restrict__ cq = nullptr)
+                               const double *__restrict__ z0 = nullptr, const double *__restrict__ cq = nullptr)
 {
     constexpr int P = N + 1, P2 = P * P, P3 = P2 * P;
     T *sr = su + P3;
@@ -278,14 +278,14 @@ __device__ inline void ax_tile(const LaneRows<T, N> &R, const T *__restrict__ D,
     const int64_t eb = (active ? e : 0) * P3;
     T uc[P];
     if (MODE >= 2) {
-        // coarse correction of this column: bilinear in (i,j) per t-side
-        T cs0 = 0, cs1 = 0;
+        // coarse correction of this column (FP64): bilinear in (i,j) per t-side
+        double cs0 = 0, cs1 = 0;
         if (MODE == 3 && active) {
             const int32_t *ev = evert + e * 8;
-            T zc[8];
+            double zc[8];
 #pragma unroll
             for (int c = 0; c < 8; ++c) zc[c] = z0[ev[c]];
-            const T ai0 = cq[i], ai1 = cq[P + i], aj0 = cq[j], aj1 = cq[P + j];
+            const double ai0 = cq[i], ai1 = cq[P + i], aj0 = cq[j], aj1 = cq[P + j];
             cs0 = aj0 * (ai0 * zc[0] + ai1 * zc[1]) + aj1 * (ai0 * zc[2] + ai1 * zc[3]);
             cs1 = aj0 * (ai0 * zc[4] + ai1 * zc[5]) + aj1 * (ai0 * zc[6] + ai1 * zc[7]);
         }
@@ -299,7 +299,7 @@ __device__ inline void ax_tile(const LaneRows<T, N> &R, const T *__restrict__ D,
                 st_stream(ld_stream(x + o) + alpha * pold, x + o);
                 const T iv = ld_stream(invdiag + o);
                 v = iv * ld_stream(in + o) + beta * pold;
-                if (MODE == 3 && iv > T(0)) v += cq[k] * cs0 + cq[P + k] * cs1;
+                if (MODE == 3 && iv > T(0)) v += (T)(cq[k] * cs0 + cq[P + k] * cs1);
                 st_stream(v, p + o);
             }
             uc[k] = v;

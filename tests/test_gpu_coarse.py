@@ -45,7 +45,8 @@ class _Op:
 
 def _meshes(semlib, oracle_mod, kind, N, nel, periodic, seed):
     if kind == "pipe":
-        return semlib.pipe_mesh(*nel, N=N, length=2.0), oracle_mod.pipe_mesh(*nel, N=N, length=2.0)
+        return (semlib.pipe_mesh(*nel, N=N, length=2.0, with_fp32=True),
+                oracle_mod.pipe_mesh(*nel, N=N, length=2.0))
     V = SI.jittered_box_vertices(nel, seed=seed)
     return (semlib.box_mesh(N, nel, vertices=V, periodic=periodic, with_fp32=True),
             oracle_mod.OracleMesh(N, nel, vertices=V, periodic=periodic))
@@ -138,6 +139,11 @@ def test_coarse_pcg(semlib, oracle_mod, kind, N, nel, periodic, seed):
         assert res.ok, res
         assert abs(res.iterations - it_o) <= max(3, 0.05 * it_o), (graph, res.iterations, it_o)
         assert om.true_residual(b, _host(xg)) <= 1e-10
+    # mixed precision: FP32 inner CG with the same coarse term (FP64 coarse solve)
+    xg, res = m.solve(_dev(b), tol=1e-10, precision="mixed")
+    assert res.ok, res
+    assert om.true_residual(b, _host(xg)) <= 1e-10
+    assert res.iterations < rj.iterations, (res.iterations, rj.iterations)
     # the same Krylov iterate after a fixed number of steps
     for steps in (1, 6):
         xs, _ = pcg(_Op(om), b, C.apply, tol=1e-30, max_iter=steps)
@@ -208,9 +214,6 @@ def test_coarse_errors(semlib):
     m.set_coarse(5, 0.05)
     b = m.zeros()
     b.fill_(1.0)
-    with pytest.raises(L.SemError) as e:
-        m.solve(b, precision="mixed")
-    assert e.value.status == L.SEM_EUNSUPPORTED
     batch = semlib.Batch(max_slots=2)
     with pytest.raises(L.SemError) as e:
         batch.admit(m, b)
