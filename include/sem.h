@@ -306,10 +306,49 @@ typedef struct {
 sem_status sem_set_coarse(sem_mesh *mesh, int chebyshev_steps, double fraction, void *stream);
 sem_status sem_get_coarse_info(const sem_mesh *mesh, sem_coarse_info *info);
 
-/* z = M^{-1} r with the mesh's FP64 preconditioner (Jacobi, plus the coarse
- * term when set).  r, z: distinct device FP64 E-vectors, r continuous; z is
+/* z = M^{-1} r with the mesh's FP64 preconditioner (Jacobi or the Schwarz
+ * local solves of sem_set_schwarz, plus the coarse term when set).  r, z: distinct device FP64 E-vectors, r continuous; z is
  * continuous and masked.  Asynchronous on `stream`. */
 sem_status sem_precond_apply(sem_mesh *mesh, const double *r, double *z, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Overlapping Schwarz local solves (Eq. 6, the sum over local subdomains),
+ * in place of Jacobi as the local part of the FP64 preconditioner:
+ *   z = sum_k R_k^T A_k^{-1} R_k r   (+ the coarse term when set)
+ * where
+ *   - subdomain k is element k extended by one node layer into every
+ *     neighbour that exists (also across periodic faces); nodes beyond a
+ *     non-periodic face do not exist and nodes on Dirichlet faces are not
+ *     unknowns;
+ *   - A_k is the separable (fast-diagonalisation) form on a box with the
+ *     element's mean edge lengths:
+ *       A_k = B_t x B_s x A_r + B_t x A_s x B_r + A_t x B_s x B_r
+ *     with A_d, B_d the 1-D GLL stiffness and lumped mass of the element and
+ *     of an equal copy on each side that has a neighbour, restricted to the
+ *     subdomain's nodes; it is inverted through the 1-D generalised
+ *     eigenvectors (six 1-D contractions per element);
+ *   - the local solutions are added without weights into every node they
+ *     cover.
+ * A_k uses the Poisson form also when sem_set_helmholtz is set (the
+ * preconditioner stays symmetric positive definite).  Mixed-precision and
+ * batched solves fail with SEM_EUNSUPPORTED while it is set.
+ */
+/* enable 1: build the 1-D factors on the host (from the element corner
+ * coordinates; factors shared by elements with equal length and sides) and
+ * the device buffers (an extended E-vector of (N+3)^3 values per element and
+ * one E-vector); 0: remove.  Synchronises `stream`.
+ * Errors: SEM_EUNSUPPORTED (N = 1: the one-node overlap reaches the far faces
+ * of the neighbours and an interior subdomain's local problem is singular),
+ * SEM_EINVAL (degenerate element), SEM_ENOMEM, SEM_EHIP. */
+sem_status sem_set_schwarz(sem_mesh *mesh, int enable, void *stream);
+/* enabled: 1 when set; n_factors: distinct 1-D factor sets (either may be NULL). */
+sem_status sem_get_schwarz_info(const sem_mesh *mesh, int *enabled, int64_t *n_factors);
+/* Host only (no device): the 1-D factors of one direction of an extended
+ * element of length ell with side kinds left/right (0 a neighbour, 1
+ * Dirichlet, 2 a free end): S (count x count, row-major, row = kept extended
+ * index lo + row, column = mode) with S^T B S = I and S^T A S = diag(lam).
+ * S holds (N+3)^2 and lam N+3 doubles.  Errors: SEM_EINVAL. */
+sem_status sem_host_fdm_1d(int N, double ell, int left, int right, double *S, double *lam, int *lo, int *count);
 
 /* ---------------------------------------------------------------------------
  * Projection onto previous solutions (section 2: successive solves of a time

@@ -180,6 +180,17 @@ class Mesh:
         L.check(self._lib.sem_set_coarse(self._h, int(chebyshev_steps), float(fraction), _stream_handle(stream)),
                 "sem_set_coarse")
 
+    def set_schwarz(self, enable: bool = True, stream=None):
+        """Use the overlapping Schwarz local solves of Eq. 6 (FDM on each
+        element extended by one node layer) as the local part of the FP64
+        preconditioner; enable=False restores Jacobi."""
+        L.check(self._lib.sem_set_schwarz(self._h, 1 if enable else 0, _stream_handle(stream)), "sem_set_schwarz")
+
+    def schwarz_info(self) -> dict:
+        en, nf = C.c_int(0), C.c_int64(0)
+        L.check(self._lib.sem_get_schwarz_info(self._h, C.byref(en), C.byref(nf)), "sem_get_schwarz_info")
+        return {"enabled": bool(en.value), "n_factors": int(nf.value)}
+
     def coarse_info(self) -> dict:
         info = L.CoarseInfo()
         L.check(self._lib.sem_get_coarse_info(self._h, C.byref(info)), "sem_get_coarse_info")
@@ -463,6 +474,21 @@ class Projection:
         if raise_on_error and status != L.SEM_OK:
             raise SemError(status, "sem_proj_solve")
         return x, res
+
+
+def fdm_1d(N: int, ell: float, left: int, right: int):
+    """Host-only 1-D Schwarz factors (S, lam, lo): S^T B S = I, S^T A S =
+    diag(lam) on the kept extended indices lo .. lo+len(lam)-1; side kinds 0
+    neighbour, 1 Dirichlet, 2 free end."""
+    lib = L.load()
+    n = N + 3
+    S = np.zeros(n * n)
+    lam = np.zeros(n)
+    lo, cnt = C.c_int(0), C.c_int(0)
+    L.check(lib.sem_host_fdm_1d(int(N), float(ell), int(left), int(right), S.ctypes.data, lam.ctypes.data,
+                                C.byref(lo), C.byref(cnt)), "sem_host_fdm_1d")
+    c = cnt.value
+    return S[:c * c].reshape(c, c).copy(), lam[:c].copy(), lo.value
 
 
 def box_mesh(N: int, nel: Sequence[int], vertices=None, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0),

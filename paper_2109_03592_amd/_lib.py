@@ -76,6 +76,9 @@ SIGNATURES = {
     "sem_set_coarse": (_i, [_vp, _i, _d, _vp]),
     "sem_get_coarse_info": (_i, [_vp, C.POINTER(CoarseInfo)]),
     "sem_precond_apply": (_i, [_vp, _vp, _vp, _vp]),
+    "sem_set_schwarz": (_i, [_vp, _i, _vp]),
+    "sem_get_schwarz_info": (_i, [_vp, C.POINTER(_i), C.POINTER(C.c_int64)]),
+    "sem_host_fdm_1d": (_i, [_i, _d, _i, _i, _vp, _vp, C.POINTER(_i), C.POINTER(_i)]),
     "sem_get_operator_kernel": (_i, [_vp, C.POINTER(_i)]),
     "sem_proj_create": (_i, [_vp, _i, C.POINTER(_vp)]),
     "sem_proj_free": (_i, [_vp]),

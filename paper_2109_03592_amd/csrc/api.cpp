@@ -11,6 +11,7 @@
 
 #include "coarse.hpp"
 #include "kernels.hpp"
+#include "schwarz.hpp"
 #include "sem_internal.hpp"
 
 namespace sem {
@@ -204,25 +205,33 @@ static int op_epw(const sem_mesh *m)
     return sizeof(T) == 8 ? m->ax_epw : m->ax_epw32;
 }
 
-// the CG iteration runs the coarse-corrected operator (mode 3)
+// the CG iteration of precision T adds the coarse correction
 template <typename T>
 static bool coarse_cg(const sem_mesh *m) { return m->coarse != nullptr; }
+// the CG iteration of precision T takes its local part from the Schwarz solves (FP64)
+template <typename T>
+static bool schwarz_cg(const sem_mesh *m) { return sizeof(T) == 8 && m->schwarz != nullptr; }
+
+// operator mode of the CG iteration: 2 Jacobi, 3 Jacobi + coarse, 4 Schwarz,
+// 5 Schwarz + coarse
+template <typename T>
+static int cg_mode(const sem_mesh *m) { return (schwarz_cg<T>(m) ? 4 : 2) + (coarse_cg<T>(m) ? 1 : 0); }
 
 // elements per workgroup of the column kernel for precision T
 template <typename T>
 static int column_epw(const sem_mesh *m) { return sizeof(T) == 8 ? m->ax_epw : m->ax_epw32; }
 
-// elements per workgroup of the CG operator launch (mode 3 runs the column kernel)
+// elements per workgroup of the CG operator launch (modes 3-5 run the column kernel)
 template <typename T>
-static int cg_epw(const sem_mesh *m) { return coarse_cg<T>(m) ? column_epw<T>(m) : op_epw<T>(m); }
+static int cg_epw(const sem_mesh *m) { return cg_mode<T>(m) > 2 ? column_epw<T>(m) : op_epw<T>(m); }
 
 template <typename T>
 static void enqueue_ax(sem_mesh *m, int mode, const T *in, T *out, hipStream_t s)
 {
     AxParams<T> a{};
     a.E = m->h.E;
-    a.epw = mode == 3 ? column_epw<T>(m) : op_epw<T>(m);
-    a.kind = mode == 3 ? 0 : m->op_kind;
+    a.epw = mode >= 3 ? column_epw<T>(m) : op_epw<T>(m);
+    a.kind = mode >= 3 ? 0 : m->op_kind;
     a.grid_cap = m->ax_grid_cap;
     a.G = Prec<T>::G(m);
     a.in = in;
@@ -236,7 +245,7 @@ static void enqueue_ax(sem_mesh *m, int mode, const T *in, T *out, hipStream_t s
         a.x = Prec<T>::x(m);
         a.st = Prec<T>::st(m);
     }
-    if (mode == 3) {
+    if (mode == 3 || mode == 5) {
         a.evert = m->coarse->evert;
         a.z0 = m->coarse->z0;
         a.cq = m->coarse->qw;
@@ -292,13 +301,18 @@ template <typename T>
 static void enqueue_iterations(sem_mesh *m, int k, hipStream_t s, Profiler *prof = nullptr)
 {
     PcgState *st = Prec<T>::st(m);
-    const bool coarse = coarse_cg<T>(m);
+    const bool coarse = coarse_cg<T>(m), schwarz = schwarz_cg<T>(m);
+    const int mode = cg_mode<T>(m);
     const int64_t axb = ax_grid(m->h.E, cg_epw<T>(m), m->ax_grid_cap);
     const int64_t nL = m->h.nL;
     const int64_t ub = update_blocks(nL);
+    // the Jacobi part of <r,z> comes from the update unless Schwarz supplies z
+    const T *jinv = schwarz ? nullptr : Prec<T>::inv(m);
+    T *zs = nullptr;
+    if constexpr (sizeof(T) == 8) zs = schwarz ? m->schwarz->zs : nullptr;
     for (int it = 0; it < k; ++it) {
         if (prof) prof->mark(s);
-        enqueue_ax<T>(m, coarse ? 3 : 2, Prec<T>::r(m), Prec<T>::w(m), s);
+        enqueue_ax<T>(m, mode, schwarz ? zs : Prec<T>::r(m), Prec<T>::w(m), s);
         if (prof) prof->mark(s);
         enqueue_gs<T>(m, Prec<T>::w(m), st, s);
         if (prof) prof->mark(s);
@@ -307,11 +321,14 @@ static void enqueue_iterations(sem_mesh *m, int k, hipStream_t s, Profiler *prof
         if (coarse) {
             // restriction fused into the update; <r, P z0> = <P^T r, z0>: the
             // coarse solve's pairs follow the update's
-            pairs = coarse_update<T>(m, Prec<T>::r(m), Prec<T>::w(m), Prec<T>::inv(m), st, m->partials, s);
+            pairs = coarse_update<T>(m, Prec<T>::r(m), Prec<T>::w(m), Prec<T>::inv(m), st, m->partials, !schwarz, s);
             pairs += coarse_solve(m, m->partials + 2 * pairs, st, s);
         } else {
-            SEM_HIP(launch_pcg_update<T>(nL, st, Prec<T>::r(m), Prec<T>::w(m), Prec<T>::inv(m), m->mult, m->partials,
-                                         s));
+            SEM_HIP(launch_pcg_update<T>(nL, st, Prec<T>::r(m), Prec<T>::w(m), jinv, m->mult, m->partials, s));
+        }
+        if constexpr (sizeof(T) == 8) {
+            // Schwarz local solves of the new r; their <r, z> pairs follow
+            if (schwarz) pairs += schwarz_apply(m, m->r64, zs, m->partials + 2 * pairs, st, s);
         }
         SEM_HIP(launch_reduce_rho(m->partials, pairs, st, s));
         if (prof) prof->mark(s);
@@ -406,19 +423,25 @@ static void true_residual(sem_mesh *m, const double *b, hipStream_t s, int slot)
     SEM_HIP(launch_dot_unique<double>(m->h.nL, m->r64, m->r64, m->mult, m->partials, m->scal + slot, s));
 }
 
-// Plain CG loop on precision T from the current r (x, p set by the caller);
-// returns the final device state.
 // CG start from the current r: rho = <r, M^-1 r>, rr, flags; p = 0
 template <typename T>
 static void pcg_start(sem_mesh *m, double stop2, int limit, hipStream_t s)
 {
     const int64_t nL = m->h.nL;
-    if (coarse_cg<T>(m)) {
+    const bool coarse = coarse_cg<T>(m), schwarz = schwarz_cg<T>(m);
+    if (coarse || schwarz) {
         const int64_t vb = vec_blocks(nL);
-        SEM_HIP(launch_pcg_init_partials<T>(nL, Prec<T>::r(m), Prec<T>::inv(m), m->mult, m->partials, s));
-        coarse_restrict<T>(m, Prec<T>::r(m), Prec<T>::inv(m), s);
-        const int64_t cb = coarse_solve(m, m->partials + 2 * vb, nullptr, s);
-        SEM_HIP(launch_reduce_init(m->partials, vb + cb, Prec<T>::st(m), stop2, limit, s));
+        int64_t pairs = vb;
+        SEM_HIP(launch_pcg_init_partials<T>(nL, Prec<T>::r(m), schwarz ? nullptr : Prec<T>::inv(m), m->mult,
+                                            m->partials, s));
+        if (coarse) {
+            coarse_restrict<T>(m, Prec<T>::r(m), Prec<T>::inv(m), s);
+            pairs += coarse_solve(m, m->partials + 2 * pairs, nullptr, s);
+        }
+        if constexpr (sizeof(T) == 8) {
+            if (schwarz) pairs += schwarz_apply(m, m->r64, m->schwarz->zs, m->partials + 2 * pairs, nullptr, s);
+        }
+        SEM_HIP(launch_reduce_init(m->partials, pairs, Prec<T>::st(m), stop2, limit, s));
         SEM_HIP(hipMemsetAsync(Prec<T>::p(m), 0, sizeof(T) * nL, s));
         return;
     }
@@ -427,6 +450,8 @@ static void pcg_start(sem_mesh *m, double stop2, int limit, hipStream_t s)
     SEM_HIP(hipMemsetAsync(Prec<T>::p(m), 0, sizeof(T) * nL, s));
 }
 
+// Plain CG loop on precision T from the current r (x, p set by the caller);
+// returns the final device state.
 template <typename T>
 static PcgState cg_loop(sem_mesh *m, double stop2, int limit, int poll, bool graph, hipStream_t s,
                         Profiler *prof = nullptr)
@@ -543,6 +568,8 @@ static sem_status solve_mixed(sem_mesh *m, const double *b, double *x, const sem
                               hipStream_t s)
 {
     if (!m->with_fp32) fail(SEM_EINVAL, "sem_pcg_solve: mixed precision needs SEM_WITH_FP32 at set-up");
+    if (m->schwarz)
+        fail(SEM_EUNSUPPORTED, "sem_pcg_solve: the Schwarz local solves run in FP64 solves only");
     const int64_t nL = m->h.nL;
     ensure_solve_space(m, true);
     SEM_HIP(launch_dot_unique<double>(nL, b, b, m->mult, m->partials, m->scal, s));
@@ -647,10 +674,11 @@ sem_status sem_setup(const sem_mesh_desc *desc, void *stream, sem_mesh **out)
             m->gs_off = dalloc<int32_t>(m, h.gs_off.size());
             m->gs_idx = dalloc<int32_t>(m, h.gs_idx.size());
             m->ax_grid_cap = persistent_grid_cap();
-            // + room for the coarse dot's pairs behind the CG partial pairs
+            // + room for the coarse dot's and the Schwarz solves' pairs behind the
+            // CG partial pairs
             const int64_t np = std::max<int64_t>(std::max<int64_t>(m->ax_grid_cap, 65536),
                                                 2 * (int64_t)std::max(vec_blocks(nL), update_blocks(nL))) +
-                               2 * kMaxCoarseDotBlocks + 64;
+                               2 * (kMaxCoarseDotBlocks + kMaxSchwarzPairs) + 64;
             m->partials = dalloc<double>(m, np);
             m->n_partials = np;
             m->state = dalloc<PcgState>(m, 2);
@@ -693,6 +721,7 @@ sem_status sem_free(sem_mesh *m)
         if (m->graph[q]) hipGraphExecDestroy(m->graph[q]);
     if (m->capture_stream) hipStreamDestroy(m->capture_stream);
     coarse_free(m->coarse);
+    schwarz_free(m->schwarz);
     for (hipEvent_t e : m->events) hipEventDestroy(e);
     for (void *p : m->allocations) hipFree(p);
     delete m;
@@ -1038,6 +1067,32 @@ sem_status sem_set_coarse(sem_mesh *m, int steps, double fraction, void *stream)
     });
 }
 
+sem_status sem_set_schwarz(sem_mesh *m, int enable, void *stream)
+{
+    return guarded([&]() -> sem_status {
+        if (!m) fail(SEM_EINVAL, "sem_set_schwarz: null mesh");
+        if (enable && m->h.N < 2)
+            fail(SEM_EUNSUPPORTED, "sem_set_schwarz: N = 1 (the overlap spans the neighbours; singular local problems)");
+        hipStream_t s = (hipStream_t)stream;
+        drop_graphs(m, s);
+        SEM_HIP(hipStreamSynchronize(s));
+        schwarz_free(m->schwarz);
+        m->schwarz = nullptr;
+        if (enable) m->schwarz = schwarz_build(m, s);
+        return SEM_OK;
+    });
+}
+
+sem_status sem_get_schwarz_info(const sem_mesh *m, int *enabled, int64_t *n_factors)
+{
+    return guarded([&]() -> sem_status {
+        if (!m) fail(SEM_EINVAL, "sem_get_schwarz_info: null mesh");
+        if (enabled) *enabled = m->schwarz ? 1 : 0;
+        if (n_factors) *n_factors = m->schwarz ? m->schwarz->n_table : 0;
+        return SEM_OK;
+    });
+}
+
 sem_status sem_get_coarse_info(const sem_mesh *m, sem_coarse_info *info)
 {
     return guarded([&]() -> sem_status {
@@ -1060,7 +1115,14 @@ sem_status sem_precond_apply(sem_mesh *m, const double *r, double *z, void *stre
     return guarded([&]() -> sem_status {
         if (!m || !r || !z) fail(SEM_EINVAL, "sem_precond_apply: null argument");
         if (r == z) fail(SEM_EINVAL, "sem_precond_apply: r and z must be distinct");
-        precond_apply(m, r, z, (hipStream_t)stream);
+        hipStream_t s = (hipStream_t)stream;
+        if (m->schwarz) schwarz_apply(m, r, z, nullptr, nullptr, s);
+        else launch_jacobi(m->h.nL, m->inv64, r, z, s);
+        if (m->coarse) {
+            coarse_restrict<double>(m, r, m->inv64, s);
+            coarse_solve(m, nullptr, nullptr, s);
+            coarse_prolong_add(m, z, s);
+        }
         return SEM_OK;
     });
 }

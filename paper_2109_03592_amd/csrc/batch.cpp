@@ -518,6 +518,7 @@ static int admit_slot(sem_batch *B, sem_mesh *m, const double *b, double *x, con
     if (o.precision == SEM_PREC_MIXED && !m->with_fp32) fail(SEM_EINVAL, "mixed precision needs SEM_WITH_FP32");
     if (m->helm) fail(SEM_EUNSUPPORTED, "batched solves take the Poisson operator only (sem_set_helmholtz is set)");
     if (m->coarse) fail(SEM_EUNSUPPORTED, "batched solves use Jacobi only (sem_set_coarse is set)");
+    if (m->schwarz) fail(SEM_EUNSUPPORTED, "batched solves use Jacobi only (sem_set_schwarz is set)");
     const int id = free_slot_index(B);
     if (id < 0) fail(SEM_EBUDGET, "no free slot");
     const size_t need = slot_bytes(m, o.precision);

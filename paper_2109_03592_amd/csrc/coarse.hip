@@ -155,8 +155,8 @@ __global__ __launch_bounds__(256) void restrict_elem_kernel(int64_t E, const T *
 
 // CG update with the coarse restriction fused in: r -= alpha w, the partial
 // pairs of <r,r> and <r, invdiag r> per workgroup (FP64 sums, the products
-// as in the plain update), and the element restriction sums of the new r;
-// one wavefront per element.
+// as in the plain update; the second 0 unless with_rz), and the element
+// restriction sums of the new r; one wavefront per element.
 template <typename T, int N>
 __global__ __launch_bounds__(256) void update_restrict_kernel(int64_t E, const PcgState *__restrict__ st,
                                                               T *__restrict__ r, const T *__restrict__ w,
@@ -164,7 +164,7 @@ __global__ __launch_bounds__(256) void update_restrict_kernel(int64_t E, const P
                                                               const uint8_t *__restrict__ mult,
                                                               const double *__restrict__ qw,
                                                               double *__restrict__ partial,
-                                                              double *__restrict__ partial8)
+                                                              double *__restrict__ partial8, int with_rz)
 {
     constexpr int P = N + 1, P3 = P * P * P;
     if (st->done) return;
@@ -186,7 +186,7 @@ __global__ __launch_bounds__(256) void update_restrict_kernel(int64_t E, const P
             const double im = 1.0 / (double)ld_stream(mult + o);
             const double rd = (double)rv;
             rr += rd * rd * im;
-            rz += rd * (double)(iv * rv) * im;
+            if (with_rz) rz += rd * (double)(iv * rv) * im;
             hat_add<N>(sqw, q, iv > T(0) ? rd * im : 0.0, s);
         }
         wave_sum8(s);
@@ -488,23 +488,25 @@ CoarseSpace *coarse_build(sem_mesh *m, int k, double frac, hipStream_t s)
 static int elem_blocks(int64_t E) { return (int)std::max<int64_t>(1, std::min<int64_t>((E + 3) / 4, 8192)); }
 
 template <typename T>
-int coarse_update(sem_mesh *m, T *r, const T *w, const T *inv, const PcgState *st, double *partial, hipStream_t s)
+int coarse_update(sem_mesh *m, T *r, const T *w, const T *inv, const PcgState *st, double *partial, bool with_rz,
+                  hipStream_t s)
 {
     CoarseSpace *C = m->coarse;
     const int64_t E = m->h.E;
     const int blocks = elem_blocks(E);
+    const int rz = with_rz ? 1 : 0;
 #define SEM_UPD(n)                                                                                              \
     hipLaunchKernelGGL((update_restrict_kernel<T, n>), dim3(blocks), dim3(256), 0, s, E, st, r, w, inv, m->mult, \
-                       C->qw, partial, C->partial8)
+                       C->qw, partial, C->partial8, rz)
     SEM_COARSE_ORDER_SWITCH(m->h.N, SEM_UPD)
 #undef SEM_UPD
     SEM_HIP(hipGetLastError());
     return blocks;
 }
 template int coarse_update<double>(sem_mesh *, double *, const double *, const double *, const PcgState *, double *,
-                                   hipStream_t);
+                                   bool, hipStream_t);
 template int coarse_update<float>(sem_mesh *, float *, const float *, const float *, const PcgState *, double *,
-                                  hipStream_t);
+                                  bool, hipStream_t);
 
 template <typename T>
 void coarse_restrict(sem_mesh *m, const T *r, const T *inv, hipStream_t s)
@@ -544,17 +546,18 @@ int coarse_solve(sem_mesh *m, double *dot_pairs, const PcgState *st, hipStream_t
     return C->dot_blocks;
 }
 
-void precond_apply(sem_mesh *m, const double *r, double *z, hipStream_t s)
+void coarse_prolong_add(sem_mesh *m, double *z, hipStream_t s)
 {
     CoarseSpace *C = m->coarse;
     const int64_t nL = m->h.nL;
-    hipLaunchKernelGGL(jacobi_kernel, dim3(vec_blocks(nL)), dim3(256), 0, s, nL, m->inv64, r, z);
-    SEM_HIP(hipGetLastError());
-    if (!C) return;
-    coarse_restrict<double>(m, r, m->inv64, s);
-    coarse_solve(m, nullptr, nullptr, s);
     hipLaunchKernelGGL(prolong_add_kernel, dim3(vec_blocks(nL)), dim3(256), 0, s, m->h.E, m->h.N + 1, C->evert, C->z0,
                        C->qw, m->inv64, z);
+    SEM_HIP(hipGetLastError());
+}
+
+void launch_jacobi(int64_t n, const double *inv, const double *r, double *z, hipStream_t s)
+{
+    hipLaunchKernelGGL(jacobi_kernel, dim3(vec_blocks(n)), dim3(256), 0, s, n, inv, r, z);
     SEM_HIP(hipGetLastError());
 }
 

@@ -42,8 +42,11 @@ void coarse_free(CoarseSpace *C);
 // CG update (precision T) with the restriction fused in: r -= alpha w,
 // partial pairs of <r,r>, <r, inv r> into `partial` (returns their count),
 // element restriction sums of the new r.  Skips when st->done.
+// with_rz = false: the second entry of each pair is 0 (another local
+// preconditioner supplies <r, z>).
 template <typename T>
-int coarse_update(sem_mesh *m, T *r, const T *w, const T *inv, const PcgState *st, double *partial, hipStream_t s);
+int coarse_update(sem_mesh *m, T *r, const T *w, const T *inv, const PcgState *st, double *partial, bool with_rz,
+                  hipStream_t s);
 // element restriction sums of r (live nodes: inv > 0)
 template <typename T>
 void coarse_restrict(sem_mesh *m, const T *r, const T *inv, hipStream_t s);
@@ -51,7 +54,9 @@ void coarse_restrict(sem_mesh *m, const T *r, const T *inv, hipStream_t s);
 // given the (0, r0.z0) pairs there (returns their count, C->dot_blocks);
 // kernels skip when st->done.
 int coarse_solve(sem_mesh *m, double *dot_pairs, const PcgState *st, hipStream_t s);
-// z = D^-1 r (+ P C(A0) P^T r when the coarse space is set)
-void precond_apply(sem_mesh *m, const double *r, double *z, hipStream_t s);
+// z += masked P z0 (z0 from the last coarse_solve)
+void coarse_prolong_add(sem_mesh *m, double *z, hipStream_t s);
+// z = inv r
+void launch_jacobi(int64_t n, const double *inv, const double *r, double *z, hipStream_t s);
 
 }  // namespace sem

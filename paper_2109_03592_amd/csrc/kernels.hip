@@ -194,14 +194,14 @@ __global__ __launch_bounds__(256) void pcg_init_kernel(int64_t n, const T *__res
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
         const double rd = (double)r[q], im = inv_mult(mult[q]);
         rr += rd * rd * im;
-        rz += rd * (double)(inv[q] * r[q]) * im;
+        if (inv) rz += rd * (double)(inv[q] * r[q]) * im;
     }
     double v[2] = {rr, rz};
     block_reduce_store<2>(v, partial, 2);
 }
 
 // CG update after the gather-scatter: r -= alpha w; partials of <r,r> and
-// <r, invdiag r>.  (x += alpha p is applied by the next operator launch, or
+// <r, invdiag r> (0 when inv is null: another preconditioner forms <r,z>).  (x += alpha p is applied by the next operator launch, or
 // by pcg_finish_kernel at the end of the run.)  Two consecutive entries per
 // lane and step over a wide grid (more waves in flight beat more steps in
 // flight per lane here).
@@ -241,7 +241,9 @@ __global__ __launch_bounds__(256) void pcg_update_kernel(int64_t n, const PcgSta
         for (int u = 0; u < U; ++u) {
             const int64_t q = q0 + u * S;
             if (q < n2) {
-                rv[u] = ld_stream(r2 + q); wv[u] = ld_stream(w2 + q); iv[u] = ld_stream(i2 + q);
+                rv[u] = ld_stream(r2 + q); wv[u] = ld_stream(w2 + q);
+                if (inv) iv[u] = ld_stream(i2 + q);
+                else iv[u].x = iv[u].y = T(0);
                 mm[u] = ld_stream(m2 + q);
             }
         }
@@ -264,7 +266,7 @@ __global__ __launch_bounds__(256) void pcg_update_kernel(int64_t n, const PcgSta
         r[q] = rq;
         const double rd = (double)rq, im = inv_mult(mult[q]);
         rr += rd * rd * im;
-        rz += rd * (double)(inv[q] * rq) * im;
+        if (inv) rz += rd * (double)(inv[q] * rq) * im;
     }
     double v[2] = {rr, rz};
     block_reduce_store<2>(v, partial, 2);
@@ -498,9 +500,10 @@ static hipError_t launch_ax_node(int N, const AxParams<T> &a, hipStream_t s)
 template <typename T, int MODE, bool HELM>
 static hipError_t launch_ax_mode(int N, const AxParams<T> &a, hipStream_t s)
 {
-    if constexpr (MODE == 3) {
-        // the coarse correction runs in the column kernel only
-        if (a.kind != 0 || !a.evert || !a.z0 || !a.cq) return hipErrorInvalidValue;
+    if constexpr (MODE >= 3) {
+        // the coarse correction and a given residual run in the column kernel only
+        if (a.kind != 0) return hipErrorInvalidValue;
+        if ((MODE == 3 || MODE == 5) && (!a.evert || !a.z0 || !a.cq)) return hipErrorInvalidValue;
     } else {
         if (a.kind == 1) return launch_ax_node<T, MODE, HELM>(N, a, s);
     }
@@ -526,6 +529,14 @@ hipError_t launch_ax(int N, int mode, const AxParams<T> &a, hipStream_t s)
     if (mode == 3) {
         if (a.h1) return launch_ax_mode<T, 3, true>(N, a, s);
         return launch_ax_mode<T, 3, false>(N, a, s);
+    }
+    if (mode == 4 || mode == 5) {
+        // the preconditioned residual is given (FP64 solves)
+        if constexpr (sizeof(T) == 8) {
+            if (mode == 4) return a.h1 ? launch_ax_mode<T, 4, true>(N, a, s) : launch_ax_mode<T, 4, false>(N, a, s);
+            return a.h1 ? launch_ax_mode<T, 5, true>(N, a, s) : launch_ax_mode<T, 5, false>(N, a, s);
+        }
+        return hipErrorInvalidValue;
     }
     if (a.h1) {
         if (mode == 0) return launch_ax_mode<T, 0, true>(N, a, s);

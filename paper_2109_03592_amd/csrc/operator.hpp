@@ -262,6 +262,8 @@ struct ColumnIndex {
 // correction added to the preconditioned residual, p <- invdiag*r +
 // sum_c phi_c z0[evert[e][c]] + beta*p at live nodes (invdiag > 0), phi_c the
 // trilinear hat of corner c (c = cx + 2cy + 4cz) with 1-D weights cq[side][i].
+// MODE 4 (CG with a preconditioned residual given, e.g. by the Schwarz local
+// solves): p <- in + beta*p.  MODE 5: MODE 4 plus the coarse correction.
 template <typename T, int N, int MODE, int LAYOUT = 0, bool HELM = false>
 __device__ inline void ax_tile(const LaneRows<T, N> &R, const T *__restrict__ D, T *su, int64_t e, bool active,
                                bool inblk, int i, int j, const T *__restrict__ G, const T *__restrict__ in,
@@ -277,10 +279,11 @@ __device__ inline void ax_tile(const LaneRows<T, N> &R, const T *__restrict__ D,
     const ColumnIndex<N, LAYOUT> ci(i, j);
     const int64_t eb = (active ? e : 0) * P3;
     T uc[P];
+    constexpr bool kCoarse = MODE == 3 || MODE == 5;
     if (MODE >= 2) {
         // coarse correction of this column (FP64): bilinear in (i,j) per t-side
         double cs0 = 0, cs1 = 0;
-        if (MODE == 3 && active) {
+        if (kCoarse && active) {
             const int32_t *ev = evert + e * 8;
             double zc[8];
 #pragma unroll
@@ -297,9 +300,14 @@ __device__ inline void ax_tile(const LaneRows<T, N> &R, const T *__restrict__ D,
                 const T pold = ld_stream(p + o);
                 // the previous iteration's x step, deferred to here where p is read anyway
                 st_stream(ld_stream(x + o) + alpha * pold, x + o);
-                const T iv = ld_stream(invdiag + o);
-                v = iv * ld_stream(in + o) + beta * pold;
-                if (MODE == 3 && iv > T(0)) v += (T)(cq[k] * cs0 + cq[P + k] * cs1);
+                if (MODE >= 4) {
+                    v = ld_stream(in + o) + beta * pold;
+                    if (kCoarse && ld_stream(invdiag + o) > T(0)) v += (T)(cq[k] * cs0 + cq[P + k] * cs1);
+                } else {
+                    const T iv = ld_stream(invdiag + o);
+                    v = iv * ld_stream(in + o) + beta * pold;
+                    if (kCoarse && iv > T(0)) v += (T)(cq[k] * cs0 + cq[P + k] * cs1);
+                }
                 st_stream(v, p + o);
             }
             uc[k] = v;

@@ -82,7 +82,8 @@ struct DeviceBuf {
     size_t bytes = 0;
 };
 
-struct CoarseSpace;  // coarse.hpp
+struct CoarseSpace;   // coarse.hpp
+struct SchwarzSpace;  // schwarz.hpp
 
 }  // namespace sem
 
@@ -109,6 +110,8 @@ struct sem_mesh {
     float *h1_32 = nullptr, *h2b32 = nullptr;
     // coarse term of the FP64 preconditioner (sem_set_coarse); nullptr: Jacobi
     sem::CoarseSpace *coarse = nullptr;
+    // overlapping Schwarz local solves in place of Jacobi (sem_set_schwarz, FP64 solves)
+    sem::SchwarzSpace *schwarz = nullptr;
     // Krylov work space, allocated on the first solve
     double *x64 = nullptr, *r64 = nullptr, *p64 = nullptr, *w64 = nullptr;
     float *x32 = nullptr, *r32 = nullptr, *p32 = nullptr, *w32 = nullptr;
