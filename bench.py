@@ -260,17 +260,20 @@ def helmholtz_section(mesh, b, args, torch, SI, stream):
 
 
 def coarse_section(mesh, b, args, torch, stream, jacobi_solve=None):
-    """Two-level preconditioner (Jacobi + the coarse term of Eq. 6) on the
-    same mesh and right-hand side: coarse-space build time, profiled PCG
-    iterations and a full FP64 solve to 1e-10 per (Chebyshev steps, interval
-    fraction) setting; the mesh is back on Jacobi afterwards."""
-    nG = mesh.n_global
+    """Two-level preconditioners of Eq. 6 on the same mesh and right-hand
+    side.  Each setting is "k:fraction" (Jacobi + coarse term with k Chebyshev
+    steps on [fraction b, b]), "s" (Schwarz local solves only) or
+    "s+k:fraction" (Schwarz + coarse): set-up time, profiled PCG iterations,
+    a full FP64 solve to 1e-10 and, without Schwarz, a mixed one.  The mesh is
+    back on Jacobi afterwards."""
     rows = []
     for item in args.coarse.split(","):
-        k, frac = item.split(":")
-        k, frac = int(k), float(frac)
+        schwarz = item.startswith("s")
+        rest = item[2:] if item.startswith("s+") else ("" if schwarz else item)
+        k, frac = (int(rest.split(":")[0]), float(rest.split(":")[1])) if rest else (0, 0.0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        mesh.set_schwarz(schwarz)
         mesh.set_coarse(k, frac)
         t_build = time.perf_counter() - t0
         info = mesh.coarse_info()
@@ -289,6 +292,17 @@ def coarse_section(mesh, b, args, torch, stream, jacobi_solve=None):
         e1.record(stream)
         torch.cuda.synchronize()
         t_graph = e0.elapsed_time(e1) / 1e3 / args.steps
+        row = {"setting": item, "schwarz": schwarz, "chebyshev_steps": k, "fraction": frac,
+               "n_coarse": info["n_coarse"], "cheb_b": info["b"], "setup_s": t_build,
+               "ms_per_iteration": t_it * 1e3, "ms_per_iteration_graph": t_graph * 1e3,
+               "ms_operator": res.ms_operator / n, "ms_gather_scatter": res.ms_gather_scatter / n,
+               "ms_update_and_preconditioner": res.ms_update / n}
+        msg = (f"precond {item}: set-up {t_build:.2f} s; {t_it * 1e3:.3f} ms/iteration ({t_graph * 1e3:.3f} graph; "
+               f"operator {row['ms_operator']:.3f}, update+precond {row['ms_update_and_preconditioner']:.3f})")
+        if args.no_solve:
+            log(msg)
+            rows.append(row)
+            continue
         x = mesh.zeros()
         torch.cuda.synchronize()
         tS = time.perf_counter()
@@ -296,32 +310,32 @@ def coarse_section(mesh, b, args, torch, stream, jacobi_solve=None):
                           raise_on_error=False)
         torch.cuda.synchronize()
         ts = time.perf_counter() - tS
-        x = mesh.zeros()
-        torch.cuda.synchronize()
-        tS = time.perf_counter()
-        _, rm = mesh.solve(b, x, tol=1e-10, max_iter=40000, precision="mixed", inner_tol=1e-4, poll_every=50,
-                           initial_guess=False, raise_on_error=False)
-        torch.cuda.synchronize()
-        tm = time.perf_counter() - tS
-        row = {"chebyshev_steps": k, "fraction": frac, "n_vertices": info["n_vertices"],
-               "n_coarse": info["n_coarse"], "nnz": info["nnz"], "cheb_a": info["a"], "cheb_b": info["b"],
-               "build_s": t_build, "ms_per_iteration": t_it * 1e3, "ms_per_iteration_graph": t_graph * 1e3,
+        row = {**row, "setting": item, "schwarz": schwarz, "chebyshev_steps": k, "fraction": frac,
+               "n_coarse": info["n_coarse"], "cheb_b": info["b"], "setup_s": t_build,
+               "ms_per_iteration": t_it * 1e3, "ms_per_iteration_graph": t_graph * 1e3,
                "ms_operator": res.ms_operator / n, "ms_gather_scatter": res.ms_gather_scatter / n,
-               "ms_update_and_coarse": res.ms_update / n,
+               "ms_update_and_preconditioner": res.ms_update / n,
                "solve": {"status": r.status, "iterations": r.iterations, "rel_residual": r.rel_residual,
-                         "seconds": ts},
-               "solve_mixed": {"status": rm.status, "iterations": rm.iterations, "outer": rm.outer_iterations,
-                               "rel_residual": rm.rel_residual, "seconds": tm}}
+                         "seconds": ts}}
         if jacobi_solve:
             row["speedup_vs_jacobi"] = jacobi_solve["seconds"] / ts
             row["iteration_ratio_vs_jacobi"] = jacobi_solve["iterations"] / max(1, r.iterations)
-        log(f"coarse k={k} a={frac}b: build {t_build:.2f} s, {info['n_coarse']} coarse unknowns; "
-            f"{t_it * 1e3:.3f} ms/iteration ({t_graph * 1e3:.3f} graph; operator {row['ms_operator']:.3f}, "
-            f"update+coarse {row['ms_update_and_coarse']:.3f}); solve status={r.status} iters={r.iterations} "
-            f"rel_res={r.rel_residual:.2e} {ts:.2f} s; mixed status={rm.status} iters={rm.iterations} "
-            f"outer={rm.outer_iterations} rel_res={rm.rel_residual:.2e} {tm:.2f} s")
+        msg += f"; solve status={r.status} iters={r.iterations} rel_res={r.rel_residual:.2e} {ts:.2f} s"
+        if not schwarz:
+            x = mesh.zeros()
+            torch.cuda.synchronize()
+            tS = time.perf_counter()
+            _, rm = mesh.solve(b, x, tol=1e-10, max_iter=40000, precision="mixed", inner_tol=1e-4,
+                               poll_every=50, initial_guess=False, raise_on_error=False)
+            torch.cuda.synchronize()
+            tm = time.perf_counter() - tS
+            row["solve_mixed"] = {"status": rm.status, "iterations": rm.iterations, "outer": rm.outer_iterations,
+                                  "rel_residual": rm.rel_residual, "seconds": tm}
+            msg += f"; mixed iters={rm.iterations} outer={rm.outer_iterations} {tm:.2f} s"
+        log(msg)
         rows.append(row)
     mesh.set_coarse(0)
+    mesh.set_schwarz(False)
     return rows
 
 
@@ -479,8 +493,11 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-mesh solves")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
     ap.add_argument("--no-helm", action="store_true", help="skip the Helmholtz-form timing")
-    ap.add_argument("--coarse", default="10:0.01",
-                    help="two-level preconditioner settings steps:fraction[,...] ('' skips)")
+    ap.add_argument("--coarse-smooth", default="",
+                    help="the same preconditioner settings on a smooth right-hand side (sin forcing)")
+    ap.add_argument("--coarse", default="4:0.05,s+4:0.05",
+                    help="preconditioner settings: k:fraction (Jacobi + coarse), s (Schwarz), s+k:fraction "
+                         "(Schwarz + coarse), comma-separated ('' skips)")
     ap.add_argument("--no-proj", action="store_true", help="skip the successive-RHS projection timing")
     ap.add_argument("--no-n9", action="store_true", help="skip the N=9 pipe (48x48x48)")
     ap.add_argument("--operator-kernel", choices=("column", "node"), default=None,
@@ -605,8 +622,7 @@ def main():
             sol[prec] = {"status": r.status, "iterations": r.iterations, "outer": r.outer_iterations,
                          "rel_residual": r.rel_residual, "seconds": ts, "solves_per_s": 1.0 / ts}
             log(f"solve {prec}: status={r.status} iters={r.iterations} outer={r.outer_iterations} "
-                f"rel_res={r.rel_residual:.2e} {ts:.2f} s; mixed status={rm.status} iters={rm.iterations} "
-            f"outer={rm.outer_iterations} rel_res={rm.rel_residual:.2e} {tm:.2f} s")
+                f"rel_res={r.rel_residual:.2e} {ts:.2f} s")
             if prec == "fp64":
                 x64 = x.clone()
             else:
@@ -616,10 +632,33 @@ def main():
         sol["mixed_speedup"] = sol["fp64"]["seconds"] / sol["mixed"]["seconds"]
         out["solve"] = sol
 
-    # ---- Jacobi + coarse term of Eq. 6 on the same mesh and right-hand side ----
+    # ---- the preconditioners of Eq. 6 (coarse term, Schwarz local solves) ------
     if args.coarse:
         out["coarse"] = coarse_section(mesh, b, args, torch, stream,
                                        out.get("solve", {}).get("fp64"))
+    if args.coarse_smooth:
+        # a smooth right-hand side: b = mask(Q Q^T B f), f = 3 pi^2 sin(pi x) sin(pi y) sin(pi z)
+        xyz = mesh.export_coords()
+        f = torch.from_numpy(SI.sin3_forcing(xyz[0], xyz[1], xyz[2])).cuda()
+        del xyz
+        bs = mesh.empty()
+        mesh.mass(f, bs)
+        del f
+        base = None
+        if not args.no_solve:
+            x = mesh.zeros()
+            torch.cuda.synchronize()
+            tS = time.perf_counter()
+            _, r = mesh.solve(bs, x, tol=1e-10, max_iter=40000, poll_every=50, initial_guess=False,
+                              raise_on_error=False)
+            torch.cuda.synchronize()
+            base = {"status": r.status, "iterations": r.iterations, "seconds": time.perf_counter() - tS}
+            log(f"smooth rhs, Jacobi: iters={r.iterations} {base['seconds']:.2f} s")
+        saved = args.coarse
+        args.coarse = args.coarse_smooth
+        out["coarse_smooth_rhs"] = {"jacobi": base, "settings": coarse_section(mesh, bs, args, torch, stream, base)}
+        args.coarse = saved
+        del bs
 
     # ---- Helmholtz form (h1-weighted stiffness + h2 B) on the same mesh ------
     if not args.no_helm:

@@ -19,7 +19,8 @@
 //    (assemble_kernel): a node receives the contributions of all extended
 //    elements that hold it, added in ascending (unwrapped) element order per
 //    direction, so every copy of a shared node gets the same bits.
-//  * <r, z> for CG is taken inside fdm_kernel as sum_k (R_k r) . y_k.
+//  * <r, z> for CG is taken inside fdm_kernel as sum_k (R_k r) . y_k, i.e. the
+//    sum over modes of yhat^2 / (lam_r + lam_s + lam_t), yhat = S^T R_k r.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -60,8 +61,27 @@ __host__ __device__ inline int ext_hi(const Lattice &L, int N, int d, int pos)
 // device kernels
 
 // One workgroup per element (persistent walk); lane (l0, l1) < n^2 owns one
-// line of the extended element in every contraction stage.  The lane's line
-// of R_k r (along r) stays in registers for the dot product.
+// line of the extended element in every contraction stage.  Each stage runs
+// over the contracted index (inputs from LDS, one row of S per step) and
+// keeps the line's n outputs in registers.  <R_k r, y_k> equals
+// sum over modes of yhat^2 / (lam_r + lam_s + lam_t), yhat = S^T R_k r, and is
+// taken where the scaling is applied.
+template <int N>
+__device__ inline void fdm_line(const double *__restrict__ Sd, const double *__restrict__ in, int in_stride,
+                                double (&acc)[N + 3], bool transpose)
+{
+    constexpr int n = N + 3;
+#pragma unroll
+    for (int b = 0; b < n; ++b) acc[b] = 0.0;
+#pragma unroll 2
+    for (int a = 0; a < n; ++a) {
+        const double x = in[a * in_stride];
+        // transpose: acc[b] += S[a][b] x (S^T applied); else acc[b] += S[b][a] x
+#pragma unroll
+        for (int b = 0; b < n; ++b) acc[b] += (transpose ? Sd[a * n + b] : Sd[b * n + a]) * x;
+    }
+}
+
 template <int N>
 __global__ __launch_bounds__(256) void fdm_kernel(int64_t E, Lattice L, const double *__restrict__ r,
                                                   const int32_t *__restrict__ tidx,
@@ -78,6 +98,7 @@ __global__ __launch_bounds__(256) void fdm_kernel(int64_t E, Lattice L, const do
     const bool line = tid < n2;
     const int l0 = tid % n, l1 = tid / n;
     double dot = 0.0;
+    double acc[n];
     for (int64_t e = blockIdx.x; e < E; e += gridDim.x) {
         const int pos[3] = {(int)(e % L.nel[0]), (int)((e / L.nel[0]) % L.nel[1]),
                             (int)(e / ((int64_t)L.nel[0] * L.nel[1]))};
@@ -93,115 +114,76 @@ __global__ __launch_bounds__(256) void fdm_kernel(int64_t E, Lattice L, const do
             else Lm[d][o - n2] = v;
         }
         __syncthreads();
-        // R_k r along the lane's line (s = l0, t = l1), from the element or a
-        // neighbour (r is continuous: any copy of a node holds its value)
-        double rl[n], in[n], out[n];
+        // R_k r: extended node (a, b, c) from the element or a neighbour (r is
+        // continuous: any copy of a node holds its value); 0 beyond the kept range
+        for (int q = tid; q < n3; q += blockDim.x) {
+            const int a[3] = {q % n, (q / n) % n, q / n2};
+            double v = 0.0;
+            if (a[0] < cnt[0] && a[1] < cnt[1] && a[2] < cnt[2]) {
+                int ep[3], loc[3];
+                bool ok = true;
 #pragma unroll
-        for (int a = 0; a < n; ++a) rl[a] = 0.0;
-        if (line && l0 < cnt[1] && l1 < cnt[2]) {
-            int ep[3], loc[3];
-            bool ok = true;
-            const int ext1 = lo[1] + l0, ext2 = lo[2] + l1;
-            const int exts[2] = {ext1, ext2};
-#pragma unroll
-            for (int d = 1; d < 3; ++d) {
-                const int v = exts[d - 1];
-                int p2 = pos[d], lc = v;
-                if (v == -1) { p2 -= 1; lc = N - 1; }
-                else if (v == N + 1) { p2 += 1; lc = 1; }
-                if (p2 < 0) p2 += L.nel[d];
-                if (p2 >= L.nel[d]) p2 -= L.nel[d];
-                ok = ok && p2 >= 0 && p2 < L.nel[d];
-                ep[d] = p2;
-                loc[d] = lc;
-            }
-#pragma unroll
-            for (int a = 0; a < n; ++a) {
-                if (a < cnt[0] && ok) {
-                    const int v = lo[0] + a;
-                    int p2 = pos[0], lc = v;
-                    if (v == -1) { p2 -= 1; lc = N - 1; }
-                    else if (v == N + 1) { p2 += 1; lc = 1; }
-                    if (p2 < 0) p2 += L.nel[0];
-                    if (p2 >= L.nel[0]) p2 -= L.nel[0];
-                    if (p2 >= 0 && p2 < L.nel[0]) {
-                        const int64_t e2 = p2 + (int64_t)L.nel[0] * (ep[1] + (int64_t)L.nel[1] * ep[2]);
-                        rl[a] = r[e2 * P3 + lc + P * loc[1] + P2 * loc[2]];
-                    }
+                for (int d = 0; d < 3; ++d) {
+                    const int x = lo[d] + a[d];
+                    int p2 = pos[d], lc = x;
+                    if (x == -1) { p2 -= 1; lc = N - 1; }
+                    else if (x == N + 1) { p2 += 1; lc = 1; }
+                    if (p2 < 0) p2 += L.nel[d];
+                    if (p2 >= L.nel[d]) p2 -= L.nel[d];
+                    ok = ok && p2 >= 0 && p2 < L.nel[d];
+                    ep[d] = p2;
+                    loc[d] = lc;
+                }
+                if (ok) {
+                    const int64_t e2 = ep[0] + (int64_t)L.nel[0] * (ep[1] + (int64_t)L.nel[1] * ep[2]);
+                    v = r[e2 * P3 + loc[0] + P * loc[1] + P2 * loc[2]];
                 }
             }
-        }
-        // 1: along r, S_r^T
-        if (line) {
-#pragma unroll
-            for (int b = 0; b < n; ++b) {
-                double s = 0.0;
-#pragma unroll
-                for (int i = 0; i < n; ++i) s += S[0][i * n + b] * rl[i];
-                V[l1 * n2 + l0 * n + b] = s;
-            }
+            U[q] = v;
         }
         __syncthreads();
-        // 2: along s, S_s^T (line r' = l0, t = l1)
+        // 1: along r, S_r^T (line s = l0, t = l1): U -> V
         if (line) {
+            fdm_line<N>(S[0], U + l1 * n2 + l0 * n, 1, acc, true);
 #pragma unroll
-            for (int j = 0; j < n; ++j) in[j] = V[l1 * n2 + j * n + l0];
-#pragma unroll
-            for (int b = 0; b < n; ++b) {
-                double s = 0.0;
-#pragma unroll
-                for (int j = 0; j < n; ++j) s += S[1][j * n + b] * in[j];
-                U[l1 * n2 + b * n + l0] = s;
-            }
+            for (int b = 0; b < n; ++b) V[l1 * n2 + l0 * n + b] = acc[b];
         }
         __syncthreads();
-        // 3: along t, S_t^T, the eigenvalue scaling, then S_t (line r' = l0, s' = l1)
+        // 2: along s, S_s^T (line r' = l0, t = l1): V -> U
         if (line) {
+            fdm_line<N>(S[1], V + l1 * n2 + l0, n, acc, true);
 #pragma unroll
-            for (int k = 0; k < n; ++k) in[k] = U[k * n2 + l1 * n + l0];
+            for (int b = 0; b < n; ++b) U[l1 * n2 + b * n + l0] = acc[b];
+        }
+        __syncthreads();
+        // 3: along t, S_t^T, scaling, S_t (line r' = l0, s' = l1): U -> V -> V
+        if (line) {
+            fdm_line<N>(S[2], U + l1 * n + l0, n2, acc, true);
             const double lrs = Lm[0][l0] + Lm[1][l1];
 #pragma unroll
             for (int b = 0; b < n; ++b) {
-                double s = 0.0;
-#pragma unroll
-                for (int k = 0; k < n; ++k) s += S[2][k * n + b] * in[k];
                 const double den = lrs + Lm[2][b];
-                out[b] = den > 0.0 ? s / den : 0.0;
+                const double y = den > 0.0 ? acc[b] / den : 0.0;
+                dot += acc[b] * y;
+                V[b * n2 + l1 * n + l0] = y;
             }
+            fdm_line<N>(S[2], V + l1 * n + l0, n2, acc, false);
 #pragma unroll
-            for (int k = 0; k < n; ++k) {
-                double s = 0.0;
-#pragma unroll
-                for (int b = 0; b < n; ++b) s += S[2][k * n + b] * out[b];
-                V[k * n2 + l1 * n + l0] = s;
-            }
+            for (int k = 0; k < n; ++k) V[k * n2 + l1 * n + l0] = acc[k];
         }
         __syncthreads();
-        // 4: along s, S_s (line r = l0, t = l1)
+        // 4: along s, S_s (line r = l0, t = l1): V -> U
         if (line) {
+            fdm_line<N>(S[1], V + l1 * n2 + l0, n, acc, false);
 #pragma unroll
-            for (int b = 0; b < n; ++b) in[b] = V[l1 * n2 + b * n + l0];
-#pragma unroll
-            for (int j = 0; j < n; ++j) {
-                double s = 0.0;
-#pragma unroll
-                for (int b = 0; b < n; ++b) s += S[1][j * n + b] * in[b];
-                U[l1 * n2 + j * n + l0] = s;
-            }
+            for (int j = 0; j < n; ++j) U[l1 * n2 + j * n + l0] = acc[j];
         }
         __syncthreads();
-        // 5: along r, S_r (line s = l0, t = l1); (R_k r) . y_k
+        // 5: along r, S_r (line s = l0, t = l1): U -> V
         if (line) {
+            fdm_line<N>(S[0], U + l1 * n2 + l0 * n, 1, acc, false);
 #pragma unroll
-            for (int b = 0; b < n; ++b) in[b] = U[l1 * n2 + l0 * n + b];
-#pragma unroll
-            for (int i = 0; i < n; ++i) {
-                double s = 0.0;
-#pragma unroll
-                for (int b = 0; b < n; ++b) s += S[0][i * n + b] * in[b];
-                V[l1 * n2 + l0 * n + i] = s;
-                dot += rl[i] * s;
-            }
+            for (int i = 0; i < n; ++i) V[l1 * n2 + l0 * n + i] = acc[i];
         }
         __syncthreads();
         for (int q = tid; q < n3; q += blockDim.x) st_stream(V[q], zext + e * n3 + q);
