@@ -304,7 +304,7 @@ static X *cmalloc(CoarseSpace *C, size_t count)
 void coarse_free(CoarseSpace *C)
 {
     if (!C) return;
-    for (void *p : C->allocations) hipFree(p);
+    for (void *p : C->allocations) (void)hipFree(p);
     delete C;
 }
 

@@ -45,18 +45,6 @@ __host__ __device__ inline bool has_right(const Lattice &L, int d, int pos)
 {
     return pos < L.nel[d] - 1 || L.periodic[d];
 }
-// first and last kept extended index of direction d at lattice position pos
-__host__ __device__ inline int ext_lo(const Lattice &L, int N, int d, int pos)
-{
-    if (has_left(L, d, pos)) return -1;
-    return ((L.dirichlet >> (2 * d)) & 1) ? 1 : 0;
-}
-__host__ __device__ inline int ext_hi(const Lattice &L, int N, int d, int pos)
-{
-    if (has_right(L, d, pos)) return N + 1;
-    return ((L.dirichlet >> (2 * d + 1)) & 1) ? N - 1 : N;
-}
-
 // ---------------------------------------------------------------------------
 // device kernels
 
@@ -92,28 +80,26 @@ __global__ __launch_bounds__(256) void fdm_kernel(int64_t E, Lattice L, const do
     constexpr int P = N + 1, P2 = P * P, P3 = P2 * P;
     constexpr int n = N + 3, n2 = n * n, n3 = n2 * n, TE = n2 + n;
     if (st && st->done) return;
-    __shared__ double U[n3], V[n3], S[3][n2], Lm[3][n];
-    __shared__ int lo[3], cnt[3];
+    __shared__ double U[n3], V[n3];
     const int tid = threadIdx.x;
     const bool line = tid < n2;
     const int l0 = tid % n, l1 = tid / n;
     double dot = 0.0;
     double acc[n];
     for (int64_t e = blockIdx.x; e < E; e += gridDim.x) {
-        const int pos[3] = {(int)(e % L.nel[0]), (int)((e / L.nel[0]) % L.nel[1]),
-                            (int)(e / ((int64_t)L.nel[0] * L.nel[1]))};
-        if (tid < 3) {
-            const int t = tidx[e * 3 + tid];
-            lo[tid] = meta[2 * t];
-            cnt[tid] = meta[2 * t + 1];
+        const int ei = (int)e;
+        const int pos[3] = {ei % L.nel[0], (ei / L.nel[0]) % L.nel[1], ei / (L.nel[0] * L.nel[1])};
+        // the element's 1-D factors: workgroup-uniform addresses (scalar loads)
+        const double *S[3];
+        int lo[3], cnt[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int t = tidx[e * 3 + d];
+            S[d] = table + (int64_t)t * TE;
+            lo[d] = meta[2 * t];
+            cnt[d] = meta[2 * t + 1];
         }
-        for (int q = tid; q < 3 * TE; q += blockDim.x) {
-            const int d = q / TE, o = q - d * TE;
-            const double v = table[(int64_t)tidx[e * 3 + d] * TE + o];
-            if (o < n2) S[d][o] = v;
-            else Lm[d][o - n2] = v;
-        }
-        __syncthreads();
+        const double *Lm[3] = {S[0] + n2, S[1] + n2, S[2] + n2};
         // R_k r: extended node (a, b, c) from the element or a neighbour (r is
         // continuous: any copy of a node holds its value); 0 beyond the kept range
         for (int q = tid; q < n3; q += blockDim.x) {
@@ -204,48 +190,48 @@ __global__ __launch_bounds__(256) void assemble_kernel(int64_t E, Lattice L, con
 {
     constexpr int P = N + 1, P2 = P * P, P3 = P2 * P;
     constexpr int n = N + 3, n2 = n * n, n3 = n2 * n;
+    static_assert(N >= 2, "the overlap of one node layer needs N >= 2");
     if (st && st->done) return;
     const int64_t nL = E * P3;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nL; q += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t e = q / P3;
-        const int rem = (int)(q - e * P3);
+        const int ei = (int)(q / P3);
+        const int rem = (int)(q - (int64_t)ei * P3);
         const int idx[3] = {rem % P, (rem / P) % P, rem / P2};
-        const int pos[3] = {(int)(e % L.nel[0]), (int)((e / L.nel[0]) % L.nel[1]),
-                            (int)(e / ((int64_t)L.nel[0] * L.nel[1]))};
-        // per direction and offset delta (ascending): whether element pos+delta
-        // holds the node in its kept range, and the node's position there
-        constexpr int DM = N == 1 ? 2 : 1;  // |delta| <= 1 once N >= 2
-        bool ok[3][2 * DM + 1];
-        int el[3][2 * DM + 1], ps[3][2 * DM + 1];
+        const int pos[3] = {ei % L.nel[0], (ei / L.nel[0]) % L.nel[1], ei / (L.nel[0] * L.nel[1])};
+        // per direction and offset delta in {-1, 0, 1} (ascending): whether
+        // element pos+delta holds the node in its kept range, and the node's
+        // position there (the extended index idx - delta N, less that
+        // element's first kept index)
+        bool ok[3][3];
+        int el[3][3], ps[3][3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
 #pragma unroll
-            for (int t = 0; t <= 2 * DM; ++t) {
-                const int delta = t - DM;
+            for (int t = 0; t < 3; ++t) {
+                const int delta = t - 1;
                 const int ext = idx[d] - delta * N;
                 int p2 = pos[d] + delta;
                 bool v = ext >= -1 && ext <= N + 1;
-                if (p2 < 0 || p2 >= L.nel[d]) {
-                    v = v && L.periodic[d];
-                    p2 = ((p2 % L.nel[d]) + L.nel[d]) % L.nel[d];
-                }
-                const int lo2 = ext_lo(L, N, d, p2), hi2 = ext_hi(L, N, d, p2);
-                v = v && ext >= lo2 && ext <= hi2;
-                ok[d][t] = v;
+                if (p2 < 0) { v = v && L.periodic[d]; p2 += L.nel[d]; }
+                if (p2 >= L.nel[d]) { v = v && L.periodic[d]; p2 -= L.nel[d]; }
+                const bool left = p2 > 0 || L.periodic[d], right = p2 < L.nel[d] - 1 || L.periodic[d];
+                const int lo2 = left ? -1 : ((L.dirichlet >> (2 * d)) & 1);
+                const int hi2 = right ? N + 1 : (((L.dirichlet >> (2 * d + 1)) & 1) ? N - 1 : N);
+                ok[d][t] = v && ext >= lo2 && ext <= hi2;
                 el[d][t] = p2;
                 ps[d][t] = ext - lo2;
             }
         }
         double s = 0.0;
 #pragma unroll
-        for (int tz = 0; tz <= 2 * DM; ++tz)
+        for (int tz = 0; tz < 3; ++tz)
 #pragma unroll
-            for (int ty = 0; ty <= 2 * DM; ++ty)
+            for (int ty = 0; ty < 3; ++ty)
 #pragma unroll
-                for (int tx = 0; tx <= 2 * DM; ++tx) {
+                for (int tx = 0; tx < 3; ++tx) {
                     if (!(ok[0][tx] && ok[1][ty] && ok[2][tz])) continue;
-                    const int64_t e2 = el[0][tx] + (int64_t)L.nel[0] * (el[1][ty] + (int64_t)L.nel[1] * el[2][tz]);
-                    s += zext[e2 * n3 + ps[0][tx] + n * ps[1][ty] + n2 * ps[2][tz]];
+                    const int e2 = el[0][tx] + L.nel[0] * (el[1][ty] + L.nel[1] * el[2][tz]);
+                    s += zext[(int64_t)e2 * n3 + ps[0][tx] + n * ps[1][ty] + n2 * ps[2][tz]];
                 }
         z[q] = ld_stream(inv + q) > 0.0 ? s : 0.0;
     }
@@ -347,7 +333,7 @@ static X *smalloc(SchwarzSpace *Z, size_t count)
 void schwarz_free(SchwarzSpace *Z)
 {
     if (!Z) return;
-    for (void *p : Z->allocations) hipFree(p);
+    for (void *p : Z->allocations) (void)hipFree(p);
     delete Z;
 }
 
@@ -367,6 +353,7 @@ SchwarzSpace *schwarz_build(sem_mesh *m, hipStream_t s)
     const HostMesh &h = m->h;
     const int N = h.N, P = N + 1, n = N + 3;
     const int64_t E = h.E, P3 = (int64_t)P * P * P;
+    if (E >= INT32_MAX) fail(SEM_EUNSUPPORTED, "sem_set_schwarz: too many elements");
     SchwarzSpace *Z = new SchwarzSpace();
     try {
         Z->n = n;
@@ -469,11 +456,11 @@ int schwarz_apply(sem_mesh *m, const double *r, double *z, double *pairs, const 
                            pairs, st);                                                                            \
         hipLaunchKernelGGL(assemble_kernel<n>, dim3(ab), dim3(256), 0, s, E, L, Z->zext, m->inv64, z, st);        \
         break;
-        SEM_SCHWARZ_CASE(1) SEM_SCHWARZ_CASE(2) SEM_SCHWARZ_CASE(3) SEM_SCHWARZ_CASE(4) SEM_SCHWARZ_CASE(5)
+        SEM_SCHWARZ_CASE(2) SEM_SCHWARZ_CASE(3) SEM_SCHWARZ_CASE(4) SEM_SCHWARZ_CASE(5)
         SEM_SCHWARZ_CASE(6) SEM_SCHWARZ_CASE(7) SEM_SCHWARZ_CASE(8) SEM_SCHWARZ_CASE(9) SEM_SCHWARZ_CASE(10)
         SEM_SCHWARZ_CASE(11) SEM_SCHWARZ_CASE(12)
 #undef SEM_SCHWARZ_CASE
-    default: fail(SEM_EUNSUPPORTED, "Schwarz: order out of range");
+    default: fail(SEM_EUNSUPPORTED, "Schwarz: order out of range (2..12)");
     }
     SEM_HIP(hipGetLastError());
     return fb;
