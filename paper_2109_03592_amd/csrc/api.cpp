@@ -323,6 +323,11 @@ static void enqueue_iterations(sem_mesh *m, int k, hipStream_t s, Profiler *prof
             // coarse solve's pairs follow the update's
             pairs = coarse_update<T>(m, Prec<T>::r(m), Prec<T>::w(m), Prec<T>::inv(m), st, m->partials, !schwarz, s);
             pairs += coarse_solve(m, m->partials + 2 * pairs, st, s);
+        } else if (sizeof(T) == 8 && m->h.N >= 3) {
+            // FP64: element by element (FP32 keeps the paired-entry update)
+            SEM_HIP(launch_pcg_update_elem<T>(m->h.N, m->h.E, st, Prec<T>::r(m), Prec<T>::w(m), jinv, m->mult,
+                                              m->partials, s));
+            pairs = update_elem_blocks(m->h.E);
         } else {
             SEM_HIP(launch_pcg_update<T>(nL, st, Prec<T>::r(m), Prec<T>::w(m), jinv, m->mult, m->partials, s));
         }

@@ -272,6 +272,38 @@ __global__ __launch_bounds__(256) void pcg_update_kernel(int64_t n, const PcgSta
     block_reduce_store<2>(v, partial, 2);
 }
 
+// The same update element by element: one wavefront per element, each lane
+// P^3/64 nodes at stride 64 (all their loads in flight together); the
+// partial pairs per workgroup of four wavefronts.
+template <typename T, int N>
+__global__ __launch_bounds__(256) void pcg_update_elem_kernel(int64_t E, const PcgState *__restrict__ st,
+                                                              T *__restrict__ r, const T *__restrict__ w,
+                                                              const T *__restrict__ inv,
+                                                              const uint8_t *__restrict__ mult,
+                                                              double *__restrict__ partial)
+{
+    constexpr int P = N + 1, P3 = P * P * P;
+    if (st->done) return;
+    const T alpha = (T)st->alpha;
+    const int lane = threadIdx.x & 63;
+    double rr = 0.0, rz = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); e < E; e += (int64_t)gridDim.x * 4) {
+        const int64_t base = e * P3;
+#pragma unroll
+        for (int q = lane; q < P3; q += 64) {
+            const int64_t o = base + q;
+            const T rv = ld_stream(r + o) - alpha * ld_stream(w + o);
+            st_stream(rv, r + o);
+            const double im = inv_mult(ld_stream(mult + o));
+            const double rd = (double)rv;
+            rr += rd * rd * im;
+            if (inv) rz += rd * (double)(ld_stream(inv + o) * rv) * im;
+        }
+    }
+    double v[2] = {rr, rz};
+    block_reduce_store<2>(v, partial, 2);
+}
+
 // ---------------------------------------------------------------------------
 // single-workgroup reductions of partials (fixed order)
 template <int NV>
@@ -683,6 +715,31 @@ hipError_t launch_pcg_update(int64_t n, const PcgState *st, T *r, const T *w, co
 }
 template hipError_t launch_pcg_update<double>(int64_t, const PcgState *, double *, const double *, const double *,
                                               const uint8_t *, double *, hipStream_t);
+
+int update_elem_blocks(int64_t E) { return (int)std::max<int64_t>(1, std::min<int64_t>((E + 3) / 4, 8192)); }
+
+template <typename T>
+hipError_t launch_pcg_update_elem(int N, int64_t E, const PcgState *st, T *r, const T *w, const T *inv,
+                                  const uint8_t *mult, double *partial, hipStream_t s)
+{
+    const int blocks = update_elem_blocks(E);
+    switch (N) {
+#define SEM_UPD_CASE(n)                                                                                           \
+    case n:                                                                                                       \
+        hipLaunchKernelGGL((pcg_update_elem_kernel<T, n>), dim3(blocks), dim3(256), 0, s, E, st, r, w, inv, mult, \
+                           partial);                                                                              \
+        break;
+        SEM_UPD_CASE(3) SEM_UPD_CASE(4) SEM_UPD_CASE(5) SEM_UPD_CASE(6) SEM_UPD_CASE(7) SEM_UPD_CASE(8)
+        SEM_UPD_CASE(9) SEM_UPD_CASE(10) SEM_UPD_CASE(11) SEM_UPD_CASE(12)
+#undef SEM_UPD_CASE
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+template hipError_t launch_pcg_update_elem<double>(int, int64_t, const PcgState *, double *, const double *,
+                                                   const double *, const uint8_t *, double *, hipStream_t);
+template hipError_t launch_pcg_update_elem<float>(int, int64_t, const PcgState *, float *, const float *,
+                                                  const float *, const uint8_t *, double *, hipStream_t);
 template hipError_t launch_pcg_update<float>(int64_t, const PcgState *, float *, const float *, const float *,
                                              const uint8_t *, double *, hipStream_t);
 

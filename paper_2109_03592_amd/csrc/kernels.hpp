@@ -81,6 +81,12 @@ hipError_t launch_reduce_init(const double *partial, int64_t pairs, PcgState *st
 template <typename T>
 hipError_t launch_pcg_update(int64_t n, const PcgState *st, T *r, const T *w, const T *inv, const uint8_t *mult,
                              double *partial, hipStream_t s);
+// the update element by element (N >= 3: at least one full wavefront per
+// element); update_elem_blocks(E) partial pairs
+int update_elem_blocks(int64_t E);
+template <typename T>
+hipError_t launch_pcg_update_elem(int N, int64_t E, const PcgState *st, T *r, const T *w, const T *inv,
+                                  const uint8_t *mult, double *partial, hipStream_t s);
 template <typename T>
 hipError_t launch_pcg_finish(int64_t n, const PcgState *st, T *x, const T *p, hipStream_t s);
 hipError_t launch_reduce_sigma(const double *partial, int64_t n, PcgState *st, hipStream_t s);
