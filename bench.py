@@ -493,7 +493,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-mesh solves")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
     ap.add_argument("--no-helm", action="store_true", help="skip the Helmholtz-form timing")
-    ap.add_argument("--coarse-smooth", default="",
+    ap.add_argument("--coarse-smooth", default="4:0.05",
                     help="the same preconditioner settings on a smooth right-hand side (sin forcing)")
     ap.add_argument("--coarse", default="4:0.05,s+4:0.05",
                     help="preconditioner settings: k:fraction (Jacobi + coarse), s (Schwarz), s+k:fraction "
