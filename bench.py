@@ -507,7 +507,7 @@ def main():
     ap.add_argument("--serve-drain", type=float, default=20.0)
     ap.add_argument("--sweep", action="store_true",
                     help="only run the Ax+gs sweep over orders and element counts (one JSON line)")
-    ap.add_argument("--sweep-orders", default="2,3,4,5,6,7,8,9,10,11,12")
+    ap.add_argument("--sweep-orders", default="2,3,4,5,6,7,8,9,10,11,12,13,14,15,16,17")
     ap.add_argument("--sweep-sizes", default="32,256,2048,16384")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain copy of known size (for scaling byte counters)")

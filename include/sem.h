@@ -50,7 +50,7 @@ enum { SEM_MAP_BOX = 0, SEM_MAP_PIPE_SQ2DISK = 1 };
 enum { SEM_FP64 = 0, SEM_FP32 = 1 };          /* element type of E-vectors       */
 enum { SEM_PREC_FP64 = 0, SEM_PREC_MIXED = 1 }; /* solve precision               */
 enum { SEM_WITH_FP32 = 1 };                   /* sem_mesh_desc.precision_flags  */
-enum { SEM_MAX_ORDER = 12 };                  /* largest N with built kernels   */
+enum { SEM_MAX_ORDER = 17 };                  /* largest N with built kernels   */
 
 typedef struct sem_mesh sem_mesh;
 

@@ -18,7 +18,7 @@ SEM_MAP_BOX, SEM_MAP_PIPE_SQ2DISK = 0, 1
 SEM_FP64, SEM_FP32 = 0, 1
 SEM_PREC_FP64, SEM_PREC_MIXED = 0, 1
 SEM_WITH_FP32 = 1
-SEM_MAX_ORDER = 12
+SEM_MAX_ORDER = 17
 
 
 class MeshDesc(C.Structure):

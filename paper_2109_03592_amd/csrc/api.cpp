@@ -1060,6 +1060,8 @@ sem_status sem_set_coarse(sem_mesh *m, int steps, double fraction, void *stream)
     return guarded([&]() -> sem_status {
         if (!m) fail(SEM_EINVAL, "sem_set_coarse: null mesh");
         if (steps < 0 || steps > 1000) fail(SEM_EINVAL, "sem_set_coarse: chebyshev_steps must be 0..1000");
+        if (steps > 0 && m->h.N > kMaxPrecondOrder)
+            fail(SEM_EUNSUPPORTED, "sem_set_coarse: the coarse term is built for N <= 12");
         if (steps > 0 && !(fraction > 0.0 && fraction < 1.0))
             fail(SEM_EINVAL, "sem_set_coarse: fraction must be in (0, 1)");
         hipStream_t s = (hipStream_t)stream;
@@ -1076,6 +1078,8 @@ sem_status sem_set_schwarz(sem_mesh *m, int enable, void *stream)
 {
     return guarded([&]() -> sem_status {
         if (!m) fail(SEM_EINVAL, "sem_set_schwarz: null mesh");
+        if (enable && m->h.N > kMaxPrecondOrder)
+            fail(SEM_EUNSUPPORTED, "sem_set_schwarz: the local solves are built for N <= 12");
         if (enable && m->h.N < 2)
             fail(SEM_EUNSUPPORTED, "sem_set_schwarz: N = 1 (the overlap spans the neighbours; singular local problems)");
         hipStream_t s = (hipStream_t)stream;

@@ -549,9 +549,19 @@ static hipError_t launch_ax_mode(int N, const AxParams<T> &a, hipStream_t s)
     case n: hipLaunchKernelGGL((ax_kernel<T, n, MODE, HELM>), dim3((unsigned)blocks), dim3(threads), lds, s, a); break;
         SEM_AX_CASE(1) SEM_AX_CASE(2) SEM_AX_CASE(3) SEM_AX_CASE(4) SEM_AX_CASE(5) SEM_AX_CASE(6)
         SEM_AX_CASE(7) SEM_AX_CASE(8) SEM_AX_CASE(9) SEM_AX_CASE(10) SEM_AX_CASE(11) SEM_AX_CASE(12)
-#undef SEM_AX_CASE
-    default: return hipErrorInvalidValue;
+    default:
+        // orders 13..17 (up to the LDS of one element per workgroup): the plain
+        // and CG modes only
+        if constexpr (MODE <= 2) {
+            switch (N) {
+                SEM_AX_CASE(13) SEM_AX_CASE(14) SEM_AX_CASE(15) SEM_AX_CASE(16) SEM_AX_CASE(17)
+            default: return hipErrorInvalidValue;
+            }
+        } else {
+            return hipErrorInvalidValue;
+        }
     }
+#undef SEM_AX_CASE
     return hipGetLastError();
 }
 
@@ -730,7 +740,8 @@ hipError_t launch_pcg_update_elem(int N, int64_t E, const PcgState *st, T *r, co
                            partial);                                                                              \
         break;
         SEM_UPD_CASE(3) SEM_UPD_CASE(4) SEM_UPD_CASE(5) SEM_UPD_CASE(6) SEM_UPD_CASE(7) SEM_UPD_CASE(8)
-        SEM_UPD_CASE(9) SEM_UPD_CASE(10) SEM_UPD_CASE(11) SEM_UPD_CASE(12)
+        SEM_UPD_CASE(9) SEM_UPD_CASE(10) SEM_UPD_CASE(11) SEM_UPD_CASE(12) SEM_UPD_CASE(13) SEM_UPD_CASE(14)
+        SEM_UPD_CASE(15) SEM_UPD_CASE(16) SEM_UPD_CASE(17)
 #undef SEM_UPD_CASE
     default: return hipErrorInvalidValue;
     }

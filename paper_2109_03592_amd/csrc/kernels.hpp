@@ -45,6 +45,7 @@ struct AxParams {
 };
 
 constexpr int kMaxNodeOrder = 7;   // the lane-per-node operator: (N+1)^3 <= 512
+constexpr int kMaxPrecondOrder = 12;  // the coarse term, the Schwarz local solves and modes 3-5
 int node_epw(int N);              // elements per workgroup of the lane-per-node operator
 
 int ax_block_threads(int N, int epw);

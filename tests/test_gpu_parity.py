@@ -51,10 +51,14 @@ def test_box_config_maps_and_geometry(semlib, oracle_mod):
     assert m.info.n_global == 29 ** 3 and m.info.n_unmasked_global == 27 ** 3
 
 
-@pytest.mark.parametrize("N", list(range(1, 13)))
+def _nel_for(N):
+    return (3, 2, 3) if N <= 9 else ((2, 2, 2) if N <= 12 else (2, 1, 2))
+
+
+@pytest.mark.parametrize("N", list(range(1, 18)))
 def test_ax_fp64_all_orders(semlib, oracle_mod, N):
     """Ragged element counts (not a multiple of the elements per workgroup)."""
-    nel = (3, 2, 3) if N <= 9 else (2, 2, 2)
+    nel = _nel_for(N)
     print(f"case: ax fp64 N={N} nel={nel}", flush=True)
     m, om = _box(semlib, oracle_mod, N, nel, seed=N)
     u = SI.random_local(om.nloc, 100 + N)
@@ -64,12 +68,12 @@ def test_ax_fp64_all_orders(semlib, oracle_mod, N):
     assert e2 <= 1e-12 and einf <= 1e-12, (e2, einf)
 
 
-@pytest.mark.parametrize("N", list(range(1, 13)))
+@pytest.mark.parametrize("N", list(range(1, 18)))
 def test_ax_fp32_all_orders(semlib, oracle_mod, N):
     """FP32 operator (geometric factors rounded to FP32) at every order against
     the oracle applied to the FP32-rounded input: the error is FP32 rounding
     of O(N) operations per output."""
-    nel = (3, 2, 3) if N <= 9 else (2, 2, 2)
+    nel = _nel_for(N)
     print(f"case: ax fp32 N={N} nel={nel}", flush=True)
     m, om = _box(semlib, oracle_mod, N, nel, seed=N, with_fp32=True)
     u32 = SI.random_local(om.nloc, 200 + N).astype(np.float32)
@@ -79,7 +83,8 @@ def test_ax_fp32_all_orders(semlib, oracle_mod, N):
     assert e2 <= 2e-6 and einf <= 2e-5, (e2, einf)
 
 
-@pytest.mark.parametrize("N,nel", [(8, (2, 2, 2)), (9, (2, 2, 2)), (10, (2, 1, 2)), (12, (1, 2, 1))])
+@pytest.mark.parametrize("N,nel", [(8, (2, 2, 2)), (9, (2, 2, 2)), (10, (2, 1, 2)), (12, (1, 2, 1)),
+                                   (14, (2, 1, 1)), (17, (1, 2, 1))])
 def test_pcg_high_order(semlib, oracle_mod, N, nel):
     """CG at the orders whose operator reads D rows from LDS."""
     print(f"case: pcg fp64 + mixed box N={N} nel={nel}", flush=True)

@@ -57,7 +57,7 @@ def test_inverted_element_rejected(L):
     assert L.load().sem_host_setup(C.byref(d), C.byref(info), *([None] * 8)) == L.SEM_EINVAL
 
 
-@pytest.mark.parametrize("N", list(range(1, 13)))
+@pytest.mark.parametrize("N", list(range(1, 18)))
 def test_gll_matches_oracle(L, oracle_mod, N):
     xi, w, D = (np.zeros(N + 1), np.zeros(N + 1), np.zeros((N + 1, N + 1)))
     L.check(L.load().sem_export_gll(N, xi.ctypes.data, w.ctypes.data, D.ctypes.data), "gll")

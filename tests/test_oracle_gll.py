@@ -46,7 +46,7 @@ def test_gll_against_numpy_roots(oracle_mod, N):
     np.testing.assert_allclose(w, w[::-1], rtol=1e-14)
 
 
-@pytest.mark.parametrize("N", range(1, 16))
+@pytest.mark.parametrize("N", range(1, 18))
 def test_gll_quadrature_exactness(oracle_mod, N):
     xi, w = oracle_mod.gll(N)
     for k in range(0, 2 * N):
@@ -57,7 +57,7 @@ def test_gll_quadrature_exactness(oracle_mod, N):
     assert abs(np.dot(w, xi ** k) - 2.0 / (k + 1)) > 1e-11
 
 
-@pytest.mark.parametrize("N", range(1, 16))
+@pytest.mark.parametrize("N", range(1, 18))
 def test_derivative_matrix(oracle_mod, N):
     xi, _ = oracle_mod.gll(N)
     D = oracle_mod.deriv(N, xi)
