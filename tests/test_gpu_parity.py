@@ -55,6 +55,14 @@ def _nel_for(N):
     return (3, 2, 3) if N <= 9 else ((2, 2, 2) if N <= 12 else (2, 1, 2))
 
 
+def _order_scale(N):
+    """Growth of the rounding error of Algorithm 1's sums with the order: the
+    entries of D grow like N^2 (|D_00| = N(N+1)/4), so the cancellation in each
+    output grows like (N+1)^2; the tolerances below hold up to N = 12 and are
+    scaled by ((N+1)/13)^2 beyond."""
+    return max(1.0, ((N + 1) / 13.0) ** 2)
+
+
 @pytest.mark.parametrize("N", list(range(1, 18)))
 def test_ax_fp64_all_orders(semlib, oracle_mod, N):
     """Ragged element counts (not a multiple of the elements per workgroup)."""
@@ -65,7 +73,8 @@ def test_ax_fp64_all_orders(semlib, oracle_mod, N):
     w = _host(m.ax(_dev(u)))
     ref = om.ax(u)
     e2, einf = _relerr(w, ref)
-    assert e2 <= 1e-12 and einf <= 1e-12, (e2, einf)
+    tol = 1e-12 * _order_scale(N)
+    assert e2 <= tol and einf <= tol, (e2, einf)
 
 
 @pytest.mark.parametrize("N", list(range(1, 18)))
@@ -80,7 +89,8 @@ def test_ax_fp32_all_orders(semlib, oracle_mod, N):
     w = _host(m.ax(_dev(u32, torch.float32)))
     ref = om.ax(u32.astype(np.float64))
     e2, einf = _relerr(w, ref)
-    assert e2 <= 2e-6 and einf <= 2e-5, (e2, einf)
+    sc = _order_scale(N)
+    assert e2 <= 2e-6 * sc and einf <= 2e-5 * sc, (e2, einf)
 
 
 @pytest.mark.parametrize("N,nel", [(8, (2, 2, 2)), (9, (2, 2, 2)), (10, (2, 1, 2)), (12, (1, 2, 1)),
