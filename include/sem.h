@@ -302,7 +302,7 @@ typedef struct {
  * Device memory: about 130 bytes per element and 380 per vertex, plus two
  * temporary FP64 E-vectors during the build.  Synchronises `stream`.
  * Errors: SEM_EINVAL (steps or fraction out of range, a zero coarse
- * operator), SEM_EUNSUPPORTED (8 E >= 2^31), SEM_ENOMEM, SEM_EHIP. */
+ * operator), SEM_EUNSUPPORTED (N > 12, or 8 E >= 2^31), SEM_ENOMEM, SEM_EHIP. */
 sem_status sem_set_coarse(sem_mesh *mesh, int chebyshev_steps, double fraction, void *stream);
 sem_status sem_get_coarse_info(const sem_mesh *mesh, sem_coarse_info *info);
 
@@ -338,7 +338,8 @@ sem_status sem_precond_apply(sem_mesh *mesh, const double *r, double *z, void *s
  * the device buffers (an extended E-vector of (N+3)^3 values per element and
  * one E-vector); 0: remove.  Synchronises `stream`.
  * Errors: SEM_EUNSUPPORTED (N = 1: the one-node overlap reaches the far faces
- * of the neighbours and an interior subdomain's local problem is singular),
+ * of the neighbours and an interior subdomain's local problem is singular;
+ * N > 12; E >= 2^31),
  * SEM_EINVAL (degenerate element), SEM_ENOMEM, SEM_EHIP. */
 sem_status sem_set_schwarz(sem_mesh *mesh, int enable, void *stream);
 /* enabled: 1 when set; n_factors: distinct 1-D factor sets (either may be NULL). */
