@@ -33,7 +33,6 @@ struct SchwarzSpace {
     int32_t *meta = nullptr;   // [n_table][2]: lo, count
     double *zext = nullptr;    // [E][n^3] local solutions on the extended elements
     double *zs = nullptr;      // [nL] assembled Schwarz output
-    int asm_blocks = 0;        // workgroups of the assembly (partial pairs)
     std::vector<void *> allocations;
 };
 

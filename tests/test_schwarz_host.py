@@ -36,7 +36,7 @@ def test_fdm_factors_diagonalise_oracle_1d(oracle_mod, N, ell):
 def test_fdm_argument_checks():
     import paper_2109_03592_amd as sem
     from paper_2109_03592_amd import _lib as L
-    for args in ((0, 1.0, 0, 0), (13, 1.0, 0, 0), (3, 0.0, 0, 0), (3, 1.0, 3, 0), (3, 1.0, 0, -1)):
+    for args in ((0, 1.0, 0, 0), (18, 1.0, 0, 0), (3, 0.0, 0, 0), (3, 1.0, 3, 0), (3, 1.0, 0, -1)):
         with pytest.raises(L.SemError) as e:
             sem.fdm_1d(*args)
         assert e.value.status == L.SEM_EINVAL
