@@ -256,3 +256,28 @@ def test_coarse_helmholtz_mixed_and_projection(semlib, oracle_mod):
     assert iters[-1] < iters[0], iters
     proj.close()
     m.close()
+
+
+DEGENERATE = [
+    ("box", 3, (1, 3, 2), (0, 0, 0), 61),   # one element across x
+    ("box", 4, (2, 1, 3), (1, 1, 0), 62),   # periodic x with two elements, periodic y with one
+    ("box", 2, (3, 2, 1), (0, 0, 1), 63),   # periodic z with one element: its two z-faces are one
+]
+
+
+@pytest.mark.parametrize("kind,N,nel,periodic,seed", DEGENERATE)
+def test_coarse_degenerate_lattices(semlib, oracle_mod, kind, N, nel, periodic, seed):
+    """Lattices where periodic images of a vertex coincide within one element
+    or an axis has a single element: the vertex space, A0 and M^-1 r against
+    the oracle."""
+    print(f"case: coarse degenerate {kind} N={N} nel={nel} periodic={periodic}", flush=True)
+    m, om = _meshes(semlib, oracle_mod, kind, N, nel, periodic, seed)
+    C = CoarseOracle(om, k=K, frac=FRAC)
+    m.set_coarse(K, FRAC)
+    info = m.coarse_info()
+    assert info["n_vertices"] == C.nvert and info["n_coarse"] == int(C.keep.sum())
+    assert abs(info["b"] - C.b) <= 1e-12 * C.b
+    r = _continuous(om, 700 + seed)
+    e2, einf = _relerr(_host(m.precond(_dev(r))), C.apply(r))
+    assert e2 <= 1e-12 and einf <= 1e-12, (e2, einf)
+    m.close()

@@ -191,3 +191,23 @@ def test_schwarz_errors(semlib):
     m.set_schwarz(False)
     assert not m.schwarz_info()["enabled"]
     m.close()
+
+
+@pytest.mark.parametrize("N,nel,periodic,seed", [(3, (1, 3, 2), (0, 0, 0), 71), (4, (2, 3, 2), (1, 0, 0), 72),
+                                                 (2, (3, 2, 2), (0, 0, 1), 73)])
+def test_schwarz_degenerate_lattices(semlib, oracle_mod, N, nel, periodic, seed):
+    """A single element across an axis (no neighbour on either side) and
+    periodic axes with two elements (both neighbours are the same element):
+    M^-1 r against the oracle."""
+    print(f"case: schwarz degenerate N={N} nel={nel} periodic={periodic}", flush=True)
+    m, om = _meshes(semlib, oracle_mod, "box", N, nel, periodic, seed)
+    S = SchwarzOracle(om)
+    m.set_schwarz(True)
+    r = _continuous(om, 800 + seed)
+    z = _host(m.precond(_dev(r)))
+    e2, einf = _relerr(z, S.apply(r))
+    assert e2 <= TOL and einf <= TOL, (e2, einf)
+    zg = np.zeros(om.nglob)
+    zg[om.numbering()] = z
+    assert np.array_equal(zg[om.numbering()], z)
+    m.close()
