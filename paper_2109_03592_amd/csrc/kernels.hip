@@ -49,11 +49,54 @@ __global__ __launch_bounds__(512) void ax_kernel(AxParams<T> a)
 
     double dot = 0.0;
     const int64_t ntiles = (a.E + a.epw - 1) / a.epw;
+    // coarse modes: the tile's corner values of z0 come from LDS, staged one
+    // tile ahead (their vertex indices two tiles ahead), so the dependent
+    // evert -> z0 loads never sit on a tile's critical path
+    constexpr bool kCoarse = MODE == 3 || MODE == 5;
+    constexpr int kZB = kCoarse ? (512 / P2) * 8 : 1;  // corner values of one tile
+    constexpr int kPer = (8 + P2 - 1) / P2;            // staged values per lane
+    __shared__ double szb[2 * kZB];
+    int32_t evn[kPer];
+    double zp[kPer];
+    int cur = 0;
+    const int nz = a.epw * 8;
+    auto vert_of = [&](int64_t t, int q) -> int32_t {
+        const int64_t e2 = t * a.epw + q / 8;
+        return (q < nz && t < ntiles && e2 < a.E) ? a.evert[e2 * 8 + (q & 7)] : -1;
+    };
+    if constexpr (kCoarse) {
+        const int64_t t0 = blockIdx.x;
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int q = tid + u * (int)blockDim.x;
+            const int32_t v0 = vert_of(t0, q);
+            if (q < nz) szb[q] = v0 >= 0 ? a.z0[v0] : 0.0;
+            evn[u] = vert_of(t0 + gridDim.x, q);
+        }
+        __syncthreads();
+    }
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t e = tile * a.epw + el;
         const bool active = inblk && e < a.E;
+        if constexpr (kCoarse) {
+#pragma unroll
+            for (int u = 0; u < kPer; ++u) {
+                const int q = tid + u * (int)blockDim.x;
+                zp[u] = evn[u] >= 0 ? a.z0[evn[u]] : 0.0;          // next tile
+                evn[u] = vert_of(tile + 2 * (int64_t)gridDim.x, q);  // the tile after
+            }
+        }
         ax_tile<T, N, MODE, 0, HELM>(R, D, su, e, active, inblk, i, j, a.G, a.in, a.out, a.invdiag, a.p, beta, a.x,
-                                     alpha, dot, a.h1, a.h2b, a.evert, a.z0, a.cq);
+                                     alpha, dot, a.h1, a.h2b, kCoarse ? szb + cur * kZB + slot * 8 : nullptr, a.cq);
+        if constexpr (kCoarse) {
+#pragma unroll
+            for (int u = 0; u < kPer; ++u) {
+                const int q = tid + u * (int)blockDim.x;
+                if (q < nz) szb[(cur ^ 1) * kZB + q] = zp[u];
+            }
+            __syncthreads();
+            cur ^= 1;
+        }
     }
     if (MODE != 0) {
         double v[1] = {dot};

@@ -260,8 +260,10 @@ struct ColumnIndex {
 // (the h2 term of Eq. 4); h2b holds h2*B per point.
 // MODE 3 (CG with the coarse term of Eq. 6): MODE 2 with the coarse
 // correction added to the preconditioned residual, p <- invdiag*r +
-// sum_c phi_c z0[evert[e][c]] + beta*p at live nodes (invdiag > 0), phi_c the
-// trilinear hat of corner c (c = cx + 2cy + 4cz) with 1-D weights cq[side][i].
+// sum_c phi_c zcl[c] + beta*p at live nodes (invdiag > 0), phi_c the
+// trilinear hat of corner c (c = cx + 2cy + 4cz) with 1-D weights cq[side][i]
+// and zcl the coarse solution at the element's corners (staged in LDS by the
+// caller).
 // MODE 4 (CG with a preconditioned residual given, e.g. by the Schwarz local
 // solves): p <- in + beta*p.  MODE 5: MODE 4 plus the coarse correction.
 template <typename T, int N, int MODE, int LAYOUT = 0, bool HELM = false>
@@ -269,8 +271,8 @@ __device__ inline void ax_tile(const LaneRows<T, N> &R, const T *__restrict__ D,
                                bool inblk, int i, int j, const T *__restrict__ G, const T *__restrict__ in,
                                T *__restrict__ out, const T *__restrict__ invdiag, T *__restrict__ p, T beta,
                                T *__restrict__ x, T alpha, double &dot, const T *__restrict__ h1 = nullptr,
-                               const T *__restrict__ h2b = nullptr, const int32_t *__restrict__ evert = nullptr,
-                               const double *__restrict__ z0 = nullptr, const double *__restrict__ cq = nullptr)
+                               const T *__restrict__ h2b = nullptr, const double *zcl = nullptr,
+                               const double *__restrict__ cq = nullptr)
 {
     constexpr int P = N + 1, P2 = P * P, P3 = P2 * P;
     T *sr = su + P3;
@@ -284,10 +286,9 @@ __device__ inline void ax_tile(const LaneRows<T, N> &R, const T *__restrict__ D,
         // coarse correction of this column (FP64): bilinear in (i,j) per t-side
         double cs0 = 0, cs1 = 0;
         if (kCoarse && active) {
-            const int32_t *ev = evert + e * 8;
             double zc[8];
 #pragma unroll
-            for (int c = 0; c < 8; ++c) zc[c] = z0[ev[c]];
+            for (int c = 0; c < 8; ++c) zc[c] = zcl[c];
             const double ai0 = cq[i], ai1 = cq[P + i], aj0 = cq[j], aj1 = cq[P + j];
             cs0 = aj0 * (ai0 * zc[0] + ai1 * zc[1]) + aj1 * (ai0 * zc[2] + ai1 * zc[3]);
             cs1 = aj0 * (ai0 * zc[4] + ai1 * zc[5]) + aj1 * (ai0 * zc[6] + ai1 * zc[7]);
