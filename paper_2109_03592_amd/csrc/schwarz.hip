@@ -182,7 +182,12 @@ __global__ __launch_bounds__(256) void fdm_kernel(int64_t E, Lattice L, const do
 }
 
 // z at every local node: the sum of the extended solutions that hold it,
-// 0 at Dirichlet nodes (invdiag 0).
+// 0 at Dirichlet nodes (invdiag 0).  Per direction a node of index idx is
+// held by its element (offset 0) and, when idx <= 1 or idx >= N-1, by the
+// neighbour on that side (N >= 3: at most two holders per direction, in
+// ascending offset).  The eight candidates are loaded together, invalid ones
+// from a clamped address, and summed in ascending order with selects; N = 2
+// (a node of index 1 is held by both neighbours) takes the general loop.
 template <int N>
 __global__ __launch_bounds__(256) void assemble_kernel(int64_t E, Lattice L, const double *__restrict__ zext,
                                                        const double *__restrict__ inv, double *__restrict__ z,
@@ -198,41 +203,80 @@ __global__ __launch_bounds__(256) void assemble_kernel(int64_t E, Lattice L, con
         const int rem = (int)(q - (int64_t)ei * P3);
         const int idx[3] = {rem % P, (rem / P) % P, rem / P2};
         const int pos[3] = {ei % L.nel[0], (ei / L.nel[0]) % L.nel[1], ei / (L.nel[0] * L.nel[1])};
-        // per direction and offset delta in {-1, 0, 1} (ascending): whether
-        // element pos+delta holds the node in its kept range, and the node's
-        // position there (the extended index idx - delta N, less that
-        // element's first kept index)
-        bool ok[3][3];
-        int el[3][3], ps[3][3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-#pragma unroll
-            for (int t = 0; t < 3; ++t) {
-                const int delta = t - 1;
-                const int ext = idx[d] - delta * N;
-                int p2 = pos[d] + delta;
-                bool v = ext >= -1 && ext <= N + 1;
-                if (p2 < 0) { v = v && L.periodic[d]; p2 += L.nel[d]; }
-                if (p2 >= L.nel[d]) { v = v && L.periodic[d]; p2 -= L.nel[d]; }
-                const bool left = p2 > 0 || L.periodic[d], right = p2 < L.nel[d] - 1 || L.periodic[d];
-                const int lo2 = left ? -1 : ((L.dirichlet >> (2 * d)) & 1);
-                const int hi2 = right ? N + 1 : (((L.dirichlet >> (2 * d + 1)) & 1) ? N - 1 : N);
-                ok[d][t] = v && ext >= lo2 && ext <= hi2;
-                el[d][t] = p2;
-                ps[d][t] = ext - lo2;
-            }
-        }
         double s = 0.0;
+        if constexpr (N >= 3) {
+            // per direction: candidate t = 0, 1 (ascending offset): validity,
+            // lattice position and position in that element's kept range
+            bool ok[3][2];
+            int el[3][2], ps[3][2];
 #pragma unroll
-        for (int tz = 0; tz < 3; ++tz)
+            for (int d = 0; d < 3; ++d) {
+                const int lo_side = idx[d] <= 1, hi_side = idx[d] >= N - 1;
 #pragma unroll
-            for (int ty = 0; ty < 3; ++ty)
-#pragma unroll
-                for (int tx = 0; tx < 3; ++tx) {
-                    if (!(ok[0][tx] && ok[1][ty] && ok[2][tz])) continue;
-                    const int e2 = el[0][tx] + L.nel[0] * (el[1][ty] + L.nel[1] * el[2][tz]);
-                    s += zext[(int64_t)e2 * n3 + ps[0][tx] + n * ps[1][ty] + n2 * ps[2][tz]];
+                for (int t = 0; t < 2; ++t) {
+                    // offsets: (-1, 0) near the low face, (0, +1) near the high face, (0, -) inside
+                    const int delta = lo_side ? t - 1 : (hi_side ? t : 0);
+                    bool v = lo_side || hi_side || t == 0;
+                    const int ext = idx[d] - delta * N;
+                    int p2 = pos[d] + delta;
+                    if (p2 < 0) { v = v && L.periodic[d]; p2 += L.nel[d]; }
+                    if (p2 >= L.nel[d]) { v = v && L.periodic[d]; p2 -= L.nel[d]; }
+                    const bool left = p2 > 0 || L.periodic[d], right = p2 < L.nel[d] - 1 || L.periodic[d];
+                    const int lo2 = left ? -1 : ((L.dirichlet >> (2 * d)) & 1);
+                    const int hi2 = right ? N + 1 : (((L.dirichlet >> (2 * d + 1)) & 1) ? N - 1 : N);
+                    ok[d][t] = v && ext >= lo2 && ext <= hi2;
+                    el[d][t] = p2;
+                    ps[d][t] = ext - lo2;
                 }
+            }
+            double val[8];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const int tx = c & 1, ty = (c >> 1) & 1, tz = c >> 2;
+                const bool good = ok[0][tx] && ok[1][ty] && ok[2][tz];
+                const int e2 = el[0][tx] + L.nel[0] * (el[1][ty] + L.nel[1] * el[2][tz]);
+                const int64_t a = good ? (int64_t)e2 * n3 + ps[0][tx] + n * ps[1][ty] + n2 * ps[2][tz]
+                                       : (int64_t)ei * n3;
+                val[c] = zext[a];
+            }
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const int tx = c & 1, ty = (c >> 1) & 1, tz = c >> 2;
+                const bool good = ok[0][tx] && ok[1][ty] && ok[2][tz];
+                s = good ? s + val[c] : s;
+            }
+        } else {
+            bool ok[3][3];
+            int el[3][3], ps[3][3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+#pragma unroll
+                for (int t = 0; t < 3; ++t) {
+                    const int delta = t - 1;
+                    const int ext = idx[d] - delta * N;
+                    int p2 = pos[d] + delta;
+                    bool v = ext >= -1 && ext <= N + 1;
+                    if (p2 < 0) { v = v && L.periodic[d]; p2 += L.nel[d]; }
+                    if (p2 >= L.nel[d]) { v = v && L.periodic[d]; p2 -= L.nel[d]; }
+                    const bool left = p2 > 0 || L.periodic[d], right = p2 < L.nel[d] - 1 || L.periodic[d];
+                    const int lo2 = left ? -1 : ((L.dirichlet >> (2 * d)) & 1);
+                    const int hi2 = right ? N + 1 : (((L.dirichlet >> (2 * d + 1)) & 1) ? N - 1 : N);
+                    ok[d][t] = v && ext >= lo2 && ext <= hi2;
+                    el[d][t] = p2;
+                    ps[d][t] = ext - lo2;
+                }
+            }
+#pragma unroll
+            for (int tz = 0; tz < 3; ++tz)
+#pragma unroll
+                for (int ty = 0; ty < 3; ++ty)
+#pragma unroll
+                    for (int tx = 0; tx < 3; ++tx) {
+                        if (!(ok[0][tx] && ok[1][ty] && ok[2][tz])) continue;
+                        const int e2 = el[0][tx] + L.nel[0] * (el[1][ty] + L.nel[1] * el[2][tz]);
+                        s += zext[(int64_t)e2 * n3 + ps[0][tx] + n * ps[1][ty] + n2 * ps[2][tz]];
+                    }
+        }
         z[q] = ld_stream(inv + q) > 0.0 ? s : 0.0;
     }
 }
