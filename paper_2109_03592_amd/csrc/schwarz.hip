@@ -70,6 +70,10 @@ __device__ inline void fdm_line(const double *__restrict__ Sd, const double *__r
     }
 }
 
+// workgroup of the local solves: the (N+3)^2 lines rounded up to wavefronts
+template <int N>
+constexpr int kFdmThreads = ((N + 3) * (N + 3) + 63) / 64 * 64;
+
 template <int N>
 __global__ __launch_bounds__(256) void fdm_kernel(int64_t E, Lattice L, const double *__restrict__ r,
                                                   const int32_t *__restrict__ tidx,
@@ -101,31 +105,38 @@ __global__ __launch_bounds__(256) void fdm_kernel(int64_t E, Lattice L, const do
         }
         const double *Lm[3] = {S[0] + n2, S[1] + n2, S[2] + n2};
         // R_k r: extended node (a, b, c) from the element or a neighbour (r is
-        // continuous: any copy of a node holds its value); 0 beyond the kept range
-        for (int q = tid; q < n3; q += blockDim.x) {
-            const int a[3] = {q % n, (q / n) % n, q / n2};
-            double v = 0.0;
-            if (a[0] < cnt[0] && a[1] < cnt[1] && a[2] < cnt[2]) {
-                int ep[3], loc[3];
-                bool ok = true;
+        // continuous: any copy of a node holds its value); 0 beyond the kept
+        // range.  All of a lane's loads are issued together, out-of-range ones
+        // from the element's first node.
+        constexpr int kIt = (n3 + kFdmThreads<N> - 1) / kFdmThreads<N>;
+        double gv[kIt];
+        bool gk[kIt];
 #pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    const int x = lo[d] + a[d];
-                    int p2 = pos[d], lc = x;
-                    if (x == -1) { p2 -= 1; lc = N - 1; }
-                    else if (x == N + 1) { p2 += 1; lc = 1; }
-                    if (p2 < 0) p2 += L.nel[d];
-                    if (p2 >= L.nel[d]) p2 -= L.nel[d];
-                    ok = ok && p2 >= 0 && p2 < L.nel[d];
-                    ep[d] = p2;
-                    loc[d] = lc;
-                }
-                if (ok) {
-                    const int64_t e2 = ep[0] + (int64_t)L.nel[0] * (ep[1] + (int64_t)L.nel[1] * ep[2]);
-                    v = r[e2 * P3 + loc[0] + P * loc[1] + P2 * loc[2]];
-                }
+        for (int it = 0; it < kIt; ++it) {
+            const int q = tid + it * kFdmThreads<N>;
+            const int a[3] = {q % n, (q / n) % n, q / n2};
+            bool ok = q < n3 && a[0] < cnt[0] && a[1] < cnt[1] && a[2] < cnt[2];
+            int ep[3], loc[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const int x = lo[d] + a[d];
+                int p2 = pos[d], lc = x;
+                if (x == -1) { p2 -= 1; lc = N - 1; }
+                else if (x == N + 1) { p2 += 1; lc = 1; }
+                if (p2 < 0) p2 += L.nel[d];
+                if (p2 >= L.nel[d]) p2 -= L.nel[d];
+                ok = ok && p2 >= 0 && p2 < L.nel[d] && lc >= 0 && lc <= N;
+                ep[d] = p2;
+                loc[d] = lc;
             }
-            U[q] = v;
+            const int64_t e2 = ep[0] + (int64_t)L.nel[0] * (ep[1] + (int64_t)L.nel[1] * ep[2]);
+            gv[it] = r[ok ? e2 * P3 + loc[0] + P * loc[1] + P2 * loc[2] : e * P3];
+            gk[it] = ok;
+        }
+#pragma unroll
+        for (int it = 0; it < kIt; ++it) {
+            const int q = tid + it * kFdmThreads<N>;
+            if (q < n3) U[q] = gk[it] ? gv[it] : 0.0;
         }
         __syncthreads();
         // 1: along r, S_r^T (line s = l0, t = l1): U -> V
@@ -172,7 +183,7 @@ __global__ __launch_bounds__(256) void fdm_kernel(int64_t E, Lattice L, const do
             for (int i = 0; i < n; ++i) V[l1 * n2 + l0 * n + i] = acc[i];
         }
         __syncthreads();
-        for (int q = tid; q < n3; q += blockDim.x) st_stream(V[q], zext + e * n3 + q);
+        for (int q = tid; q < n3; q += kFdmThreads<N>) st_stream(V[q], zext + e * n3 + q);
         __syncthreads();
     }
     if (partial) {
@@ -484,19 +495,20 @@ SchwarzSpace *schwarz_build(sem_mesh *m, hipStream_t s)
 }
 
 static int fdm_blocks(int64_t E) { return (int)std::max<int64_t>(1, std::min<int64_t>(E, kMaxSchwarzPairs)); }
-static int fdm_threads(int N) { return ((N + 3) * (N + 3) + 63) / 64 * 64; }
+
 
 int schwarz_apply(sem_mesh *m, const double *r, double *z, double *pairs, const PcgState *st, hipStream_t s)
 {
     SchwarzSpace *Z = m->schwarz;
     const Lattice L = lattice_of(m, Z->dirichlet);
     const int64_t E = m->h.E, nL = m->h.nL;
-    const int fb = fdm_blocks(E), ft = fdm_threads(m->h.N);
+    const int fb = fdm_blocks(E);
     const int ab = vec_blocks(nL);
     switch (m->h.N) {
 #define SEM_SCHWARZ_CASE(n)                                                                                       \
     case n:                                                                                                       \
-        hipLaunchKernelGGL(fdm_kernel<n>, dim3(fb), dim3(ft), 0, s, E, L, r, Z->tidx, Z->table, Z->meta, Z->zext, \
+        hipLaunchKernelGGL(fdm_kernel<n>, dim3(fb), dim3(kFdmThreads<n>), 0, s, E, L, r, Z->tidx, Z->table,         \
+                           Z->meta, Z->zext,                                                                      \
                            pairs, st);                                                                            \
         hipLaunchKernelGGL(assemble_kernel<n>, dim3(ab), dim3(256), 0, s, E, L, Z->zext, m->inv64, z, st);        \
         break;
