@@ -225,8 +225,10 @@ static int column_epw(const sem_mesh *m) { return sizeof(T) == 8 ? m->ax_epw : m
 template <typename T>
 static int cg_epw(const sem_mesh *m) { return cg_mode<T>(m) > 2 ? column_epw<T>(m) : op_epw<T>(m); }
 
+// launches the operator; returns its workgroup count (the number of dot
+// partials of modes 1-5)
 template <typename T>
-static void enqueue_ax(sem_mesh *m, int mode, const T *in, T *out, hipStream_t s)
+static int64_t enqueue_ax(sem_mesh *m, int mode, const T *in, T *out, hipStream_t s)
 {
     AxParams<T> a{};
     a.E = m->h.E;
@@ -250,7 +252,9 @@ static void enqueue_ax(sem_mesh *m, int mode, const T *in, T *out, hipStream_t s
         a.z0 = m->coarse->z0;
         a.cq = m->coarse->qw;
     }
-    SEM_HIP(launch_ax<T>(m->h.N, mode, a, s));
+    int64_t grid = 0;
+    SEM_HIP(launch_ax<T>(m->h.N, mode, a, s, &grid));
+    return grid;
 }
 
 template <typename T>
@@ -303,7 +307,6 @@ static void enqueue_iterations(sem_mesh *m, int k, hipStream_t s, Profiler *prof
     PcgState *st = Prec<T>::st(m);
     const bool coarse = coarse_cg<T>(m), schwarz = schwarz_cg<T>(m);
     const int mode = cg_mode<T>(m);
-    const int64_t axb = ax_grid(m->h.E, cg_epw<T>(m), m->ax_grid_cap);
     const int64_t nL = m->h.nL;
     const int64_t ub = update_blocks(nL);
     // the Jacobi part of <r,z> comes from the update unless Schwarz supplies z
@@ -312,7 +315,7 @@ static void enqueue_iterations(sem_mesh *m, int k, hipStream_t s, Profiler *prof
     if constexpr (sizeof(T) == 8) zs = schwarz ? m->schwarz->zs : nullptr;
     for (int it = 0; it < k; ++it) {
         if (prof) prof->mark(s);
-        enqueue_ax<T>(m, mode, schwarz ? zs : Prec<T>::r(m), Prec<T>::w(m), s);
+        const int64_t axb = enqueue_ax<T>(m, mode, schwarz ? zs : Prec<T>::r(m), Prec<T>::w(m), s);
         if (prof) prof->mark(s);
         enqueue_gs<T>(m, Prec<T>::w(m), st, s);
         if (prof) prof->mark(s);
@@ -1003,12 +1006,9 @@ sem_status sem_ax(sem_mesh *m, int dtype, const void *u, void *w, double *opt_do
         check_dtype(m, dtype);
         hipStream_t s = (hipStream_t)stream;
         const int mode = opt_dot ? 1 : 0;
-        if (dtype == SEM_FP64) enqueue_ax<double>(m, mode, (const double *)u, (double *)w, s);
-        else enqueue_ax<float>(m, mode, (const float *)u, (float *)w, s);
-        if (opt_dot)
-            SEM_HIP(launch_reduce_scalar(
-                m->partials, ax_grid(m->h.E, dtype == SEM_FP64 ? op_epw<double>(m) : op_epw<float>(m), m->ax_grid_cap),
-                opt_dot, s));
+        const int64_t grid = dtype == SEM_FP64 ? enqueue_ax<double>(m, mode, (const double *)u, (double *)w, s)
+                                               : enqueue_ax<float>(m, mode, (const float *)u, (float *)w, s);
+        if (opt_dot) SEM_HIP(launch_reduce_scalar(m->partials, grid, opt_dot, s));
         return SEM_OK;
     });
 }

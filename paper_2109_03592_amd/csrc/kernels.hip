@@ -14,6 +14,10 @@
 //  * PCG update / reductions: fused x, r update with the Jacobi-weighted
 //    <r,z> and <r,r>, per-workgroup partials reduced in a fixed order by a
 //    single-workgroup kernel that also forms alpha and beta on the device.
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "kernels.hpp"
 #include "operator.hpp"
 
@@ -521,10 +525,31 @@ size_t ax_lds_bytes(int N, int epw, size_t elem)
 }
 
 
-int64_t ax_grid(int64_t E, int epw, int cap)
+// Workgroups of a persistent operator launch: at most cap (the partials
+// buffer holds that many) and at most one per tile; when fewer than cap
+// workgroups of this kernel fit on the device at once, the largest multiple
+// of that resident count, so that no partial last round leaves SIMDs idle.
+static int64_t resident_grid(const void *fn, int threads, size_t lds, int64_t tiles, int cap)
 {
-    const int64_t tiles = (E + epw - 1) / epw;
-    return tiles < cap ? tiles : cap;
+    static std::mutex mu;
+    static std::map<std::tuple<const void *, int, size_t, int>, int64_t> resident;
+    int dev = 0;
+    int64_t res = 0;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        std::lock_guard<std::mutex> lock(mu);
+        const auto key = std::make_tuple(fn, threads, lds, dev);
+        auto it = resident.find(key);
+        if (it == resident.end()) {
+            int per_cu = 0, cus = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) != hipSuccess) per_cu = 0;
+            if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 0;
+            it = resident.emplace(key, (int64_t)per_cu * cus).first;
+        }
+        res = it->second;
+    }
+    int64_t c = cap;
+    if (res > 0 && res < c) c = (c / res) * res;
+    return tiles < c ? tiles : c;
 }
 
 // dynamic LDS a workgroup may request on the current device
@@ -554,42 +579,53 @@ int node_epw(int N)
 }
 
 template <typename T, int MODE, bool HELM>
-static hipError_t launch_ax_node(int N, const AxParams<T> &a, hipStream_t s)
+static hipError_t launch_ax_node(int N, const AxParams<T> &a, hipStream_t s, int64_t *grid)
 {
     const int P3 = (N + 1) * (N + 1) * (N + 1);
     const int threads = (a.epw * P3 + 63) / 64 * 64;
     const size_t lds = (size_t)a.epw * 4 * P3 * sizeof(T);
-    const int64_t blocks = ax_grid(a.E, a.epw, a.grid_cap);
-    if (N > kMaxNodeOrder || threads > 512 || blocks < 1 || blocks > INT32_MAX) return hipErrorInvalidConfiguration;
+    const int64_t tiles = (a.E + a.epw - 1) / a.epw;
+    int64_t blocks = 0;
+    if (N > kMaxNodeOrder || threads > 512 || tiles < 1 || a.grid_cap < 1) return hipErrorInvalidConfiguration;
     switch (N) {
-#define SEM_NODE_CASE(n) \
-    case n: hipLaunchKernelGGL((ax_node_kernel<T, n, MODE, HELM>), dim3((unsigned)blocks), dim3(threads), lds, s, a); break;
+#define SEM_NODE_CASE(n)                                                                                          \
+    case n:                                                                                                       \
+        blocks = resident_grid(reinterpret_cast<const void *>(&ax_node_kernel<T, n, MODE, HELM>), threads, lds,   \
+                               tiles, a.grid_cap);                                                                \
+        hipLaunchKernelGGL((ax_node_kernel<T, n, MODE, HELM>), dim3((unsigned)blocks), dim3(threads), lds, s, a); \
+        break;
         SEM_NODE_CASE(1) SEM_NODE_CASE(2) SEM_NODE_CASE(3) SEM_NODE_CASE(4) SEM_NODE_CASE(5) SEM_NODE_CASE(6)
         SEM_NODE_CASE(7)
 #undef SEM_NODE_CASE
     default: return hipErrorInvalidValue;
     }
+    if (grid) *grid = blocks;
     return hipGetLastError();
 }
 
 template <typename T, int MODE, bool HELM>
-static hipError_t launch_ax_mode(int N, const AxParams<T> &a, hipStream_t s)
+static hipError_t launch_ax_mode(int N, const AxParams<T> &a, hipStream_t s, int64_t *grid)
 {
     if constexpr (MODE >= 3) {
         // the coarse correction and a given residual run in the column kernel only
         if (a.kind != 0) return hipErrorInvalidValue;
         if ((MODE == 3 || MODE == 5) && (!a.evert || !a.z0 || !a.cq)) return hipErrorInvalidValue;
     } else {
-        if (a.kind == 1) return launch_ax_node<T, MODE, HELM>(N, a, s);
+        if (a.kind == 1) return launch_ax_node<T, MODE, HELM>(N, a, s, grid);
     }
     static const size_t lds_cap = max_dynamic_lds();
     const int threads = ax_block_threads(N, a.epw);
     const size_t lds = ax_lds_bytes(N, a.epw, sizeof(T));
-    const int64_t blocks = ax_grid(a.E, a.epw, a.grid_cap);
-    if (threads > 512 || lds > lds_cap || blocks < 1 || blocks > INT32_MAX) return hipErrorInvalidConfiguration;
+    const int64_t tiles = (a.E + a.epw - 1) / a.epw;
+    int64_t blocks = 0;
+    if (threads > 512 || lds > lds_cap || tiles < 1 || a.grid_cap < 1) return hipErrorInvalidConfiguration;
     switch (N) {
-#define SEM_AX_CASE(n) \
-    case n: hipLaunchKernelGGL((ax_kernel<T, n, MODE, HELM>), dim3((unsigned)blocks), dim3(threads), lds, s, a); break;
+#define SEM_AX_CASE(n)                                                                                       \
+    case n:                                                                                                  \
+        blocks = resident_grid(reinterpret_cast<const void *>(&ax_kernel<T, n, MODE, HELM>), threads, lds,   \
+                               tiles, a.grid_cap);                                                           \
+        hipLaunchKernelGGL((ax_kernel<T, n, MODE, HELM>), dim3((unsigned)blocks), dim3(threads), lds, s, a); \
+        break;
         SEM_AX_CASE(1) SEM_AX_CASE(2) SEM_AX_CASE(3) SEM_AX_CASE(4) SEM_AX_CASE(5) SEM_AX_CASE(6)
         SEM_AX_CASE(7) SEM_AX_CASE(8) SEM_AX_CASE(9) SEM_AX_CASE(10) SEM_AX_CASE(11) SEM_AX_CASE(12)
     default:
@@ -605,35 +641,37 @@ static hipError_t launch_ax_mode(int N, const AxParams<T> &a, hipStream_t s)
         }
     }
 #undef SEM_AX_CASE
+    if (grid) *grid = blocks;
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_ax(int N, int mode, const AxParams<T> &a, hipStream_t s)
+hipError_t launch_ax(int N, int mode, const AxParams<T> &a, hipStream_t s, int64_t *grid)
 {
     if (mode == 3) {
-        if (a.h1) return launch_ax_mode<T, 3, true>(N, a, s);
-        return launch_ax_mode<T, 3, false>(N, a, s);
+        if (a.h1) return launch_ax_mode<T, 3, true>(N, a, s, grid);
+        return launch_ax_mode<T, 3, false>(N, a, s, grid);
     }
     if (mode == 4 || mode == 5) {
         // the preconditioned residual is given (FP64 solves)
         if constexpr (sizeof(T) == 8) {
-            if (mode == 4) return a.h1 ? launch_ax_mode<T, 4, true>(N, a, s) : launch_ax_mode<T, 4, false>(N, a, s);
-            return a.h1 ? launch_ax_mode<T, 5, true>(N, a, s) : launch_ax_mode<T, 5, false>(N, a, s);
+            if (mode == 4)
+                return a.h1 ? launch_ax_mode<T, 4, true>(N, a, s, grid) : launch_ax_mode<T, 4, false>(N, a, s, grid);
+            return a.h1 ? launch_ax_mode<T, 5, true>(N, a, s, grid) : launch_ax_mode<T, 5, false>(N, a, s, grid);
         }
         return hipErrorInvalidValue;
     }
     if (a.h1) {
-        if (mode == 0) return launch_ax_mode<T, 0, true>(N, a, s);
-        if (mode == 1) return launch_ax_mode<T, 1, true>(N, a, s);
-        return launch_ax_mode<T, 2, true>(N, a, s);
+        if (mode == 0) return launch_ax_mode<T, 0, true>(N, a, s, grid);
+        if (mode == 1) return launch_ax_mode<T, 1, true>(N, a, s, grid);
+        return launch_ax_mode<T, 2, true>(N, a, s, grid);
     }
-    if (mode == 0) return launch_ax_mode<T, 0, false>(N, a, s);
-    if (mode == 1) return launch_ax_mode<T, 1, false>(N, a, s);
-    return launch_ax_mode<T, 2, false>(N, a, s);
+    if (mode == 0) return launch_ax_mode<T, 0, false>(N, a, s, grid);
+    if (mode == 1) return launch_ax_mode<T, 1, false>(N, a, s, grid);
+    return launch_ax_mode<T, 2, false>(N, a, s, grid);
 }
-template hipError_t launch_ax<double>(int, int, const AxParams<double> &, hipStream_t);
-template hipError_t launch_ax<float>(int, int, const AxParams<float> &, hipStream_t);
+template hipError_t launch_ax<double>(int, int, const AxParams<double> &, hipStream_t, int64_t *);
+template hipError_t launch_ax<float>(int, int, const AxParams<float> &, hipStream_t, int64_t *);
 
 template <typename T>
 hipError_t launch_gs(const GsPlan &plan, const int32_t *off, const int32_t *idx, T *v, bool zero_only,

@@ -50,13 +50,14 @@ int node_epw(int N);              // elements per workgroup of the lane-per-node
 
 int ax_block_threads(int N, int epw);
 size_t ax_lds_bytes(int N, int epw, size_t elem);
-int64_t ax_grid(int64_t E, int epw, int cap);
 hipError_t upload_dtables(const double *d64, const float *d32, hipStream_t s);
 int vec_blocks(int64_t n);
 int update_blocks(int64_t n);  // workgroups of the PCG update (one partial pair each)
 
+// grid (may be null) receives the workgroups launched: the count of per-
+// workgroup dot partials (modes 1-5)
 template <typename T>
-hipError_t launch_ax(int N, int mode, const AxParams<T> &a, hipStream_t s);
+hipError_t launch_ax(int N, int mode, const AxParams<T> &a, hipStream_t s, int64_t *grid = nullptr);
 template <typename T>
 hipError_t launch_gs(const GsPlan &plan, const int32_t *off, const int32_t *idx, T *v, bool zero_only,
                      const PcgState *st, hipStream_t s);
