@@ -526,11 +526,16 @@ size_t ax_lds_bytes(int N, int epw, size_t elem)
 
 
 // Workgroups of a persistent operator launch: at most cap (the partials
-// buffer holds that many) and at most one per tile; when fewer than cap
-// workgroups of this kernel fit on the device at once, the largest multiple
-// of that resident count, so that no partial last round leaves SIMDs idle.
-static int64_t resident_grid(const void *fn, int threads, size_t lds, int64_t tiles, int cap)
+// buffer holds that many) and at most one per tile.  With `whole_rounds`,
+// when fewer than cap workgroups of this kernel fit on the device at once,
+// the largest multiple of that resident count, so that no partial last round
+// leaves SIMDs idle.  Measured on the 48x48x96 pipe this pays for the
+// coarse-corrected FP32 operator (three waves per SIMD, one-wave
+// workgroups: 1.60 -> 1.19 ms) but not for the plain ones (FP32 at N = 9
+// lost 12%), so only the coarse modes ask for it.
+static int64_t resident_grid(const void *fn, int threads, size_t lds, int64_t tiles, int cap, bool whole_rounds)
 {
+    if (!whole_rounds) return tiles < cap ? tiles : cap;
     static std::mutex mu;
     static std::map<std::tuple<const void *, int, size_t, int>, int64_t> resident;
     int dev = 0;
@@ -591,7 +596,7 @@ static hipError_t launch_ax_node(int N, const AxParams<T> &a, hipStream_t s, int
 #define SEM_NODE_CASE(n)                                                                                          \
     case n:                                                                                                       \
         blocks = resident_grid(reinterpret_cast<const void *>(&ax_node_kernel<T, n, MODE, HELM>), threads, lds,   \
-                               tiles, a.grid_cap);                                                                \
+                               tiles, a.grid_cap, false);                                                         \
         hipLaunchKernelGGL((ax_node_kernel<T, n, MODE, HELM>), dim3((unsigned)blocks), dim3(threads), lds, s, a); \
         break;
         SEM_NODE_CASE(1) SEM_NODE_CASE(2) SEM_NODE_CASE(3) SEM_NODE_CASE(4) SEM_NODE_CASE(5) SEM_NODE_CASE(6)
@@ -623,7 +628,7 @@ static hipError_t launch_ax_mode(int N, const AxParams<T> &a, hipStream_t s, int
 #define SEM_AX_CASE(n)                                                                                       \
     case n:                                                                                                  \
         blocks = resident_grid(reinterpret_cast<const void *>(&ax_kernel<T, n, MODE, HELM>), threads, lds,   \
-                               tiles, a.grid_cap);                                                           \
+                               tiles, a.grid_cap, MODE == 3 || MODE == 5);                                   \
         hipLaunchKernelGGL((ax_kernel<T, n, MODE, HELM>), dim3((unsigned)blocks), dim3(threads), lds, s, a); \
         break;
         SEM_AX_CASE(1) SEM_AX_CASE(2) SEM_AX_CASE(3) SEM_AX_CASE(4) SEM_AX_CASE(5) SEM_AX_CASE(6)
