@@ -177,17 +177,45 @@ __global__ __launch_bounds__(256) void update_restrict_kernel(int64_t E, const P
     for (int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); e < E; e += (int64_t)gridDim.x * 4) {
         double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         const int64_t base = e * P3;
+        if constexpr (sizeof(T) == 4 && P3 % 2 == 0) {
+            // FP32, N odd: two adjacent nodes of one element row per lane
+            // (paired 8-byte loads), in the same per-node arithmetic
+            const float2 *r2 = reinterpret_cast<const float2 *>(r + base);
+            const float2 *w2 = reinterpret_cast<const float2 *>(w + base);
+            const float2 *i2 = reinterpret_cast<const float2 *>(inv + base);
+            const uint16_t *m2 = reinterpret_cast<const uint16_t *>(mult + base);
 #pragma unroll
-        for (int q = lane; q < P3; q += 64) {
-            const int64_t o = base + q;
-            const T rv = ld_stream(r + o) - alpha * ld_stream(w + o);
-            st_stream(rv, r + o);
-            const T iv = ld_stream(inv + o);
-            const double im = 1.0 / (double)ld_stream(mult + o);
-            const double rd = (double)rv;
-            rr += rd * rd * im;
-            if (with_rz) rz += rd * (double)(iv * rv) * im;
-            hat_add<N>(sqw, q, iv > T(0) ? rd * im : 0.0, s);
+            for (int h = lane; h < P3 / 2; h += 64) {
+                float2 rv = ld_stream(r2 + h);
+                const float2 wv = ld_stream(w2 + h), iv = ld_stream(i2 + h);
+                const uint16_t mm = ld_stream(m2 + h);
+                rv.x = rv.x - (float)alpha * wv.x;
+                rv.y = rv.y - (float)alpha * wv.y;
+                st_stream(rv, reinterpret_cast<float2 *>(r + base) + h);
+                const double ima = 1.0 / (double)(mm & 0xff), imb = 1.0 / (double)(mm >> 8);
+                const double ra = (double)rv.x, rb = (double)rv.y;
+                rr += ra * ra * ima;
+                rr += rb * rb * imb;
+                if (with_rz) {
+                    rz += ra * (double)(iv.x * rv.x) * ima;
+                    rz += rb * (double)(iv.y * rv.y) * imb;
+                }
+                hat_add<N>(sqw, 2 * h, iv.x > 0.0f ? ra * ima : 0.0, s);
+                hat_add<N>(sqw, 2 * h + 1, iv.y > 0.0f ? rb * imb : 0.0, s);
+            }
+        } else {
+#pragma unroll
+            for (int q = lane; q < P3; q += 64) {
+                const int64_t o = base + q;
+                const T rv = ld_stream(r + o) - alpha * ld_stream(w + o);
+                st_stream(rv, r + o);
+                const T iv = ld_stream(inv + o);
+                const double im = 1.0 / (double)ld_stream(mult + o);
+                const double rd = (double)rv;
+                rr += rd * rd * im;
+                if (with_rz) rz += rd * (double)(iv * rv) * im;
+                hat_add<N>(sqw, q, iv > T(0) ? rd * im : 0.0, s);
+            }
         }
         wave_sum8(s);
         const double out = pick8(s, lane);
