@@ -281,3 +281,31 @@ def test_coarse_degenerate_lattices(semlib, oracle_mod, kind, N, nel, periodic, 
     e2, einf = _relerr(_host(m.precond(_dev(r))), C.apply(r))
     assert e2 <= 1e-12 and einf <= 1e-12, (e2, einf)
     m.close()
+
+
+def test_coarse_cg_with_odd_grids(semlib, oracle_mod):
+    """The coarse-corrected operator sizes its grid to whole rounds of its
+    resident workgroups and reports it for the dot partials: CG (FP64 and
+    mixed) and the operator's u.w agree with the oracle under odd grid caps
+    and several tile shapes."""
+    print("case: coarse cg with odd grid caps box 5x4x3 N=5", flush=True)
+    nel = (5, 4, 3)
+    m, om = _meshes(semlib, oracle_mod, "box", 5, nel, (0, 0, 0), 91)
+    x, y, z = om.coords()
+    b = om.mass(SI.sin3_forcing(x, y, z))
+    C = CoarseOracle(om, k=K, frac=FRAC)
+    _, it_o = pcg(_Op(om), b, C.apply, tol=1e-10)
+    m.set_coarse(K, FRAC)
+    u = SI.random_local(om.nloc, 92)
+    ref_dot = float(np.sum(u * om.ax(u)))
+    for epw, grid in ((1, 7), (2, 13), (3, 1000), (1, 0)):
+        m.set_operator_config(epw, grid)
+        for prec in ("fp64", "mixed"):
+            xg, res = m.solve(_dev(b), tol=1e-10, precision=prec)
+            assert res.ok, (epw, grid, prec, res)
+            assert om.true_residual(b, _host(xg)) <= 1e-10
+            if prec == "fp64":
+                assert abs(res.iterations - it_o) <= max(3, 0.05 * it_o), (epw, grid, res.iterations, it_o)
+        _, d = m.ax(_dev(u), dot=True)
+        assert abs(float(d.item()) - ref_dot) <= 1e-12 * abs(ref_dot), (epw, grid)
+    m.close()
