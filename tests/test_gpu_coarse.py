@@ -120,6 +120,7 @@ PCG_CASES = [
     ("box", 5, (4, 4, 3), (0, 0, 0), 21),
     ("pipe", 5, (6, 6, 5), None, 22),
     ("box", 7, (3, 3, 4), (0, 0, 1), 23),
+    ("box", 4, (3, 3, 3), (0, 0, 0), 24),  # even N: the FP32 update takes one node per lane
 ]
 
 
