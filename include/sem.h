@@ -438,6 +438,15 @@ sem_status sem_batch_step(sem_batch *batch, int iterations, int use_graph, void 
 sem_status sem_batch_finished(const sem_batch *batch, int *slots, int capacity, int *n);
 sem_status sem_batch_retire(sem_batch *batch, int slot, sem_solve_stats *stats);
 
+/* Host-only (for checking): the byte layout of one slot's vector buffer for a
+ * mesh of n_local local points.  offsets[0..2] receive the offsets of the
+ * FP64 r, p, w; with precision SEM_PREC_MIXED offsets[3..6] those of the FP32
+ * x, r, p, w (otherwise 0).  Each vector starts on a 256-byte boundary;
+ * *bytes receives the size the batch allocates for the slot, which holds
+ * every vector.  SEM_EINVAL on a null pointer, n_local < 1 or an unknown
+ * precision. */
+sem_status sem_batch_slot_layout(int64_t n_local, int precision, size_t *offsets, size_t *bytes);
+
 #ifdef __cplusplus
 }
 #endif

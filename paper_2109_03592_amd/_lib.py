@@ -103,6 +103,7 @@ SIGNATURES = {
     "sem_batch_step": (_i, [_vp, _i, _i, _vp, C.POINTER(_i)]),
     "sem_batch_finished": (_i, [_vp, C.POINTER(_i), _i, C.POINTER(_i)]),
     "sem_batch_retire": (_i, [_vp, _i, C.POINTER(SolveStats)]),
+    "sem_batch_slot_layout": (_i, [C.c_int64, _i, _vp, C.POINTER(C.c_size_t)]),
     "sem_solve_opts_default": (None, [C.POINTER(SolveOpts)]),
     "sem_pcg_solve": (_i, [_vp, _vp, _vp, C.POINTER(SolveOpts), C.POINTER(SolveStats), _vp]),
 }

@@ -503,12 +503,32 @@ static int free_slot_index(sem_batch *B)
     return -1;
 }
 
+// Layout of a slot's vector buffer: r, p, w in FP64, then (mixed) x, r, p, w
+// in FP32, each starting on a 256-byte boundary.  off[0..6] receive the byte
+// offsets (unused ones 0); returns the bytes the buffer must hold.  The one
+// helper sizes the allocation and carves it, so the two cannot disagree.
+size_t slot_layout(int64_t nL, int precision, size_t off[7])
+{
+    const size_t v64 = (size_t)nL * 8, v32 = (size_t)nL * 4;
+    auto ru = [](size_t b) { return (b + 255) / 256 * 256; };
+    size_t o = 0;
+    for (int q = 0; q < 7; ++q) off[q] = 0;
+    for (int q = 0; q < 3; ++q) {
+        off[q] = o;
+        o += ru(v64);
+    }
+    if (precision == SEM_PREC_MIXED)
+        for (int q = 3; q < 7; ++q) {
+            off[q] = o;
+            o += ru(v32);
+        }
+    return o;
+}
+
 static size_t slot_bytes(const sem_mesh *m, int precision)
 {
-    const size_t nL = (size_t)m->h.nL;
-    size_t b = 3 * nL * 8;                                   // r, p, w FP64
-    if (precision == SEM_PREC_MIXED) b += 4 * nL * 4;        // x, r, p, w FP32
-    return (b + 255) / 256 * 256 + 256;
+    size_t off[7];
+    return slot_layout(m->h.nL, precision, off);
 }
 
 static int admit_slot(sem_batch *B, sem_mesh *m, const double *b, double *x, const sem_solve_opts &o, hipStream_t s)
@@ -544,6 +564,7 @@ static int admit_slot(sem_batch *B, sem_mesh *m, const double *b, double *x, con
         B->used += need;
         B->slots[id].buf_bytes = need;
     }
+    if (B->slots[id].buf_bytes < need) fail(SEM_EINVAL, "slot buffer smaller than its layout");
     HostSlot &h = B->slots[id];
     h.mesh = m;
     h.opts = o;
@@ -574,22 +595,18 @@ static int admit_slot(sem_batch *B, sem_mesh *m, const double *b, double *x, con
     d.gs_n_ids = hm.gs_n_ids;
     d.b = b;
     d.x64 = x;
+    size_t off[7];
+    slot_layout(hm.nL, o.precision, off);
     char *p = static_cast<char *>(buf);
-    const size_t v64 = (size_t)hm.nL * 8, v32 = (size_t)hm.nL * 4;
-    auto take = [&](size_t bytes) {
-        void *q = p;
-        p += (bytes + 255) / 256 * 256;
-        return q;
-    };
     d.x[0] = x;
-    d.r[0] = take(v64);
-    d.p[0] = take(v64);
-    d.w[0] = take(v64);
+    d.r[0] = p + off[0];
+    d.p[0] = p + off[1];
+    d.w[0] = p + off[2];
     if (o.precision == SEM_PREC_MIXED) {
-        d.x[1] = take(v32);
-        d.r[1] = take(v32);
-        d.p[1] = take(v32);
-        d.w[1] = take(v32);
+        d.x[1] = p + off[3];
+        d.r[1] = p + off[4];
+        d.p[1] = p + off[5];
+        d.w[1] = p + off[6];
     }
     d.st = B->d_state + 2 * id;
     d.scal = B->d_scal + 2 * id;
@@ -613,6 +630,17 @@ static void retire_slot(sem_batch *B, int id)
 using namespace sem;
 
 extern "C" {
+
+sem_status sem_batch_slot_layout(int64_t n_local, int precision, size_t *offsets, size_t *bytes)
+{
+    return bguard([&]() -> sem_status {
+        if (!offsets || !bytes || n_local < 1) fail(SEM_EINVAL, "sem_batch_slot_layout: bad arguments");
+        if (precision != SEM_PREC_FP64 && precision != SEM_PREC_MIXED)
+            fail(SEM_EINVAL, "sem_batch_slot_layout: unknown precision");
+        *bytes = slot_layout(n_local, precision, offsets);
+        return SEM_OK;
+    });
+}
 
 sem_status sem_batch_create(int max_slots, size_t device_budget, void *stream, sem_batch **out)
 {

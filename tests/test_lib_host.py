@@ -154,3 +154,41 @@ def test_host_maps_pipe_full_size(oracle_mod):
     assert info.n_unmasked_global == 335 * 335 * 672
     om = oracle_mod.pipe_mesh(48, 48, 96, N=7)
     assert np.array_equal(gid, om.numbering())
+
+
+def _slot_layout(lib, n_local, precision):
+    off = np.zeros(7, dtype=np.uint64)
+    total = C.c_size_t(0)
+    st = lib.sem_batch_slot_layout(C.c_int64(n_local), precision, off.ctypes.data, C.byref(total))
+    return st, off.astype(np.int64), int(total.value)
+
+
+def test_batch_slot_layout_holds_every_vector(L):
+    """Every vector a batch slot carves from its buffer lies inside the
+    allocation, 256-byte aligned and disjoint from the others, for every
+    order the batch takes (2..10) and element counts 1..4096."""
+    lib = L.load()
+    Es = sorted(set([1, 2, 3, 5, 7, 8, 27, 63, 64, 100, 343, 511, 512, 729, 1000, 2047, 4095, 4096]
+                    + list(np.random.default_rng(5).integers(1, 4097, 60))))
+    for N in range(2, 11):
+        P3 = (N + 1) ** 3
+        for E in Es:
+            nL = int(E) * P3
+            for prec, sizes in ((L.SEM_PREC_FP64, [8, 8, 8]), (L.SEM_PREC_MIXED, [8, 8, 8, 4, 4, 4, 4])):
+                st, off, total = _slot_layout(lib, nL, prec)
+                assert st == L.SEM_OK
+                spans = sorted((int(off[q]), int(off[q]) + nL * sz) for q, sz in enumerate(sizes))
+                for a, b in spans:
+                    assert a % 256 == 0 and b <= total, (N, E, prec, a, b, total)
+                for (a0, b0), (a1, b1) in zip(spans, spans[1:]):
+                    assert b0 <= a1, (N, E, prec)
+                if prec == L.SEM_PREC_FP64:
+                    assert not off[3:].any()
+
+
+def test_batch_slot_layout_rejects_bad_arguments(L):
+    lib = L.load()
+    assert _slot_layout(lib, 0, L.SEM_PREC_FP64)[0] == L.SEM_EINVAL
+    assert _slot_layout(lib, 64, 7)[0] == L.SEM_EINVAL
+    total = C.c_size_t(0)
+    assert lib.sem_batch_slot_layout(C.c_int64(64), L.SEM_PREC_FP64, None, C.byref(total)) == L.SEM_EINVAL
