@@ -6,7 +6,8 @@ imports it, and it imports nothing from the product package.
 
 Every function follows the paper's definitions (arXiv 2109.03592): the GLL
 tensor-product basis and the global/local split of section 2, and the local
-operator of Algorithm 1 (axhelm).  See ``sem_oracle.c`` for the formulas.
+operator (the element stiffness that Algorithm 1 evaluates, here as staged
+tensor contractions).  See ``sem_oracle.c`` for the formulas.
 """
 from __future__ import annotations
 
@@ -81,8 +82,15 @@ def lib():
         L.orc_apply.argtypes = [C.POINTER(_Problem), vp, vp]
         L.orc_pcg.argtypes = [C.POINTER(_Problem), vp, vp, C.c_double, i, C.POINTER(_Stats)]
         L.orc_pcg.restype = i
+        L.orc_threads.argtypes = [i]
+        L.orc_threads.restype = i
         _lib = L
     return _lib
+
+
+def threads(n: int = 0) -> int:
+    """Set the oracle's OpenMP thread count (n > 0); returns the count in use."""
+    return int(lib().orc_threads(int(n)))
 
 
 def _p(a: Optional[np.ndarray]):
@@ -223,7 +231,7 @@ class OracleMesh:
 
     # -- operators ---------------------------------------------------------
     def ax(self, u, h1=None, h2=None, elems=None):
-        """Local operator A_L u of Algorithm 1 (no gather-scatter)."""
+        """Local operator A_L u (the operator of Algorithm 1; no gather-scatter)."""
         G, B = self.geom(elems)
         ne = self.E if elems is None else len(elems)
         u = np.ascontiguousarray(u, dtype=np.float64)

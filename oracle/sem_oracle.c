@@ -24,6 +24,24 @@
 
 #include "sem_oracle.h"
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Threads of the OpenMP loops: n > 0 sets the count; returns the count the
+ * next parallel loop uses (1 without OpenMP).  The loops' results do not
+ * depend on it (each iteration writes its own outputs).                     */
+int orc_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
+
 /* ------------------------------------------------------------------------- */
 /* Legendre polynomial P_n and its first derivative, by the three-term
  * recurrence (n+1) P_{n+1} = (2n+1) x P_n - n P_{n-1}.                        */
@@ -323,65 +341,75 @@ void orc_multiplicity(long nloc, const int64_t *gid, long nglob, int32_t *gmult)
 }
 
 /* ------------------------------------------------------------------------- */
-/* Local operator, Algorithm 1 (axhelm) with the Helmholtz coefficient h1
- * (h1 == NULL means h1 = 1, the Poisson case) and an optional mass term
- * h2 B u (h2 == NULL or B == NULL means none): for every element and node,
- *   ur = sum_l D[i][l] u(l,j,k), us = sum_l D[j][l] u(i,l,k),
- *   ut = sum_l D[k][l] u(i,j,l),
- *   wr = g1 ur + g4 us + g5 ut, ws = g2 us + g4 ur + g6 ut,
- *   wt = g3 ut + g5 ur + g6 us, all times h1,
- * then w(i,j,k) = sum_l D[l][i] wr(l,j,k) + D[l][j] ws(i,l,k) + D[l][k] wt(i,j,l)
- * with the three products added per l in that order, l ascending.
- * G is component-major over the ne*P^3 points passed.                        */
+/* Local operator of one element in tensor-product form (section 2: the GLL
+ * stiffness of Eq. 5, or Eq. 4's Helmholtz form; Algorithm 1 evaluates the
+ * same operator).  With D_a the 1-D derivative matrix acting along axis a of
+ * the element's (i,j,k) grid (a = r: i, s: j, t: k), G the symmetric 3x3
+ * matrix of geometric factors at each point (g1 = G_rr, g2 = G_ss,
+ * g3 = G_tt, g4 = G_rs, g5 = G_rt, g6 = G_st; weights and det J folded in):
+ *   A_e u = sum_a D_a^T (h1 sum_b G_ab (D_b u)) + h2 B u,
+ * evaluated as three stages: the reference gradient (D_r u, D_s u, D_t u),
+ * the pointwise metric product, and the transposed contractions, each
+ * direction in its own pass and the three added per point (r, then s, then
+ * t).  Every contraction sums over its index in ascending order.  h1 == NULL
+ * means h1 = 1 (Poisson); h2 or B == NULL means no mass term.             */
+
+/* y = (M along axis `axis`) x on a P^3 grid, or with M transposed:
+ *   axis 0: y(i,j,k) = sum_l M(i,l) x(l,j,k)   (transposed: M(l,i))
+ *   axis 1: y(i,j,k) = sum_l M(j,l) x(i,l,k)
+ *   axis 2: y(i,j,k) = sum_l M(k,l) x(i,j,l)                             */
+static void contract_axis(int P, const double *M, int transposed, int axis, const double *x, double *y)
+{
+    const long stride = axis == 0 ? 1 : (axis == 1 ? P : (long)P * P);
+    for (int k = 0; k < P; ++k)
+        for (int j = 0; j < P; ++j)
+            for (int i = 0; i < P; ++i) {
+                const int row = axis == 0 ? i : (axis == 1 ? j : k);
+                const long base = i + (long)P * j + (long)P * P * k - (long)row * stride;
+                double sum = 0.0;
+                for (int l = 0; l < P; ++l) {
+                    const double m = transposed ? M[l * P + row] : M[row * P + l];
+                    sum += m * x[base + l * stride];
+                }
+                y[i + (long)P * j + (long)P * P * k] = sum;
+            }
+}
+
 void orc_ax(int N, long ne, const double *D, const double *G, const double *h1,
             const double *h2, const double *B, const double *u, double *w)
 {
     const int P = N + 1;
     const long P3 = (long)P * P * P;
     const long nloc = ne * P3;
+    /* position in G of the factor G_ab (component-major, g1..g6 as above) */
+    static const int comp[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
 #pragma omp parallel
     {
-        double *wr = (double *)malloc(sizeof(double) * P3);
-        double *ws = (double *)malloc(sizeof(double) * P3);
-        double *wt = (double *)malloc(sizeof(double) * P3);
+        double *grad = (double *)malloc(sizeof(double) * 3 * P3);  /* D_a u        */
+        double *flux = (double *)malloc(sizeof(double) * 3 * P3);  /* h1 G grad    */
+        double *part = (double *)malloc(sizeof(double) * 3 * P3);  /* D_a^T flux_a */
 #pragma omp for schedule(static)
         for (long e = 0; e < ne; ++e) {
             const double *ue = u + e * P3;
-            for (int k = 0; k < P; ++k)
-                for (int j = 0; j < P; ++j)
-                    for (int i = 0; i < P; ++i) {
-                        long p = i + (long)P * j + (long)P * P * k;
-                        double rtmp = 0, stmp = 0, ttmp = 0;
-                        for (int l = 0; l < P; ++l) {
-                            rtmp += D[i * P + l] * ue[l + P * j + P * P * k];
-                            stmp += D[j * P + l] * ue[i + P * l + P * P * k];
-                            ttmp += D[k * P + l] * ue[i + P * j + P * P * l];
-                        }
-                        long o = e * P3 + p;
-                        double g1 = G[0 * nloc + o], g2 = G[1 * nloc + o], g3 = G[2 * nloc + o];
-                        double g4 = G[3 * nloc + o], g5 = G[4 * nloc + o], g6 = G[5 * nloc + o];
-                        double a = g1 * rtmp + g4 * stmp + g5 * ttmp;
-                        double b = g2 * stmp + g4 * rtmp + g6 * ttmp;
-                        double c = g3 * ttmp + g5 * rtmp + g6 * stmp;
-                        double h = h1 ? h1[o] : 1.0;
-                        wr[p] = a * h;
-                        ws[p] = b * h;
-                        wt[p] = c * h;
-                    }
-            for (int k = 0; k < P; ++k)
-                for (int j = 0; j < P; ++j)
-                    for (int i = 0; i < P; ++i) {
-                        double acc = 0;
-                        for (int l = 0; l < P; ++l)
-                            acc = acc + D[l * P + i] * wr[l + P * j + P * P * k]
-                                      + D[l * P + j] * ws[i + P * l + P * P * k]
-                                      + D[l * P + k] * wt[i + P * j + P * P * l];
-                        long o = e * P3 + i + (long)P * j + (long)P * P * k;
-                        if (h2 && B) acc += h2[o] * B[o] * ue[i + P * j + P * P * k];
-                        w[o] = acc;
-                    }
+            for (int ax = 0; ax < 3; ++ax) contract_axis(P, D, 0, ax, ue, grad + ax * P3);
+            for (long p = 0; p < P3; ++p) {
+                const long o = e * P3 + p;
+                const double scale = h1 ? h1[o] : 1.0;
+                for (int ax = 0; ax < 3; ++ax) {
+                    double f = 0.0;
+                    for (int bx = 0; bx < 3; ++bx) f += G[comp[ax][bx] * nloc + o] * grad[bx * P3 + p];
+                    flux[ax * P3 + p] = f * scale;
+                }
+            }
+            for (int ax = 0; ax < 3; ++ax) contract_axis(P, D, 1, ax, flux + ax * P3, part + ax * P3);
+            for (long p = 0; p < P3; ++p) {
+                const long o = e * P3 + p;
+                double v = part[p] + part[P3 + p] + part[2 * P3 + p];
+                if (h2 && B) v += h2[o] * B[o] * ue[p];
+                w[o] = v;
+            }
         }
-        free(wr); free(ws); free(wt);
+        free(grad); free(flux); free(part);
     }
 }
 

@@ -58,6 +58,7 @@ void orc_jacobi(int N, long ne, const double *D, const double *G, const double *
                 const double *h2, const double *B, const int64_t *gid, long nglob,
                 const uint8_t *gmask, double *invdiag);
 void orc_apply(const orc_problem *pb, const double *v, double *w);
+int orc_threads(int n);
 int orc_pcg(const orc_problem *pb, const double *b, double *x, double tol, int max_iter,
             orc_pcg_stats *st);
 
