@@ -46,20 +46,32 @@ class ServeStats:
     refused: int = 0
     elapsed: float = 0.0
     latencies: List[float] = field(default_factory=list)
+    # requests without a result when the run ends: their wait so far, a lower
+    # bound of their latency (right-censored)
+    censored: List[float] = field(default_factory=list)
     steps: int = 0
     max_active: int = 0
 
-    def summary(self) -> Dict:
-        lat = sorted(self.latencies)
+    @staticmethod
+    def _pct(lat: List[float], p: float) -> float:
+        if not lat:
+            return float("nan")
+        k = min(len(lat) - 1, max(0, int(math.ceil(p / 100.0 * len(lat))) - 1))
+        return lat[k]
 
-        def pct(p):
-            if not lat:
-                return float("nan")
-            k = min(len(lat) - 1, max(0, int(math.ceil(p / 100.0 * len(lat))) - 1))
-            return lat[k]
+    def summary(self) -> Dict:
+        """p50/p99 over every request that arrived: completed ones at their
+        latency, unfinished ones at their wait so far.  With unfinished
+        requests the percentiles are lower bounds (``censored`` > 0); the
+        completed-only figures are reported beside them."""
+        done = sorted(self.latencies)
+        every = sorted(self.latencies + self.censored)
         return {"completed": self.completed, "unfinished": self.unfinished, "refused": self.refused,
                 "solves_per_s": self.completed / self.elapsed if self.elapsed > 0 else 0.0,
-                "p50_ms": pct(50) * 1e3, "p99_ms": pct(99) * 1e3, "max_ms": (lat[-1] * 1e3 if lat else float("nan")),
+                "p50_ms": self._pct(every, 50) * 1e3, "p99_ms": self._pct(every, 99) * 1e3,
+                "max_ms": (every[-1] * 1e3 if every else float("nan")),
+                "censored": len(self.censored), "percentiles_are_lower_bounds": bool(self.censored),
+                "p50_completed_ms": self._pct(done, 50) * 1e3, "p99_completed_ms": self._pct(done, 99) * 1e3,
                 "elapsed_s": self.elapsed, "steps": self.steps, "max_active": self.max_active}
 
 
@@ -166,6 +178,9 @@ class Scheduler:
             if self.clock() > t_end:
                 break
         stats.unfinished += len(self.active) + len(self.pending) + len(arrivals)
+        now = self.clock()
+        for job in list(self.active.values()) + list(self.pending) + list(arrivals):
+            stats.censored.append(max(0.0, now - job.t_arrival))
         for slot in list(self.active):
             job = self.active.pop(slot)
             self.e.retire(slot)

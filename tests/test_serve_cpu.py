@@ -132,6 +132,23 @@ def test_drain_limit_counts_unfinished():
     st = sched.run(jobs, horizon=0.1, drain_limit=1.0)
     assert st.completed == 0 and st.unfinished == 2
     assert not sched.active and sched.slot_mem == 0
+    # both enter the percentiles at their wait so far (lower bounds)
+    assert len(st.censored) == 2 and min(st.censored) >= 1.0
+    s = st.summary()
+    assert s["censored"] == 2 and s["percentiles_are_lower_bounds"]
+    assert s["p50_ms"] >= 1000.0 and s["p99_ms"] >= 1000.0
+
+
+def test_censored_requests_raise_the_percentiles():
+    """Unfinished requests count at their wait so far: a saturated run's p99
+    can only rise over the completed-only figure."""
+    st = ServeStats(completed=90, elapsed=2.0, latencies=[i / 1000 for i in range(1, 91)],
+                    censored=[5.0] * 10)
+    s = st.summary()
+    assert s["p50_completed_ms"] == pytest.approx(45.0)
+    assert s["p50_ms"] == pytest.approx(50.0)
+    assert s["p99_ms"] == pytest.approx(5000.0) and s["max_ms"] == pytest.approx(5000.0)
+    assert s["censored"] == 10 and s["percentiles_are_lower_bounds"]
 
 
 def test_percentiles():
