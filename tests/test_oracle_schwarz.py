@@ -72,3 +72,45 @@ def test_fewer_iterations_than_jacobi(oracle_mod):
     xs, its = pcg(m, b, SchwarzOracle(m).apply, tol=1e-10)
     assert m.true_residual(b, xs) <= 1e-10
     assert its < 0.6 * rj.iterations, (its, rj.iterations)
+
+
+def test_element_lengths_on_a_distorted_element(oracle_mod):
+    """The local problem's length per direction is the mean of the four
+    straight edges of the element along that direction.  On one trilinear
+    element with hand-placed vertices whose four edges differ in every
+    direction, the oracle's lengths equal the means computed here directly
+    from the vertex coordinates (so averaging two edges, mixing directions or
+    measuring along the curve would all fail)."""
+    V = np.array([[0.00, 0.00, 0.00], [1.00, 0.05, 0.00], [0.10, 1.20, 0.05], [1.30, 1.10, 0.10],
+                  [0.05, 0.10, 0.90], [0.90, 0.20, 1.00], [0.00, 1.00, 1.10], [1.20, 1.05, 1.30]])
+    m = oracle_mod.OracleMesh(3, (1, 1, 1), vertices=V.reshape(-1))
+    S = SchwarzOracle(m)
+    d = lambda a, b: float(np.linalg.norm(V[a] - V[b]))
+    edges = {
+        "r": [(0, 1), (2, 3), (4, 5), (6, 7)],
+        "s": [(0, 2), (1, 3), (4, 6), (5, 7)],
+        "t": [(0, 4), (1, 5), (2, 6), (3, 7)],
+    }
+    want = [np.mean([d(a, b) for a, b in edges[x]]) for x in "rst"]
+    for x in "rst":
+        lens = [d(a, b) for a, b in edges[x]]
+        assert max(lens) - min(lens) > 0.05, x  # the four edges really differ
+    got = S.lengths(0)
+    assert np.allclose(got, want, rtol=1e-14, atol=0.0), (got, want)
+
+
+def test_element_lengths_on_jittered_elements(oracle_mod):
+    """The same rule on every element of a jittered 3x2x2 box, from the
+    vertex array passed to the mesh."""
+    nel = (3, 2, 2)
+    V = SI.jittered_box_vertices(nel, seed=8)
+    m = oracle_mod.OracleMesh(3, nel, vertices=V)
+    S = SchwarzOracle(m)
+    VV = np.asarray(V).reshape(nel[2] + 1, nel[1] + 1, nel[0] + 1, 3)
+    for e in range(m.E):
+        ex, ey, ez = e % nel[0], (e // nel[0]) % nel[1], e // (nel[0] * nel[1])
+        c = lambda dx, dy, dz: VV[ez + dz, ey + dy, ex + dx]
+        lr = np.mean([np.linalg.norm(c(1, y, z) - c(0, y, z)) for y in (0, 1) for z in (0, 1)])
+        ls = np.mean([np.linalg.norm(c(x, 1, z) - c(x, 0, z)) for x in (0, 1) for z in (0, 1)])
+        lt = np.mean([np.linalg.norm(c(x, y, 1) - c(x, y, 0)) for x in (0, 1) for y in (0, 1)])
+        assert np.allclose(S.lengths(e), (lr, ls, lt), rtol=1e-13, atol=0.0), e
