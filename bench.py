@@ -69,7 +69,8 @@ def gs_bytes(info, dtype_bytes: int = 8) -> float:
 # Sources the operator kernel is built from; the committed counter summary
 # records their hash, and its traffic figure is used only while they match.
 KERNEL_SOURCES = ("paper_2109_03592_amd/csrc/operator.hpp", "paper_2109_03592_amd/csrc/kernels.hip",
-                  "paper_2109_03592_amd/csrc/kernels.hpp")
+                  "paper_2109_03592_amd/csrc/kernels.hpp", "paper_2109_03592_amd/csrc/axgs_impl.hpp",
+                  "paper_2109_03592_amd/csrc/axgs.hpp", "paper_2109_03592_amd/csrc/axgs64.hip")
 TRAFFIC_PROFILE = "profiles/hbm_traffic_pcg_pipe48x48x96_N7.txt"
 
 
@@ -114,10 +115,27 @@ def copy_calibration():
     log(f"copy calibration: {8 * n} bytes read and {8 * n} written per dispatch")
 
 
-def cpu_baseline(seconds_target: float = 15.0):
-    """The oracle, as it stands, on a bounded slab of the same pipe."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(seconds_target: float = 10.0):
+    """The oracle, as it stands, on the host cores.  `value`: FP64 Jacobi-PCG
+    iterations on a 48x48x8 slab of the pipe (the step's unit, GDOF/s) with
+    every OpenMP thread; beside it the full 48x48x96 pipe's Ax+gs apply
+    (median of 3 on every thread, and one apply on 1 thread)."""
     from oracle import oracle as O
     import seeded_inputs as SI
+    threads = O.threads(0)
+    out = {"unit": "GDOF/s", "cores": threads, "kind": "oracle", "cpu_model": cpu_model(),
+           "host_cpus": os.cpu_count()}
     nz = 8
     om = O.pipe_mesh(48, 48, nz, N=7)
     gid = om.numbering()
@@ -133,31 +151,75 @@ def cpu_baseline(seconds_target: float = 15.0):
     t0 = time.perf_counter()
     _, res = om.pcg(b, tol=1e-30, max_iter=iters)
     dt = time.perf_counter() - t0
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {
-        "value": om.nglob * res.iterations / dt / 1e9,
-        "unit": "GDOF/s",
-        "cores": threads,
-        "kind": "oracle",
-        "sample": (f"pipe 48x48x{nz} N=7 ({om.E} elements, {om.nglob} global nodes), "
-                   f"{res.iterations} FP64 Jacobi-PCG iterations in {dt:.2f} s (plus 2 residual applies); "
-                   f"OpenMP over elements, gather-scatter and dots sequential"),
-    }
+    out["value"] = om.nglob * res.iterations / dt / 1e9
+    sample = (f"pipe 48x48x{nz} N=7 ({om.E} elements, {om.nglob} global nodes), {res.iterations} FP64 "
+              f"Jacobi-PCG iterations in {dt:.2f} s (plus 2 residual applies) on {threads} threads; "
+              f"OpenMP over elements, gather-scatter and dots sequential")
+    del om, b, gid
+    # the full pipe: Ax+gs applies
+    om = O.pipe_mesh(48, 48, 96, N=7)
+    om.geom()
+    om.numbering()
+    u = SI.random_local(om.nloc, 3)
+    om.apply(u)
+    ts = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        om.apply(u)
+        ts.append(time.perf_counter() - t0)
+    t_all = sorted(ts)[1]
+    O.threads(1)
+    try:
+        t0 = time.perf_counter()
+        om.apply(u)
+        t_one = time.perf_counter() - t0
+    finally:
+        O.threads(threads)
+    out["axgs_full_pipe"] = {"gdofs": om.nglob / t_all / 1e9, "s_per_apply": t_all, "threads": threads,
+                             "gdofs_1_thread": om.nglob / t_one / 1e9, "s_per_apply_1_thread": t_one,
+                             "applies": "median of 3 (all threads), 1 (1 thread)"}
+    out["sample"] = sample + (f"; full 48x48x96 pipe Ax+gs apply {t_all:.2f} s on {threads} threads "
+                              f"(median of 3), {t_one:.2f} s on 1 thread")
+    return out
+
+
+def _event_mean(evs, stride, a, b, n):
+    return float(np.mean([evs[stride * q + a].elapsed_time(evs[stride * q + b]) for q in range(n)])) / 1e3
 
 
 def axgs_timing(mesh, info, N, torch, SI, stream, applies: int):
-    """Stand-alone Ax+gs applies in FP64 and FP32 (events around each launch)."""
+    """Stand-alone Ax+gs applies in FP64 and FP32 through sem_axgs, events
+    around each apply (median); the library's default runs the operator and
+    the gather-scatter as two launches, timed here also launch by launch; the
+    opt-in fused operator + gather-scatter is timed beside it."""
     nL, nG = mesh.n_local, mesh.n_global
     res = {}
+
+    def applies_ms(u, w):
+        for _ in range(3):
+            mesh.axgs(u, w)
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(2 * applies)]
+        torch.cuda.synchronize()
+        for q in range(applies):
+            evs[2 * q].record(stream)
+            mesh.axgs(u, w)
+            evs[2 * q + 1].record(stream)
+        torch.cuda.synchronize()
+        return sorted(evs[2 * q].elapsed_time(evs[2 * q + 1]) for q in range(applies))[applies // 2] / 1e3
+
     for name, dt, eb in (("fp64", torch.float64, 8), ("fp32", torch.float32, 4)):
         u = torch.from_numpy(SI.random_local(nL, 3)).to(device="cuda", dtype=dt)
         w = torch.empty_like(u)
+        byt = bytes_per_point(N, "ax", eb) * nL + gs_bytes(info, eb)
+        tA = time.perf_counter()
+        tot = applies_ms(u, w)
+        wall = time.perf_counter() - tA
+        # launch by launch
         for _ in range(3):
             mesh.ax(u, w)
             mesh.gs(w)
         evs = [torch.cuda.Event(enable_timing=True) for _ in range(3 * applies)]
         torch.cuda.synchronize()
-        tA = time.perf_counter()
         for q in range(applies):
             evs[3 * q].record(stream)
             mesh.ax(u, w)
@@ -165,17 +227,23 @@ def axgs_timing(mesh, info, N, torch, SI, stream, applies: int):
             mesh.gs(w)
             evs[3 * q + 2].record(stream)
         torch.cuda.synchronize()
-        wall = time.perf_counter() - tA
-        t_ax = np.mean([evs[3 * q].elapsed_time(evs[3 * q + 1]) for q in range(applies)]) / 1e3
-        t_gs = np.mean([evs[3 * q + 1].elapsed_time(evs[3 * q + 2]) for q in range(applies)]) / 1e3
-        tot = evs[0].elapsed_time(evs[-1]) / 1e3 / applies
-        byt = bytes_per_point(N, "ax", eb) * nL + gs_bytes(info, eb)
-        res[name] = {"gdofs": nG / tot / 1e9, "ms_per_apply": tot * 1e3, "ms_ax": t_ax * 1e3,
-                     "ms_gs": t_gs * 1e3, "ax_gbs": bytes_per_point(N, "ax", eb) * nL / t_ax / 1e9,
-                     "gs_gbs": gs_bytes(info, eb) / t_gs / 1e9,
-                     "hbm_frac": byt / tot / 1e9 / HBM_PEAK_GBS,
-                     "ax_tflops": flops_per_point(N) * nL / t_ax / 1e12,
-                     "algorithmic_bytes": byt, "applies": applies, "wall_s": wall}
+        t_ax = _event_mean(evs, 3, 0, 1, applies)
+        t_gs = _event_mean(evs, 3, 1, 2, applies)
+        r = {"gdofs": nG / tot / 1e9, "ms_per_apply": tot * 1e3, "hbm_frac": byt / tot / 1e9 / HBM_PEAK_GBS,
+             "ms_ax": t_ax * 1e3, "ms_gs": t_gs * 1e3,
+             "ax_gbs": bytes_per_point(N, "ax", eb) * nL / t_ax / 1e9, "gs_gbs": gs_bytes(info, eb) / t_gs / 1e9,
+             "ax_tflops": flops_per_point(N) * nL / t_ax / 1e12, "algorithmic_bytes": byt, "applies": applies,
+             "wall_s": wall, "timing": "median of per-apply events"}
+        # the opt-in fused path (lines per workgroup chosen automatically)
+        mesh.set_axgs_config(True)
+        fused = mesh.axgs_info(dt)
+        if fused["enabled"]:
+            tf = applies_ms(u, w)
+            r["fused"] = {"ms_per_apply": tf * 1e3, "hbm_frac": byt / tf / 1e9 / HBM_PEAK_GBS,
+                          **{k: fused[k] for k in ("epw", "lines_per_wg", "y_onchip", "residual_ids",
+                                                   "residual_copies")}}
+        mesh.set_axgs_config(False)
+        res[name] = r
         del u, w
     return res
 
@@ -287,6 +355,8 @@ def coarse_section(mesh, b, args, torch, stream, jacobi_solve=None):
         torch.cuda.synchronize()
         t_it = e0.elapsed_time(e1) / 1e3 / args.steps
         n = max(1, res.operator_launches)
+        mesh.solve(b, x, fixed_iters=args.steps, use_graph=True, poll_every=25, initial_guess=False)
+        torch.cuda.synchronize()
         e0.record(stream)
         mesh.solve(b, x, fixed_iters=args.steps, use_graph=True, poll_every=25, initial_guess=False)
         e1.record(stream)
@@ -375,6 +445,44 @@ def sweep(sem, torch, SI, orders, sizes, applies: int = 20):
                 f"({row['fp64']['hbm_frac'] * 100:5.1f}% HBM), fp32 {row['fp32']['gdofs']:7.2f} GDOF/s "
                 f"({row['fp32']['hbm_frac'] * 100:5.1f}% HBM)")
     return rows
+
+
+def oracle_error_section(sem, torch, SI, nel=(12, 12, 8), N: int = 7):
+    """Each GPU solve's error against the FP64 oracle's solve of the same
+    system: a 12x12x8 slab of the pipe (the full pipe's oracle solve would take
+    hours on the host) with the oracle's own factors loaded into the library,
+    the same seeded noise right-hand side; FP64 and mixed GPU solves and the
+    oracle's Jacobi-PCG all to a 1e-10 relative residual.  Errors in the
+    unique-dof 2-norm, relative to the oracle's solution; the oracle also
+    measures each GPU solution's true residual."""
+    from oracle import oracle as O
+    om = O.pipe_mesh(*nel, N=N)
+    G, B = om.geom()
+    m = sem.pipe_mesh(*nel, N=N, with_fp32=True)
+    m.load_geometry(G, B)
+    del G, B
+    gid = om.numbering()
+    b = SI.uniform_global_values(om.nglob, 2)[gid]
+    b[om.local_mask() == 1] = 0.0
+    t0 = time.perf_counter()
+    xo, ro = om.pcg(b, tol=1e-10, max_iter=20000)
+    out = {"mesh": f"pipe {nel[0]}x{nel[1]}x{nel[2]} N={N}", "n_global": om.nglob,
+           "oracle": {"iterations": ro.iterations, "rel_residual": ro.rel_residual,
+                      "seconds": time.perf_counter() - t0, "threads": O.threads(0)}}
+    bd = torch.from_numpy(b).cuda()
+    no = np.sqrt(om.dot(xo, xo))
+    for prec in ("fp64", "mixed"):
+        x, r = m.solve(bd, tol=1e-10, max_iter=20000, precision=prec, raise_on_error=False)
+        xh = x.cpu().numpy()
+        d = xh - xo
+        out[prec] = {"status": r.status, "iterations": r.iterations, "outer": r.outer_iterations,
+                     "rel_error_vs_oracle": float(np.sqrt(om.dot(d, d)) / no),
+                     "oracle_true_residual": float(om.true_residual(b, xh))}
+    m.close()
+    log(f"vs oracle ({out['mesh']}): fp64 error {out['fp64']['rel_error_vs_oracle']:.2e}, mixed error "
+        f"{out['mixed']['rel_error_vs_oracle']:.2e} (oracle {ro.iterations} iterations, residual "
+        f"{ro.rel_residual:.2e})")
+    return out
 
 
 def projection_section(sem, torch, SI, nel=(24, 24, 48), N: int = 7, solves: int = 6, vectors: int = 8):
@@ -500,8 +608,6 @@ def main():
                          "(Schwarz + coarse), comma-separated ('' skips)")
     ap.add_argument("--no-proj", action="store_true", help="skip the successive-RHS projection timing")
     ap.add_argument("--no-n9", action="store_true", help="skip the N=9 pipe (48x48x48)")
-    ap.add_argument("--operator-kernel", choices=("column", "node"), default=None,
-                    help="thread layout of the operator on the N=7 pipe (default: the library's)")
     ap.add_argument("--serve-rates", default="10,100,1000")
     ap.add_argument("--serve-duration", type=float, default=5.0)
     ap.add_argument("--serve-drain", type=float, default=20.0)
@@ -541,8 +647,6 @@ def main():
     N = args.order
     t0 = time.perf_counter()
     mesh = sem.pipe_mesh(nx, ny, nz, N=N, with_fp32=True)
-    if args.operator_kernel:
-        mesh.set_operator_kernel(args.operator_kernel)
     info = mesh.info
     log(f"setup: E={mesh.E} N={N} n_local={mesh.n_local} n_global={mesh.n_global} "
         f"({time.perf_counter() - t0:.1f} s, {info.device_bytes / 2**30:.1f} GiB on device)")
@@ -568,7 +672,10 @@ def main():
     up_ms = res.ms_update / max(1, res.operator_launches)
     log(f"pcg steps: {args.steps} in {t_steps * 1e3:.1f} ms -> {value:.2f} GDOF/s; per iteration "
         f"operator {ax_ms:.3f} ms, gs {gs_ms:.3f} ms, update {up_ms:.3f} ms")
-    # graph-replayed iterations (no per-kernel events)
+    # graph-replayed iterations (no per-kernel events); the same call once
+    # untimed first, so that the graph of this iteration count is captured
+    # and instantiated outside the timed region
+    mesh.solve(b, x, fixed_iters=args.steps, use_graph=True, poll_every=25, initial_guess=False)
     torch.cuda.synchronize()
     ev0.record(stream)
     mesh.solve(b, x, fixed_iters=args.steps, use_graph=True, poll_every=25, initial_guess=False)
@@ -576,11 +683,17 @@ def main():
     torch.cuda.synchronize()
     t_graph = ev0.elapsed_time(ev1) / 1e3
 
+    # the dominant kernel: the CG operator, fused with the gather-scatter of
+    # the ids a workgroup holds where that path runs; achieved counts only the
+    # operator's own streams (r, D^-1, p, x, 6 factors read; p, w, x written)
+    fused = mesh.axgs_info()
+    kname = (f"axgs_kernel<double, {N}, 2, false>" if fused["enabled"] else f"ax_kernel<double, {N}, 2, false>")
     ax_bytes = bytes_per_point(N, "ax_pcg") * nL
-    roof = {"bound": "hbm", "kernel": f"ax_kernel<double,{N},cg>",
+    roof = {"bound": "hbm", "kernel": kname,
             "achieved": ax_bytes / (ax_ms / 1e3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "traffic": measured_traffic(f"ax_kernel<double, {N}, 2, false>", (nx, ny, nz), N, nL),
-            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)"}
+            "traffic": measured_traffic(kname, (nx, ny, nz), N, nL),
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+            "algorithmic_bytes_per_launch": ax_bytes, "ms_per_launch": ax_ms}
     roof["frac"] = roof["achieved"] / roof["peak"]
     step_bytes = ax_bytes + gs_bytes(info) + bytes_per_point(N, "update") * nL
 
@@ -592,6 +705,7 @@ def main():
                    "E": mesh.E, "N": N, "n_local": nL, "n_global": nG},
         "roofline": roof,
         "step": {"ms_operator": ax_ms, "ms_gather_scatter": gs_ms, "ms_update_reduce": up_ms,
+                 "fused_operator_gs": fused,
                  "hbm_frac_step": step_bytes / (t_steps / args.steps) / 1e9 / HBM_PEAK_GBS,
                  "algorithmic_bytes_per_step": step_bytes,
                  "ms_per_step_graph": t_graph / args.steps * 1e3,
@@ -605,7 +719,7 @@ def main():
             a = axgs[name]
             log(f"ax+gs {name}: {a['gdofs']:.2f} GDOF/s, {a['ms_per_apply']:.3f} ms/apply, "
                 f"ax {a['ms_ax']:.3f} ms ({a['ax_gbs']:.0f} GB/s), gs {a['ms_gs']:.3f} ms, "
-                f"HBM {a['hbm_frac'] * 100:.1f}%")
+                f"HBM {a['hbm_frac'] * 100:.1f}%; fused {a.get('fused')}")
         out["ax_gs"] = axgs
 
     # ---- full solves to 1e-10: FP64 and mixed --------------------------------
@@ -630,6 +744,8 @@ def main():
                 err = float(torch.linalg.norm(d) / torch.linalg.norm(x64))
                 sol[prec]["rel_diff_vs_fp64"] = err
         sol["mixed_speedup"] = sol["fp64"]["seconds"] / sol["mixed"]["seconds"]
+        if not args.no_cpu:
+            sol["vs_fp64_oracle"] = oracle_error_section(sem, torch, SI)
         out["solve"] = sol
 
     # ---- the preconditioners of Eq. 6 (coarse term, Schwarz local solves) ------
@@ -688,7 +804,10 @@ def main():
     if not args.no_cpu:
         log("cpu baseline: oracle on a pipe slab ...")
         out["cpu_baseline"] = cpu_baseline()
-        log(f"cpu baseline: {out['cpu_baseline']['value']:.4f} GDOF/s on {out['cpu_baseline']['cores']} threads")
+        cb = out["cpu_baseline"]
+        log(f"cpu baseline ({cb['cpu_model']}, {cb['cores']} threads): PCG {cb['value']:.4f} GDOF/s; "
+            f"full-pipe Ax+gs {cb['axgs_full_pipe']['gdofs']:.4f} GDOF/s, 1 thread "
+            f"{cb['axgs_full_pipe']['gdofs_1_thread']:.4f} GDOF/s")
 
     print(json.dumps(out), flush=True)
 

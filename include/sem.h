@@ -157,19 +157,54 @@ sem_status sem_load_geometry(sem_mesh *mesh, const double *G, const double *B, v
 sem_status sem_set_operator_config(sem_mesh *mesh, int epw, int grid);
 sem_status sem_get_operator_config(const sem_mesh *mesh, int *epw, int *grid);
 
-/* Thread layout of the local operator:
- *   SEM_OPK_COLUMN -- one lane per (i,j) column of an element, the column in
- *     registers and the t-derivative without LDS (any N; uses the
- *     elements-per-workgroup of sem_set_operator_config);
- *   SEM_OPK_NODE   -- one lane per node, as in Algorithm 1's thread layout,
- *     with the element and the three weighted derivatives in LDS (N <= 7;
- *     whole elements fill up to 512 lanes).
- * Both compute Algorithm 1 with the same sums in the same order; results may
- * differ in the last bit where the compiler fuses multiply-adds differently.
- * Errors: SEM_EINVAL (unknown kind, SEM_OPK_NODE with N > 7). */
-enum { SEM_OPK_COLUMN = 0, SEM_OPK_NODE = 1 };
-sem_status sem_set_operator_kernel(sem_mesh *mesh, int kind);
-sem_status sem_get_operator_kernel(const sem_mesh *mesh, int *kind);
+
+/* Fused operator and gather-scatter (Algorithm 1 followed by section 2's
+ * exchange of element face values, done in one launch for the faces a
+ * workgroup holds).  A workgroup takes lines_per_wg consecutive x-lines of
+ * elements (elements are numbered x fastest) and walks them in element order,
+ * epw elements per tile.  A node on an interior t-plane (0 < k < N) whose
+ * copies all lie in the workgroup -- across an x-face of one line, a y-face
+ * between two of its lines, or the edge where both meet -- is summed in LDS
+ * in ascending local index, the order of sem_gs, and written to every copy;
+ * Dirichlet nodes are written as 0.  The remaining shared nodes (the t-planes
+ * k = 0 and N, faces between workgroups, periodic x and y seams) are summed
+ * by a gather-scatter launch over a residual plan.  The result is the same
+ * bits as sem_ax followed by sem_gs.
+ * Used by sem_axgs, the true residual of sem_pcg_solve and the Jacobi CG
+ * iteration (FP64 and FP32) for orders 2..12; other settings (coarse term,
+ * Schwarz, other orders) run the operator and the full gather-scatter as two
+ * launches.
+ * It is off by default: on the 48x48x96 pipe at N = 7 the fused apply
+ * measured 1.95-1.98 ms against 1.92 ms for the two launches (the
+ * line-ordered walk and the epilogue cost more than the gather-scatter
+ * traffic they save).
+ * sem_set_axgs_config: enable 0 (default) or 1; epw and lines_per_wg 0 pick
+ * them automatically (the tile that keeps the most waves resident, then the
+ * smallest line count that fills the device in one round).  It waits for the
+ * device and drops cached CG graphs.  Errors: SEM_EINVAL (enable not 0/1,
+ * negative counts, epw (N+1)^2 > 512, more workgroups than the partials
+ * buffer holds); a tile whose LDS exceeds the device limit makes the fused
+ * path unavailable (the two launches run).
+ * sem_get_axgs_info: the shape in use for dtype (SEM_FP64 or SEM_FP32; built
+ * on first use); enabled = 0 when the fused path does not apply. */
+typedef struct {
+    int enabled;              /* 1: the fused path runs for this precision     */
+    int epw;                  /* elements per tile                             */
+    int lines_per_wg;         /* x-lines per workgroup                         */
+    int y_onchip;             /* 1: y-faces between a workgroup's lines in LDS */
+    int64_t grid;             /* workgroups per launch                         */
+    int64_t residual_ids;     /* global ids left to the residual launch        */
+    int64_t residual_copies;  /* their local copies                            */
+} sem_axgs_info;
+sem_status sem_set_axgs_config(sem_mesh *mesh, int enable, int epw, int lines_per_wg);
+sem_status sem_get_axgs_info(sem_mesh *mesh, int dtype, sem_axgs_info *info);
+/* Host-only (for checking): the residual plan the fused path would use on the
+ * mesh of desc with lines_per_wg x-lines per workgroup (y_onchip 0 or 1), in
+ * the sem_host_setup plan format: *n_ids and *n_copies receive its sizes;
+ * off[n_ids + 1] and idx[n_copies] (may be NULL) the ids' local copies.
+ * Errors: SEM_EINVAL (null desc or sizes, lines_per_wg < 1, invalid mesh). */
+sem_status sem_host_axgs_residual(const sem_mesh_desc *desc, int lines_per_wg, int y_onchip, int64_t *n_ids,
+                                  int64_t *n_copies, int32_t *off, int32_t *idx);
 
 /* Helmholtz form of the operator (Eq. 4 with the variable coefficient h1 of
  * Algorithm 1): afterwards sem_ax, sem_axgs and sem_pcg_solve apply
@@ -419,6 +454,15 @@ sem_status sem_batch_tune(sem_batch *batch, sem_mesh *const *meshes, int n, void
  * SEM_FP32). */
 sem_status sem_batch_set_epw(sem_batch *batch, int N, int epw);
 sem_status sem_batch_get_epw(const sem_batch *batch, int N, int precision, int *epw);
+/* Workgroups of the batched launches: ax_grid for each order's operator,
+ * vec_grid for the gather-scatter and vector kernels (> 0; 0 restores the
+ * default of 16 per compute unit).  Each persistent workgroup walks the work
+ * table from its index in steps of the grid, so a small grid makes every
+ * workgroup take many (slot, tile) items in turn; results do not depend on it
+ * (each slot's partial sums follow its own items).  The batch must have no
+ * admitted slots (SEM_EINVAL); cached graphs are dropped. */
+sem_status sem_batch_set_grid(sem_batch *batch, int ax_grid, int vec_grid);
+sem_status sem_batch_get_grid(const sem_batch *batch, int *ax_grid, int *vec_grid);
 
 /* One-shot: solve A_i x_i = b_i for i < n together (b_i, x_i device FP64
  * E-vectors of mesh i; opts as for sem_pcg_solve, shared by all; stats: n

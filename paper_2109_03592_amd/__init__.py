@@ -148,20 +148,24 @@ class Mesh:
         """Elements per workgroup and persistent grid size of the operator (0 = default)."""
         L.check(self._lib.sem_set_operator_config(self._h, int(epw), int(grid)), "sem_set_operator_config")
 
-    def set_operator_kernel(self, kind: str):
-        """'column' (lane per (i,j) column) or 'node' (lane per node, N <= 7)."""
-        k = {"column": 0, "node": 1}[kind]
-        L.check(self._lib.sem_set_operator_kernel(self._h, k), "sem_set_operator_kernel")
-
-    def operator_kernel(self) -> str:
-        k = C.c_int()
-        L.check(self._lib.sem_get_operator_kernel(self._h, C.byref(k)), "sem_get_operator_kernel")
-        return ("column", "node")[k.value]
-
     def operator_config(self):
         e, g = C.c_int(), C.c_int()
         L.check(self._lib.sem_get_operator_config(self._h, C.byref(e), C.byref(g)), "sem_get_operator_config")
         return e.value, g.value
+
+    def set_axgs_config(self, enable: bool = True, epw: int = 0, lines_per_wg: int = 0):
+        """Fused operator and gather-scatter: on/off, elements per tile and
+        x-lines per workgroup (0 = automatic)."""
+        L.check(self._lib.sem_set_axgs_config(self._h, int(bool(enable)), int(epw), int(lines_per_wg)),
+                "sem_set_axgs_config")
+
+    def axgs_info(self, dtype=torch.float64) -> dict:
+        """Shape of the fused operator and gather-scatter for a precision
+        (enabled = 0 where the two launches run)."""
+        info = L.AxgsInfo()
+        dt = SEM_FP32 if dtype == torch.float32 else SEM_FP64
+        L.check(self._lib.sem_get_axgs_info(self._h, dt, C.byref(info)), "sem_get_axgs_info")
+        return {k: getattr(info, k) for k, _ in L.AxgsInfo._fields_}
 
     def set_helmholtz(self, h1: Optional[torch.Tensor] = None, h2: Optional[torch.Tensor] = None, stream=None):
         """Helmholtz form h1 (grad, grad) + h2 B of the operator (None: h1 = 1,
@@ -363,6 +367,15 @@ class Batch:
         p = SEM_FP32 if precision == "fp32" else SEM_FP64
         L.check(self._lib.sem_batch_get_epw(self._h, int(N), p, C.byref(e)), "sem_batch_get_epw")
         return e.value
+
+    def set_grid(self, ax_grid: int = 0, vec_grid: int = 0):
+        """Workgroups of the batched operator and vector launches (0 = default)."""
+        L.check(self._lib.sem_batch_set_grid(self._h, int(ax_grid), int(vec_grid)), "sem_batch_set_grid")
+
+    def grid(self):
+        a, v = C.c_int(), C.c_int()
+        L.check(self._lib.sem_batch_get_grid(self._h, C.byref(a), C.byref(v)), "sem_batch_get_grid")
+        return a.value, v.value
 
     def solve(self, meshes, bs, xs=None, stream=None, raise_on_error: bool = True, **kw):
         """Solve A_i x_i = b_i together; returns (xs, [SolveResult])."""

@@ -55,6 +55,11 @@ class CoarseInfo(C.Structure):
                 ("chebyshev_steps", C.c_int), ("a", C.c_double), ("b", C.c_double)]
 
 
+class AxgsInfo(C.Structure):
+    _fields_ = [("enabled", C.c_int), ("epw", C.c_int), ("lines_per_wg", C.c_int), ("y_onchip", C.c_int),
+                ("grid", C.c_int64), ("residual_ids", C.c_int64), ("residual_copies", C.c_int64)]
+
+
 # name -> (restype, argtypes); kept in step with include/sem.h
 _vp, _i, _d = C.c_void_p, C.c_int, C.c_double
 SIGNATURES = {
@@ -72,14 +77,16 @@ SIGNATURES = {
     "sem_set_operator_config": (_i, [_vp, _i, _i]),
     "sem_get_operator_config": (_i, [_vp, C.POINTER(_i), C.POINTER(_i)]),
     "sem_set_helmholtz": (_i, [_vp, _vp, _vp, _vp]),
-    "sem_set_operator_kernel": (_i, [_vp, _i]),
     "sem_set_coarse": (_i, [_vp, _i, _d, _vp]),
     "sem_get_coarse_info": (_i, [_vp, C.POINTER(CoarseInfo)]),
     "sem_precond_apply": (_i, [_vp, _vp, _vp, _vp]),
     "sem_set_schwarz": (_i, [_vp, _i, _vp]),
     "sem_get_schwarz_info": (_i, [_vp, C.POINTER(_i), C.POINTER(C.c_int64)]),
     "sem_host_fdm_1d": (_i, [_i, _d, _i, _i, _vp, _vp, C.POINTER(_i), C.POINTER(_i)]),
-    "sem_get_operator_kernel": (_i, [_vp, C.POINTER(_i)]),
+    "sem_set_axgs_config": (_i, [_vp, _i, _i, _i]),
+    "sem_get_axgs_info": (_i, [_vp, _i, C.POINTER(AxgsInfo)]),
+    "sem_host_axgs_residual": (_i, [C.POINTER(MeshDesc), _i, _i, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                    _vp, _vp]),
     "sem_proj_create": (_i, [_vp, _i, C.POINTER(_vp)]),
     "sem_proj_free": (_i, [_vp]),
     "sem_proj_reset": (_i, [_vp]),
@@ -97,6 +104,8 @@ SIGNATURES = {
     "sem_batch_tune": (_i, [_vp, C.POINTER(_vp), _i, _vp]),
     "sem_batch_set_epw": (_i, [_vp, _i, _i]),
     "sem_batch_get_epw": (_i, [_vp, _i, _i, C.POINTER(_i)]),
+    "sem_batch_set_grid": (_i, [_vp, _i, _i]),
+    "sem_batch_get_grid": (_i, [_vp, C.POINTER(_i), C.POINTER(_i)]),
     "sem_batch_solve": (_i, [_vp, C.POINTER(_vp), _i, C.POINTER(_vp), C.POINTER(_vp), C.POINTER(SolveOpts),
                              _vp, _vp]),
     "sem_batch_admit": (_i, [_vp, _vp, _vp, _vp, C.POINTER(SolveOpts), C.POINTER(_i), _vp]),

@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsem.so")
-SOURCES = ["kernels.hip", "batch.hip", "projection.hip", "coarse.hip", "schwarz.hip", "setup.cpp", "api.cpp", "batch.cpp"]
+SOURCES = ["kernels.hip", "batch.hip", "projection.hip", "coarse.hip", "schwarz.hip", "axgs64.hip", "axgs32.hip",
+           "setup.cpp", "api.cpp", "batch.cpp", "axgs.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 COMMON = [

@@ -9,6 +9,7 @@
 #include <mutex>
 #include <new>
 
+#include "axgs_host.hpp"
 #include "coarse.hpp"
 #include "kernels.hpp"
 #include "schwarz.hpp"
@@ -117,6 +118,7 @@ static void ensure_dtables(hipStream_t s)
     std::vector<float> d32(d64.begin(), d64.end());
     SEM_HIP(upload_dtables(d64.data(), d32.data(), s));
     SEM_HIP(upload_batch_dtables(d64.data(), d32.data(), s));
+    SEM_HIP(upload_axgs_dtables(d64.data(), d32.data(), s));
     SEM_HIP(hipStreamSynchronize(s));
     done[dev] = 1;
 }
@@ -201,7 +203,6 @@ struct Prec<float> {
 template <typename T>
 static int op_epw(const sem_mesh *m)
 {
-    if (m->op_kind == 1) return node_epw(m->h.N);
     return sizeof(T) == 8 ? m->ax_epw : m->ax_epw32;
 }
 
@@ -228,12 +229,11 @@ static int cg_epw(const sem_mesh *m) { return cg_mode<T>(m) > 2 ? column_epw<T>(
 // launches the operator; returns its workgroup count (the number of dot
 // partials of modes 1-5)
 template <typename T>
-static int64_t enqueue_ax(sem_mesh *m, int mode, const T *in, T *out, hipStream_t s)
+static AxParams<T> ax_params(sem_mesh *m, int mode, const T *in, T *out)
 {
     AxParams<T> a{};
     a.E = m->h.E;
     a.epw = mode >= 3 ? column_epw<T>(m) : op_epw<T>(m);
-    a.kind = mode >= 3 ? 0 : m->op_kind;
     a.grid_cap = m->ax_grid_cap;
     a.G = Prec<T>::G(m);
     a.in = in;
@@ -252,6 +252,13 @@ static int64_t enqueue_ax(sem_mesh *m, int mode, const T *in, T *out, hipStream_
         a.z0 = m->coarse->z0;
         a.cq = m->coarse->qw;
     }
+    return a;
+}
+
+template <typename T>
+static int64_t enqueue_ax(sem_mesh *m, int mode, const T *in, T *out, hipStream_t s)
+{
+    AxParams<T> a = ax_params<T>(m, mode, in, out);
     int64_t grid = 0;
     SEM_HIP(launch_ax<T>(m->h.N, mode, a, s, &grid));
     return grid;
@@ -261,6 +268,169 @@ template <typename T>
 static void enqueue_gs(sem_mesh *m, T *v, const PcgState *st, hipStream_t s)
 {
     SEM_HIP(launch_gs<T>(m->gsplan, m->gs_off, m->gs_idx, v, false, st, s));
+}
+
+// --- fused operator and gather-scatter ---------------------------------------
+static void axgs_drop(AxgsShape &sh)
+{
+    if (sh.owns_plan) {
+        hipFree(sh.res_off);
+        hipFree(sh.res_idx);
+    }
+    sh = AxgsShape();
+}
+
+static void axgs_reset(sem_mesh *m)
+{
+    if (!m->axgs) return;
+    // a shape that shares the other's plan goes first
+    for (int q = 0; q < 2; ++q)
+        if (!m->axgs->shape[q].owns_plan) axgs_drop(m->axgs->shape[q]);
+    for (int q = 0; q < 2; ++q) axgs_drop(m->axgs->shape[q]);
+}
+
+// The launch shape and residual plan of precision T (built by
+// axgs_build at set-up and on a change of configuration, never inside a
+// launch sequence, which may be under graph capture); nullptr when the fused
+// kernel does not apply (disabled, order outside its range, no tile fits).
+template <typename T>
+static AxgsShape *axgs_shape(sem_mesh *m)
+{
+    AxgsSpace *A = m->axgs;
+    if (!A || !A->enabled) return nullptr;
+    AxgsShape &sh = A->shape[sizeof(T) == 8 ? 0 : 1];
+    return sh.ready == 1 ? &sh : nullptr;
+}
+
+template <typename T>
+static void axgs_build_shape(sem_mesh *m)
+{
+    AxgsSpace *A = m->axgs;
+    const HostMesh &h = m->h;
+    const int prec = sizeof(T) == 8 ? 0 : 1;
+    AxgsShape &sh = A->shape[prec];
+    if (sh.ready) return;
+    sh.ready = -1;  // not usable unless completed below
+    if (!A->enabled || !axgs_order_supported(h.N)) return;
+    const int P2 = h.P * h.P;
+    const size_t elem = sizeof(T);
+    int dev = 0, cus = 0, lds_cap = 0;
+    SEM_HIP(hipGetDevice(&dev));
+    SEM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    SEM_HIP(hipDeviceGetAttribute(&lds_cap, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    const size_t lds_limit = (size_t)lds_cap - 4096;  // static LDS of the kernel
+    // elements per tile: the count that keeps the most waves resident (then
+    // the fuller waves, then the smaller count), with or without the y line
+    // buffer
+    auto pick = [&](bool yon, int &best_e, int &best_blocks) {
+        best_e = 0;
+        best_blocks = 0;
+        double best_score = -1.0;
+        for (int e = 1; e * P2 <= 512; ++e) {
+            if (A->req_epw && e != A->req_epw) continue;
+            const size_t lds = axgs_lds_bytes(h.N, e, h.nel[0], yon, elem);
+            if (lds > lds_limit) continue;
+            const int blocks = axgs_blocks_per_cu<T>(h.N, 2, m->helm != 0, e, lds);
+            if (blocks < 1) continue;
+            const int lanes = e * P2, waves = (lanes + 63) / 64;
+            const double score = (double)blocks * waves + (double)lanes / (waves * 64) * 1e-3;
+            if (score > best_score + 1e-9) {
+                best_score = score;
+                best_e = e;
+                best_blocks = blocks;
+            }
+        }
+    };
+    const int64_t n_lines = (int64_t)h.nel[1] * h.nel[2];
+    const int64_t cap = m->n_partials - 64;
+    // one line per workgroup leaves no y-face to sum on-chip: no line buffer
+    bool best_y = A->req_lines != 1 && h.nel[1] > 1;
+    int best_e = 0, best_blocks = 0;
+    if (best_y) pick(true, best_e, best_blocks);
+    if (best_e == 0) {
+        best_y = false;
+        pick(false, best_e, best_blocks);
+    }
+    if (best_e == 0) return;  // no tile shape fits the LDS
+    int Lw = A->req_lines ? A->req_lines : axgs_pick_lines(n_lines, (int64_t)best_blocks * cus, cap);
+    if (Lw == 1 && best_y) {
+        best_y = false;
+        pick(false, best_e, best_blocks);
+        if (best_e == 0) return;
+    }
+    if ((n_lines + Lw - 1) / Lw > cap) fail(SEM_EINVAL, "fused operator: more workgroups than dot partials");
+    sh.epw = best_e;
+    sh.lines_per_wg = Lw;
+    sh.y_onchip = best_y ? 1 : 0;
+    sh.grid = (n_lines + Lw - 1) / Lw;
+    sh.L = axgs_lattice(h, best_e, Lw, best_y);
+    const AxgsShape &other = A->shape[1 - prec];
+    if (other.ready == 1 && other.lines_per_wg == Lw && other.y_onchip == sh.y_onchip) {
+        sh.res = other.res;
+        sh.res_copies = other.res_copies;
+        sh.res_off = other.res_off;
+        sh.res_idx = other.res_idx;
+        sh.owns_plan = false;
+    } else {
+        std::vector<int32_t> off, idx;
+        axgs_residual_plan(h, Lw, best_y, off, idx);
+        sh.res.n_sum = sh.res.n_ids = (int64_t)off.size() - 1;
+        sh.res_copies = (int64_t)idx.size();
+        SEM_HIP(hipMalloc((void **)&sh.res_off, sizeof(int32_t) * off.size()));
+        sh.owns_plan = true;
+        if (hipMalloc((void **)&sh.res_idx, sizeof(int32_t) * std::max<size_t>(idx.size(), 1)) != hipSuccess) {
+            hipFree(sh.res_off);
+            sh = AxgsShape();
+            fail(SEM_ENOMEM, "fused operator: residual plan");
+        }
+        hipStream_t s = nullptr;
+        SEM_HIP(hipMemcpyAsync(sh.res_off, off.data(), sizeof(int32_t) * off.size(), hipMemcpyHostToDevice, s));
+        if (!idx.empty())
+            SEM_HIP(hipMemcpyAsync(sh.res_idx, idx.data(), sizeof(int32_t) * idx.size(), hipMemcpyHostToDevice, s));
+        SEM_HIP(hipStreamSynchronize(s));
+    }
+    sh.ready = 1;
+}
+
+// both precisions' shapes (FP32 with the FP32 copies)
+static void axgs_build(sem_mesh *m)
+{
+    if (!m->axgs) return;
+    axgs_build_shape<double>(m);
+    if (m->with_fp32) axgs_build_shape<float>(m);
+}
+
+// The fused kernel (modes 0 and 2); returns its workgroup count (the dot
+// partials of mode 2).  The residual gather-scatter follows with enqueue_axgs_rest.
+template <typename T>
+static int64_t enqueue_axgs_fused(sem_mesh *m, AxgsShape &sh, int mode, const T *in, T *out, hipStream_t s)
+{
+    AxParams<T> a = ax_params<T>(m, mode, in, out);
+    a.epw = sh.epw;
+    a.grid_cap = (int)std::min<int64_t>(m->n_partials - 64, INT32_MAX);
+    int64_t grid = 0;
+    SEM_HIP(launch_axgs<T>(m->h.N, mode, a, sh.L, s, &grid));
+    return grid;
+}
+
+template <typename T>
+static void enqueue_axgs_rest(AxgsShape &sh, T *out, const PcgState *st, hipStream_t s)
+{
+    SEM_HIP(launch_gs<T>(sh.res, sh.res_off, sh.res_idx, out, false, st, s));
+}
+
+// w = mask(Q Q^T A_L u): the fused kernel and its residual plan where it
+// applies, else the operator and the full gather-scatter
+template <typename T>
+static void enqueue_ax_gs(sem_mesh *m, const T *in, T *out, hipStream_t s)
+{
+    if (AxgsShape *sh = axgs_shape<T>(m)) {
+        enqueue_axgs_fused<T>(m, *sh, 0, in, out, s);
+        enqueue_axgs_rest<T>(*sh, out, nullptr, s);
+        return;
+    }
+    enqueue_ax<T>(m, 0, in, out, s);
+    enqueue_gs<T>(m, out, nullptr, s);
 }
 
 // Per-kernel-class timing with HIP events recorded on the launch stream.
@@ -313,11 +483,20 @@ static void enqueue_iterations(sem_mesh *m, int k, hipStream_t s, Profiler *prof
     const T *jinv = schwarz ? nullptr : Prec<T>::inv(m);
     T *zs = nullptr;
     if constexpr (sizeof(T) == 8) zs = schwarz ? m->schwarz->zs : nullptr;
+    // the Jacobi iteration runs the fused operator and gather-scatter where it applies
+    AxgsShape *fused = mode == 2 ? axgs_shape<T>(m) : nullptr;
     for (int it = 0; it < k; ++it) {
         if (prof) prof->mark(s);
-        const int64_t axb = enqueue_ax<T>(m, mode, schwarz ? zs : Prec<T>::r(m), Prec<T>::w(m), s);
-        if (prof) prof->mark(s);
-        enqueue_gs<T>(m, Prec<T>::w(m), st, s);
+        int64_t axb = 0;
+        if (fused) {
+            axb = enqueue_axgs_fused<T>(m, *fused, 2, Prec<T>::r(m), Prec<T>::w(m), s);
+            if (prof) prof->mark(s);
+            enqueue_axgs_rest<T>(*fused, Prec<T>::w(m), st, s);
+        } else {
+            axb = enqueue_ax<T>(m, mode, schwarz ? zs : Prec<T>::r(m), Prec<T>::w(m), s);
+            if (prof) prof->mark(s);
+            enqueue_gs<T>(m, Prec<T>::w(m), st, s);
+        }
         if (prof) prof->mark(s);
         SEM_HIP(launch_reduce_sigma(m->partials, axb, st, s));
         int64_t pairs = ub;
@@ -353,7 +532,7 @@ static void run_iterations(sem_mesh *m, int k, bool use_graph, hipStream_t s, Pr
     }
     const int slot = sizeof(T) == 8 ? 0 : 1;
     // graph key: tile shape and kernel (a change of the coarse space drops the graphs)
-    const int epw = cg_epw<T>(m) + 1024 * (coarse_cg<T>(m) ? 2 : m->op_kind);
+    const int epw = cg_epw<T>(m) + 1024 * (coarse_cg<T>(m) ? 2 : 0);
     if (!m->graph[slot] || m->graph_k[slot] != k || m->graph_epw[slot] != epw ||
         m->graph_grid[slot] != m->ax_grid_cap) {
         if (m->graph[slot]) {
@@ -425,8 +604,7 @@ static double read_scalar(const double *d, hipStream_t s)
 // r = b - A x (FP64), then rr = <r, r> into scal[slot]
 static void true_residual(sem_mesh *m, const double *b, hipStream_t s, int slot)
 {
-    enqueue_ax<double>(m, 0, m->x64, m->w64, s);
-    enqueue_gs<double>(m, m->w64, nullptr, s);
+    enqueue_ax_gs<double>(m, m->x64, m->w64, s);
     SEM_HIP(launch_residual(m->h.nL, b, m->w64, m->r64, s));
     SEM_HIP(launch_dot_unique<double>(m->h.nL, m->r64, m->r64, m->mult, m->partials, m->scal + slot, s));
 }
@@ -670,6 +848,7 @@ sem_status sem_setup(const sem_mesh_desc *desc, void *stream, sem_mesh **out)
             m->with_fp32 = (desc->precision_flags & SEM_WITH_FP32) ? 1 : 0;
             m->ax_epw = default_epw(h.N);
             m->ax_epw32 = default_epw(h.N, true);
+            m->axgs = new AxgsSpace();
             const int64_t nL = h.nL;
             ensure_dtables(s);
             m->G64 = dalloc<double>(m, 6 * nL);
@@ -708,6 +887,7 @@ sem_status sem_setup(const sem_mesh_desc *desc, void *stream, sem_mesh **out)
             }
             SEM_HIP(hipMemsetAsync(m->state, 0, 2 * sizeof(PcgState), s));
             SEM_HIP(hipStreamSynchronize(s));
+            axgs_build(m);
             // the device holds these now; keep only what exports need
             std::vector<double>().swap(h.G);
             std::vector<double>().swap(h.B);
@@ -730,6 +910,8 @@ sem_status sem_free(sem_mesh *m)
     if (m->capture_stream) hipStreamDestroy(m->capture_stream);
     coarse_free(m->coarse);
     schwarz_free(m->schwarz);
+    axgs_reset(m);
+    delete m->axgs;
     for (hipEvent_t e : m->events) hipEventDestroy(e);
     for (void *p : m->allocations) hipFree(p);
     delete m;
@@ -913,27 +1095,6 @@ sem_status sem_set_operator_config(sem_mesh *m, int epw, int grid)
     });
 }
 
-sem_status sem_set_operator_kernel(sem_mesh *m, int kind)
-{
-    return guarded([&]() -> sem_status {
-        if (!m) fail(SEM_EINVAL, "sem_set_operator_kernel: null mesh");
-        if (kind != SEM_OPK_COLUMN && kind != SEM_OPK_NODE) fail(SEM_EINVAL, "sem_set_operator_kernel: unknown kind");
-        if (kind == SEM_OPK_NODE && m->h.N > kMaxNodeOrder)
-            fail(SEM_EINVAL, "sem_set_operator_kernel: the lane-per-node operator takes N <= 7");
-        m->op_kind = kind;
-        return SEM_OK;
-    });
-}
-
-sem_status sem_get_operator_kernel(const sem_mesh *m, int *kind)
-{
-    return guarded([&]() -> sem_status {
-        if (!m || !kind) fail(SEM_EINVAL, "sem_get_operator_kernel: null argument");
-        *kind = m->op_kind;
-        return SEM_OK;
-    });
-}
-
 sem_status sem_get_operator_config(const sem_mesh *m, int *epw, int *grid)
 {
     return guarded([&]() -> sem_status {
@@ -1027,9 +1188,74 @@ sem_status sem_gs(sem_mesh *m, int dtype, void *v, void *stream)
 
 sem_status sem_axgs(sem_mesh *m, int dtype, const void *u, void *w, void *stream)
 {
-    sem_status st = sem_ax(m, dtype, u, w, nullptr, stream);
-    if (st != SEM_OK) return st;
-    return sem_gs(m, dtype, w, stream);
+    return guarded([&]() -> sem_status {
+        if (!m || !u || !w) fail(SEM_EINVAL, "sem_axgs: null argument");
+        if (u == w) fail(SEM_EINVAL, "sem_axgs: u and w must not overlap");
+        check_dtype(m, dtype);
+        hipStream_t s = (hipStream_t)stream;
+        if (dtype == SEM_FP64) enqueue_ax_gs<double>(m, (const double *)u, (double *)w, s);
+        else enqueue_ax_gs<float>(m, (const float *)u, (float *)w, s);
+        return SEM_OK;
+    });
+}
+
+sem_status sem_set_axgs_config(sem_mesh *m, int enable, int epw, int lines_per_wg)
+{
+    return guarded([&]() -> sem_status {
+        if (!m || !m->axgs) fail(SEM_EINVAL, "sem_set_axgs_config: null mesh");
+        if (enable != 0 && enable != 1) fail(SEM_EINVAL, "sem_set_axgs_config: enable must be 0 or 1");
+        if (epw < 0 || lines_per_wg < 0) fail(SEM_EINVAL, "sem_set_axgs_config: negative count");
+        if (epw * m->h.P * m->h.P > 512) fail(SEM_EINVAL, "sem_set_axgs_config: epw (N+1)^2 > 512");
+        const int64_t n_lines = (int64_t)m->h.nel[1] * m->h.nel[2];
+        if (lines_per_wg > 0 && (n_lines + lines_per_wg - 1) / lines_per_wg > m->n_partials - 64)
+            fail(SEM_EINVAL, "sem_set_axgs_config: more workgroups than dot partials");
+        SEM_HIP(hipDeviceSynchronize());  // launches in flight may still read the residual plans
+        drop_graphs(m, nullptr);
+        axgs_reset(m);
+        m->axgs->enabled = enable;
+        m->axgs->req_epw = epw;
+        m->axgs->req_lines = lines_per_wg;
+        axgs_build(m);
+        return SEM_OK;
+    });
+}
+
+sem_status sem_host_axgs_residual(const sem_mesh_desc *desc, int lines_per_wg, int y_onchip, int64_t *n_ids,
+                                  int64_t *n_copies, int32_t *off, int32_t *idx)
+{
+    return guarded([&]() -> sem_status {
+        if (!desc || !n_ids || !n_copies || lines_per_wg < 1 || (y_onchip != 0 && y_onchip != 1))
+            fail(SEM_EINVAL, "sem_host_axgs_residual: bad arguments");
+        HostMesh h;
+        build_host_mesh(*desc, h);
+        h.desc = *desc;
+        std::vector<int32_t> o, x;
+        axgs_residual_plan(h, lines_per_wg, y_onchip != 0, o, x);
+        *n_ids = (int64_t)o.size() - 1;
+        *n_copies = (int64_t)x.size();
+        if (off) std::memcpy(off, o.data(), sizeof(int32_t) * o.size());
+        if (idx && !x.empty()) std::memcpy(idx, x.data(), sizeof(int32_t) * x.size());
+        return SEM_OK;
+    });
+}
+
+sem_status sem_get_axgs_info(sem_mesh *m, int dtype, sem_axgs_info *info)
+{
+    return guarded([&]() -> sem_status {
+        if (!m || !info || !m->axgs) fail(SEM_EINVAL, "sem_get_axgs_info: null argument");
+        check_dtype(m, dtype);
+        std::memset(info, 0, sizeof(*info));
+        AxgsShape *sh = dtype == SEM_FP64 ? axgs_shape<double>(m) : axgs_shape<float>(m);
+        if (!sh) return SEM_OK;
+        info->enabled = 1;
+        info->epw = sh->epw;
+        info->lines_per_wg = sh->lines_per_wg;
+        info->y_onchip = sh->y_onchip;
+        info->grid = sh->grid;
+        info->residual_ids = sh->res.n_ids;
+        info->residual_copies = sh->res_copies;
+        return SEM_OK;
+    });
 }
 
 sem_status sem_mass(sem_mesh *m, const double *f, double *b, void *stream)

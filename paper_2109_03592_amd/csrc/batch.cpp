@@ -916,6 +916,34 @@ sem_status sem_batch_set_epw(sem_batch *B, int N, int epw)
     });
 }
 
+sem_status sem_batch_set_grid(sem_batch *B, int ax_grid, int vec_grid)
+{
+    return bguard([&]() -> sem_status {
+        if (!B || ax_grid < 0 || vec_grid < 0) fail(SEM_EINVAL, "sem_batch_set_grid: bad arguments");
+        for (int id = 0; id < B->max_slots; ++id)
+            if (B->slots[id].phase != PH_FREE) fail(SEM_EINVAL, "sem_batch_set_grid: the batch must be empty");
+        const int cap = persistent_grid_cap_public();
+        B->L.ax_grid = ax_grid > 0 ? ax_grid : cap;
+        B->L.vec_grid = vec_grid > 0 ? vec_grid : cap;
+        for (Group *g : {&B->g64, &B->g32, &B->gres})
+            if (g->graph) {
+                hipGraphExecDestroy(g->graph);
+                g->graph = nullptr;
+            }
+        return SEM_OK;
+    });
+}
+
+sem_status sem_batch_get_grid(const sem_batch *B, int *ax_grid, int *vec_grid)
+{
+    return bguard([&]() -> sem_status {
+        if (!B || !ax_grid || !vec_grid) fail(SEM_EINVAL, "sem_batch_get_grid: bad arguments");
+        *ax_grid = B->L.ax_grid;
+        *vec_grid = B->L.vec_grid;
+        return SEM_OK;
+    });
+}
+
 sem_status sem_batch_get_epw(const sem_batch *B, int N, int precision, int *epw)
 {
     return bguard([&]() -> sem_status {

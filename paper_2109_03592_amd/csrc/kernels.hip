@@ -108,47 +108,6 @@ __global__ __launch_bounds__(512) void ax_kernel(AxParams<T> a)
     }
 }
 
-// Lane per node: each workgroup walks tiles of epw elements (epw (N+1)^3
-// lanes); the same persistent walk and partials as ax_kernel.
-template <typename T, int N, int MODE, bool HELM>
-__global__ __launch_bounds__(512) void ax_node_kernel(AxParams<T> a)
-{
-    constexpr int P = N + 1, P2 = P * P, P3 = P2 * P;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *sm = reinterpret_cast<T *>(smem_raw);
-    __shared__ T sD[P2];
-
-    if (MODE == 2 && a.st->done) return;
-
-    const int tid = threadIdx.x;
-    const int el = tid / P3;
-    const int pt = tid - el * P3;
-    const int i = pt % P, j = (pt / P) % P, k = pt / P2;
-    const bool inblk = el < a.epw;
-    T *su = sm + (size_t)(inblk ? el : a.epw - 1) * 4 * P3;
-    const T *__restrict__ D = dtable<T>(N);
-    for (int q = tid; q < P2; q += blockDim.x) sD[q] = D[q];
-    NodeRows<T, N> R;
-    R.load(D, i, j, k);
-    T beta = 0, alpha = 0;
-    if (MODE == 2) {
-        beta = (T)a.st->beta;
-        alpha = (T)a.st->alpha;
-    }
-    double dot = 0.0;
-    const int64_t ntiles = (a.E + a.epw - 1) / a.epw;
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const int64_t e = tile * a.epw + el;
-        const bool active = inblk && e < a.E;
-        ax_node_tile<T, N, MODE, HELM>(R, sD, su, e, active, inblk, i, j, k, a.G, a.in, a.out, a.invdiag, a.p, beta,
-                                       a.x, alpha, dot, a.h1, a.h2b);
-    }
-    if (MODE != 0) {
-        double v[1] = {dot};
-        block_reduce_store<1>(v, a.partial, 1);
-    }
-}
-
 // ---------------------------------------------------------------------------
 // Gather-scatter from the plan sorted by global id (lattice order, so that
 // neighbouring lanes touch neighbouring rows of neighbouring elements).  One
@@ -567,56 +526,11 @@ static size_t max_dynamic_lds()
     return (size_t)v - 4096;  // static LDS of the kernel (reduction, D copy)
 }
 
-int node_epw(int N)
-{
-    const int P3 = (N + 1) * (N + 1) * (N + 1);
-    int best = 1;
-    double best_fill = 0.0;
-    for (int epw = 1; epw * P3 <= 512; ++epw) {
-        const int t = epw * P3, tr = (t + 63) / 64 * 64;
-        const double fill = (double)t / tr;
-        if (fill > best_fill + 0.005) {
-            best_fill = fill;
-            best = epw;
-        }
-    }
-    return best;
-}
-
-template <typename T, int MODE, bool HELM>
-static hipError_t launch_ax_node(int N, const AxParams<T> &a, hipStream_t s, int64_t *grid)
-{
-    const int P3 = (N + 1) * (N + 1) * (N + 1);
-    const int threads = (a.epw * P3 + 63) / 64 * 64;
-    const size_t lds = (size_t)a.epw * 4 * P3 * sizeof(T);
-    const int64_t tiles = (a.E + a.epw - 1) / a.epw;
-    int64_t blocks = 0;
-    if (N > kMaxNodeOrder || threads > 512 || tiles < 1 || a.grid_cap < 1) return hipErrorInvalidConfiguration;
-    switch (N) {
-#define SEM_NODE_CASE(n)                                                                                          \
-    case n:                                                                                                       \
-        blocks = resident_grid(reinterpret_cast<const void *>(&ax_node_kernel<T, n, MODE, HELM>), threads, lds,   \
-                               tiles, a.grid_cap, false);                                                         \
-        hipLaunchKernelGGL((ax_node_kernel<T, n, MODE, HELM>), dim3((unsigned)blocks), dim3(threads), lds, s, a); \
-        break;
-        SEM_NODE_CASE(1) SEM_NODE_CASE(2) SEM_NODE_CASE(3) SEM_NODE_CASE(4) SEM_NODE_CASE(5) SEM_NODE_CASE(6)
-        SEM_NODE_CASE(7)
-#undef SEM_NODE_CASE
-    default: return hipErrorInvalidValue;
-    }
-    if (grid) *grid = blocks;
-    return hipGetLastError();
-}
-
 template <typename T, int MODE, bool HELM>
 static hipError_t launch_ax_mode(int N, const AxParams<T> &a, hipStream_t s, int64_t *grid)
 {
-    if constexpr (MODE >= 3) {
-        // the coarse correction and a given residual run in the column kernel only
-        if (a.kind != 0) return hipErrorInvalidValue;
-        if ((MODE == 3 || MODE == 5) && (!a.evert || !a.z0 || !a.cq)) return hipErrorInvalidValue;
-    } else {
-        if (a.kind == 1) return launch_ax_node<T, MODE, HELM>(N, a, s, grid);
+    if constexpr (MODE == 3 || MODE == 5) {
+        if (!a.evert || !a.z0 || !a.cq) return hipErrorInvalidValue;
     }
     static const size_t lds_cap = max_dynamic_lds();
     const int threads = ax_block_threads(N, a.epw);

@@ -37,16 +37,13 @@ struct AxParams {
     const PcgState *st;    // mode 2: alpha, beta and the done flag
     const T *h1;           // Helmholtz: h1 per local point (nullptr: Poisson)
     const T *h2b;          // Helmholtz: h2*B per local point (with h1)
-    int kind;              // 0: lane per (i,j) column; 1: lane per node (N <= 7)
     // mode 3: mode 2 plus the coarse correction in the prologue (FP64 coarse data)
     const int32_t *evert;  // [E][8] vertex of each element corner
     const double *z0;      // coarse solution per vertex
     const double *cq;      // [2][N+1] 1-D hat weights at the GLL nodes
 };
 
-constexpr int kMaxNodeOrder = 7;   // the lane-per-node operator: (N+1)^3 <= 512
 constexpr int kMaxPrecondOrder = 12;  // the coarse term, the Schwarz local solves and modes 3-5
-int node_epw(int N);              // elements per workgroup of the lane-per-node operator
 
 int ax_block_threads(int N, int epw);
 size_t ax_lds_bytes(int N, int epw, size_t elem);

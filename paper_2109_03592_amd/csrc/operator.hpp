@@ -5,6 +5,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace sem {
@@ -266,13 +268,21 @@ struct ColumnIndex {
 // caller).
 // MODE 4 (CG with a preconditioned residual given, e.g. by the Schwarz local
 // solves): p <- in + beta*p.  MODE 5: MODE 4 plus the coarse correction.
-template <typename T, int N, int MODE, int LAYOUT = 0, bool HELM = false>
+// Sink: with a callable other than NoSink, each output w(i,j,k) of the lane
+// goes to sink(k, w) as it is formed instead of to `out`, and the tile ends
+// without the trailing barrier (the caller's epilogue barrier orders the LDS
+// reuse).
+struct NoSink {
+    template <typename T>
+    __device__ void operator()(int, T) const {}
+};
+template <typename T, int N, int MODE, int LAYOUT = 0, bool HELM = false, typename Sink = NoSink>
 __device__ inline void ax_tile(const LaneRows<T, N> &R, const T *__restrict__ D, T *su, int64_t e, bool active,
                                bool inblk, int i, int j, const T *__restrict__ G, const T *__restrict__ in,
                                T *__restrict__ out, const T *__restrict__ invdiag, T *__restrict__ p, T beta,
                                T *__restrict__ x, T alpha, double &dot, const T *__restrict__ h1 = nullptr,
                                const T *__restrict__ h2b = nullptr, const double *zcl = nullptr,
-                               const double *__restrict__ cq = nullptr)
+                               const double *__restrict__ cq = nullptr, const Sink &sink = Sink())
 {
     constexpr int P = N + 1, P2 = P * P, P3 = P2 * P;
     T *sr = su + P3;
@@ -363,103 +373,13 @@ __device__ inline void ax_tile(const LaneRows<T, N> &R, const T *__restrict__ D,
         for (int l = 0; l < P; ++l)
             acc += R.dti(l) * sr[k * P2 + j * P + l] + R.dtj(l) * ss[k * P2 + l * P + i] + R.dk(D, l, k) * wt[l];
         if (HELM && active) acc += ld_stream(h2b + eb + ci.off(k)) * uc[k];
-        if (active) st_stream(acc, out + eb + ci.off(k));
+        constexpr bool kSink = !std::is_same<Sink, NoSink>::value;
+        if constexpr (kSink) sink(k, acc);
+        else if (active) st_stream(acc, out + eb + ci.off(k));
         if (MODE != 0) dot += (double)uc[k] * (double)acc;
     }
-    __syncthreads();  // the LDS slot is rewritten by the next tile
+    if constexpr (std::is_same<Sink, NoSink>::value) __syncthreads();  // the LDS slot is rewritten by the next tile
 }
 
-
-// ---------------------------------------------------------------------------
-// Local operator, one lane per node (the paper's thread layout): lane (el,
-// i, j, k) owns node (i,j,k) of element tile*epw + el.  The element and the
-// three weighted derivatives live in LDS (4 (N+1)^3 values per element); the
-// lane's rows D[i][.], D[j][.], D[k][.] sit in VGPRs, the columns come from
-// the LDS copy sD of D.  Few registers per lane, so many waves per SIMD hide
-// the HBM latency.  Same MODE/HELM meaning as ax_tile; every vector access is
-// one coalesced load or store per lane.  The caller ends each tile's work
-// with the barrier inside (the LDS of a tile is reused by the next).
-template <typename T, int N>
-struct NodeRows {
-    static constexpr int P = N + 1;
-    T Di[P], Dj[P], Dk[P];
-    __device__ inline void load(const T *__restrict__ D, int i, int j, int k)
-    {
-#pragma unroll
-        for (int l = 0; l < P; ++l) {
-            Di[l] = D[i * P + l];
-            Dj[l] = D[j * P + l];
-            Dk[l] = D[k * P + l];
-        }
-    }
-};
-
-template <typename T, int N, int MODE, bool HELM>
-__device__ inline void ax_node_tile(const NodeRows<T, N> &R, const T *__restrict__ sD, T *su, int64_t e, bool active,
-                                    bool inblk, int i, int j, int k, const T *__restrict__ G, const T *__restrict__ in,
-                                    T *__restrict__ out, const T *__restrict__ invdiag, T *__restrict__ p, T beta,
-                                    T *__restrict__ x, T alpha, double &dot, const T *__restrict__ h1,
-                                    const T *__restrict__ h2b)
-{
-    constexpr int P = N + 1, P2 = P * P, P3 = P2 * P;
-    T *sr = su + P3;
-    T *ss = sr + P3;
-    T *st = ss + P3;
-    const int pt = i + P * j + P2 * k;
-    const int64_t o = (active ? e : 0) * P3 + pt;
-    T v = 0;
-    if (active) {
-        if (MODE == 2) {
-            const T pold = ld_stream(p + o);
-            // the previous iteration's x step, deferred to here where p is read anyway
-            st_stream(ld_stream(x + o) + alpha * pold, x + o);
-            v = ld_stream(invdiag + o) * ld_stream(in + o) + beta * pold;
-            st_stream(v, p + o);
-        } else {
-            v = ld_stream(in + o);
-        }
-    }
-    if (inblk) su[pt] = v;
-    T g1 = 0, g2 = 0, g3 = 0, g4 = 0, g5 = 0, g6 = 0, h = 0;
-    if (active) {
-        const T *g = G + (active ? e : 0) * 6 * P3 + pt;
-        g1 = ld_stream(g + 0 * P3); g2 = ld_stream(g + 1 * P3); g3 = ld_stream(g + 2 * P3);
-        g4 = ld_stream(g + 3 * P3); g5 = ld_stream(g + 4 * P3); g6 = ld_stream(g + 5 * P3);
-        if (HELM) h = ld_stream(h1 + o);
-    }
-    __syncthreads();
-    T ur = 0, us = 0, ut = 0;
-#pragma unroll
-    for (int l = 0; l < P; ++l) {
-        ur += R.Di[l] * su[l + P * j + P2 * k];
-        us += R.Dj[l] * su[i + P * l + P2 * k];
-        ut += R.Dk[l] * su[i + P * j + P2 * l];
-    }
-    T wr = g1 * ur + g4 * us + g5 * ut;
-    T ws = g2 * us + g4 * ur + g6 * ut;
-    T wt = g3 * ut + g5 * ur + g6 * us;
-    if (HELM) {
-        wr *= h;
-        ws *= h;
-        wt *= h;
-    }
-    if (inblk) {
-        sr[pt] = wr;
-        ss[pt] = ws;
-        st[pt] = wt;
-    }
-    __syncthreads();
-    T acc = 0;
-#pragma unroll
-    for (int l = 0; l < P; ++l)
-        acc += sD[l * P + i] * sr[l + P * j + P2 * k] + sD[l * P + j] * ss[i + P * l + P2 * k] +
-               sD[l * P + k] * st[i + P * j + P2 * l];
-    if (active) {
-        if (HELM) acc += ld_stream(h2b + o) * v;
-        st_stream(acc, out + o);
-    }
-    if (MODE != 0) dot += (double)v * (double)acc;
-    __syncthreads();  // the LDS of this tile is rewritten by the next
-}
 
 }  // namespace sem

@@ -84,6 +84,7 @@ struct DeviceBuf {
 
 struct CoarseSpace;   // coarse.hpp
 struct SchwarzSpace;  // schwarz.hpp
+struct AxgsSpace;     // axgs_host.hpp
 
 }  // namespace sem
 
@@ -112,6 +113,8 @@ struct sem_mesh {
     sem::CoarseSpace *coarse = nullptr;
     // overlapping Schwarz local solves in place of Jacobi (sem_set_schwarz, FP64 solves)
     sem::SchwarzSpace *schwarz = nullptr;
+    // fused operator and gather-scatter (sem_set_axgs_config); created at set-up
+    sem::AxgsSpace *axgs = nullptr;
     // Krylov work space, allocated on the first solve
     double *x64 = nullptr, *r64 = nullptr, *p64 = nullptr, *w64 = nullptr;
     float *x32 = nullptr, *r32 = nullptr, *p32 = nullptr, *w32 = nullptr;
@@ -121,7 +124,6 @@ struct sem_mesh {
     double *scal = nullptr;          // small device scratch for norms
     int ax_epw = 1;                  // elements per workgroup of the FP64 operator
     int ax_epw32 = 1;                // ... of the FP32 operator
-    int op_kind = 0;                 // 0: lane per (i,j) column, 1: lane per node (N <= 7)
     int ax_grid_cap = 4096;          // persistent operator grid
     std::vector<hipEvent_t> events;  // profiling event pool
     hipStream_t capture_stream = nullptr;

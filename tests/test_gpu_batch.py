@@ -70,6 +70,77 @@ def test_batch_alone_vs_mixed_bitwise(semlib, cases):
     B.close()
 
 
+@pytest.mark.parametrize("grid", [1, 3, 7])
+def test_batch_multi_item_walks(semlib, cases, grid):
+    """With 1, 3 or 7 persistent workgroups every workgroup walks many
+    (slot, tile) items of several slots and orders in turn (the path of every
+    launch on large batches): each slot still meets the oracle's true
+    residual and keeps the bits of its alone-solve at the default grid."""
+    print(f"case: batch multi-item walks, grid {grid}", flush=True)
+    B = semlib.Batch(max_slots=16)
+    meshes = [c[0] for c in cases]
+    bs = [torch.from_numpy(c[2]).cuda() for c in cases]
+    alone = {}
+    for prec in ("fp64", "mixed"):
+        for k in (0, 2, 3):
+            (xa,), (ra,) = B.solve([meshes[k]], [bs[k]], tol=1e-10, precision=prec)
+            alone[(prec, k)] = (xa.clone(), ra.iterations)
+    B.set_grid(grid, grid)
+    assert B.grid() == (grid, grid)
+    for prec in ("fp64", "mixed"):
+        xs, res = B.solve(meshes, bs, tol=1e-10, precision=prec, poll_every=8)
+        for (m, om, b), x, r in zip(cases, xs, res):
+            rel = om.true_residual(b, x.cpu().numpy())
+            assert r.ok and rel <= 1e-10, (grid, prec, m.N, m.E, rel)
+        for k in (0, 2, 3):
+            xa, ia = alone[(prec, k)]
+            assert torch.equal(xs[k], xa) and res[k].iterations == ia, (grid, prec, k)
+    B.set_grid(0, 0)
+    B.close()
+
+
+@pytest.mark.timeout(900)
+def test_batch_64_meshes(semlib, oracle_mod):
+    """The batched workload at its real size: 64 jittered boxes (seeds
+    100..163, E log-uniform in [8, 4096], N in {5, 7, 9}), after the autotuner,
+    FP64 and mixed.  Every slot's solution meets the oracle's true residual,
+    and the largest slots of each order keep the bits of their alone-solves."""
+    cases64 = SI.batched_box_cases(64)
+    print(f"case: batch 64 meshes, {sum(c.E for c in cases64)} elements", flush=True)
+    meshes, oms, bh, bs = [], [], [], []
+    for c in cases64:
+        V = SI.jittered_box_vertices(c.nel, seed=c.seed)
+        meshes.append(semlib.box_mesh(c.N, c.nel, vertices=V, with_fp32=True))
+        om = oracle_mod.OracleMesh(c.N, c.nel, vertices=V)
+        x, y, z = om.coords()
+        b = om.mass(SI.sin3_forcing(x, y, z))
+        oms.append(om)
+        bh.append(b)
+        bs.append(torch.from_numpy(b).cuda())
+    B = semlib.Batch(max_slots=64)
+    B.tune(meshes)
+    picks = []
+    for N in (5, 7, 9):
+        ks = [k for k, c in enumerate(cases64) if c.N == N]
+        if ks:
+            picks.append(max(ks, key=lambda k: cases64[k].E))
+    for prec in ("fp64", "mixed"):
+        print(f"case: batch 64 meshes {prec}", flush=True)
+        xs, res = B.solve(meshes, bs, tol=1e-10, precision=prec, poll_every=16)
+        worst = 0.0
+        for k, (om, b, x, r) in enumerate(zip(oms, bh, xs, res)):
+            rel = om.true_residual(b, x.cpu().numpy())
+            worst = max(worst, rel)
+            assert r.ok and rel <= 1e-10, (prec, k, cases64[k], rel)
+        print(f"  {prec}: worst oracle residual {worst:.2e}", flush=True)
+        for k in picks:
+            (xa,), (ra,) = B.solve([meshes[k]], [bs[k]], tol=1e-10, precision=prec, poll_every=16)
+            assert torch.equal(xs[k], xa) and res[k].iterations == ra.iterations, (prec, k)
+    B.close()
+    for m in meshes:
+        m.close()
+
+
 def test_continuous_batching(semlib, cases, oracle_mod):
     """Slots admitted while others run: each result equals its alone-solve bit for bit."""
     print("case: continuous batching", flush=True)

@@ -4,7 +4,11 @@ nodes) in the launch configuration the benchmark uses.
   * maps and multiplicities bit-exact against the oracle's numbering;
   * gather-scatter bit-exact against the oracle on identical input;
   * operator on sampled elements (including the columns at the square's
-    corners) against the oracle's element-local operator;
+    corners) against the oracle's element-local operator, on the library's
+    geometry (1e-10 next to the corners, where the two FP64 geometries
+    differ by rounding) and on the oracle's own factors (1e-12 everywhere);
+  * Ax+gs (two launches, and fused) on the whole mesh against the oracle's
+    assembled apply;
   * FP64 and mixed solves on the oracle's own geometric factors (loaded
     through sem_load_geometry), whose true residual the oracle measures on
     the whole mesh.
@@ -76,13 +80,63 @@ def test_full_ax_sampled(pipe):
         assert err <= tol, (int(e), err)
 
 
-def test_full_solve_on_oracle_geometry(semlib, oracle_mod):
-    """Solve with the oracle's factors loaded; the oracle measures the true residual."""
-    print("case: full pipe solve (oracle geometry)", flush=True)
+@pytest.fixture(scope="module")
+def pipe_oracle_geom(semlib, oracle_mod):
+    """The pipe with the oracle's own geometric factors loaded, so that the
+    operator is compared on identical factors (no conditioning slack at the
+    singular corners)."""
+    print("case: full pipe setup on the oracle's geometry", flush=True)
     om = oracle_mod.pipe_mesh(*NEL, N=N)
     G, B = om.geom()
     m = semlib.pipe_mesh(*NEL, N=N, with_fp32=True)
     m.load_geometry(G, B)
+    del G, B
+    yield m, om
+    m.close()
+
+
+def test_full_ax_axgs_on_oracle_geometry(pipe_oracle_geom):
+    """On identical factors the operator meets the 1e-12 bar on every sampled
+    element, the corner columns (G = 0 at the dropped quadrature points)
+    included, and Ax+gs meets it on the whole mesh (norm-wise and max-norm)
+    against the oracle's assembled apply, as two launches and fused."""
+    m, om = pipe_oracle_geom
+    print("case: full pipe ax sampled + axgs whole (oracle geometry)", flush=True)
+    rng = np.random.default_rng(6)
+    nx, ny, nz = NEL
+    corners = [ex + nx * (ey + ny * ez) for ez in (0, 1, nz // 2, nz - 1)
+               for ex in (0, 1, nx - 2, nx - 1) for ey in (0, 1, ny - 2, ny - 1)]
+    elems = np.unique(np.concatenate([rng.integers(0, om.E, 64), corners, [0, om.E - 1]])).astype(np.int64)
+    u = SI.random_local(om.nloc, 23)
+    ud = torch.from_numpy(u).cuda()
+    w = m.ax(ud).cpu().numpy()
+    P3 = (N + 1) ** 3
+    us = np.concatenate([u[e * P3:(e + 1) * P3] for e in elems])
+    ref = om.ax(us, elems=elems)
+    worst = 0.0
+    for q, e in enumerate(elems):
+        a = w[e * P3:(e + 1) * P3]
+        b = ref[q * P3:(q + 1) * P3]
+        err = max(np.linalg.norm(a - b) / np.linalg.norm(b), np.max(np.abs(a - b)) / np.max(np.abs(b)))
+        worst = max(worst, err)
+        assert err <= 1e-12, (int(e), err)
+    print(f"  worst sampled element error {worst:.2e}", flush=True)
+    del w, ref, us
+    refg = om.apply(u)
+    for fused in (False, True):
+        m.set_axgs_config(fused, 4 if fused else 0, 9 if fused else 0)
+        wg = m.axgs(ud).cpu().numpy()
+        e2 = np.linalg.norm(wg - refg) / np.linalg.norm(refg)
+        einf = np.max(np.abs(wg - refg)) / np.max(np.abs(refg))
+        print(f"  axgs (fused={fused}) whole mesh: {e2:.2e} norm-wise, {einf:.2e} max-norm", flush=True)
+        assert e2 <= 1e-12 and einf <= 1e-12, (fused, e2, einf)
+    m.set_axgs_config(False)
+
+
+def test_full_solve_on_oracle_geometry(pipe_oracle_geom):
+    """Solve with the oracle's factors loaded; the oracle measures the true residual."""
+    print("case: full pipe solve (oracle geometry)", flush=True)
+    m, om = pipe_oracle_geom
     gid = om.numbering()
     b = SI.uniform_global_values(om.nglob, 2)[gid]
     b[om.local_mask() == 1] = 0.0
@@ -96,21 +150,16 @@ def test_full_solve_on_oracle_geometry(semlib, oracle_mod):
               f"gpu residual {res.rel_residual:.3e}, oracle residual {rel:.3e}", flush=True)
         assert res.ok
         assert rel <= 1e-10, rel
-    m.close()
 
 
-def test_full_two_level_preconditioners(semlib, oracle_mod):
+def test_full_two_level_preconditioners(pipe_oracle_geom):
     """Eq. 6 at full size, where the oracle cannot form A0 or the local
     solves: with the coarse term, FP64 and mixed solves meet the oracle's true
     residual in far fewer iterations than Jacobi's 3229; M^-1 is symmetric
     and positive (unique-dof products) with the coarse term and with the
     Schwarz local solves plus the coarse term."""
     print("case: full pipe two-level preconditioners (oracle geometry)", flush=True)
-    om = oracle_mod.pipe_mesh(*NEL, N=N)
-    G, B = om.geom()
-    m = semlib.pipe_mesh(*NEL, N=N, with_fp32=True)
-    m.load_geometry(G, B)
-    del G, B
+    m, om = pipe_oracle_geom
     gid = om.numbering()
     live = om.local_mask() == 0
     b = SI.uniform_global_values(om.nglob, 2)[gid] * live
@@ -137,4 +186,5 @@ def test_full_two_level_preconditioners(semlib, oracle_mod):
         assert abs(a - c) <= 1e-11 * max(abs(a), abs(c)), (label, a, c)
         assert om.dot(r1, z1) > 0 and om.dot(r2, z2) > 0
         assert np.all(z1[~live] == 0.0)
-    m.close()
+    m.set_schwarz(False)
+    m.set_coarse(0)

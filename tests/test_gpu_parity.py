@@ -56,25 +56,84 @@ def _nel_for(N):
 
 
 def _order_scale(N):
-    """Growth of the rounding error of Algorithm 1's sums with the order: the
-    entries of D grow like N^2 (|D_00| = N(N+1)/4), so the cancellation in each
-    output grows like (N+1)^2; the tolerances below hold up to N = 12 and are
-    scaled by ((N+1)/13)^2 beyond."""
+    """Growth with the order of the difference between two FP64 evaluations
+    that start from differently rounded geometric factors: the factors come
+    from differentiating node coordinates with D, whose entries grow like N^2
+    (|D_00| = N(N+1)/4), and each output sums 3(N+1) products with D again;
+    the tolerances on each side's own geometry hold up to N = 12 and are
+    scaled by ((N+1)/13)^2 beyond.  The operator's own rounding stays within
+    the unscaled bar (the extended-precision test below), and on identical
+    factors so does its difference from the oracle."""
     return max(1.0, ((N + 1) / 13.0) ** 2)
 
 
 @pytest.mark.parametrize("N", list(range(1, 18)))
 def test_ax_fp64_all_orders(semlib, oracle_mod, N):
-    """Ragged element counts (not a multiple of the elements per workgroup)."""
+    """Ragged element counts (not a multiple of the elements per workgroup).
+    On the library's own geometry the result differs from the oracle's by the
+    two FP64 geometries' rounding, which grows with the order (the factors
+    come from differentiating coordinates with D, |D| ~ N^2); on the oracle's
+    factors, loaded through sem_load_geometry, the 1e-12 bar holds at every
+    order."""
     nel = _nel_for(N)
     print(f"case: ax fp64 N={N} nel={nel}", flush=True)
     m, om = _box(semlib, oracle_mod, N, nel, seed=N)
     u = SI.random_local(om.nloc, 100 + N)
-    w = _host(m.ax(_dev(u)))
     ref = om.ax(u)
-    e2, einf = _relerr(w, ref)
+    e2, einf = _relerr(_host(m.ax(_dev(u))), ref)
     tol = 1e-12 * _order_scale(N)
     assert e2 <= tol and einf <= tol, (e2, einf)
+    m.load_geometry(*om.geom())
+    e2, einf = _relerr(_host(m.ax(_dev(u))), ref)
+    assert e2 <= 1e-12 and einf <= 1e-12, (e2, einf)
+
+
+def _ax_extended(N, D, G, u, E):
+    """A_L u in 80-bit extended precision from the library's own FP64 D and
+    factors (exact inputs): the reference against which the rounding of the
+    FP64 operator itself is measured."""
+    LD = np.longdouble
+    P = N + 1
+    P3 = P ** 3
+    D = D.astype(LD)
+    out = np.zeros(E * P3, dtype=LD)
+    for e in range(E):
+        U = u[e * P3:(e + 1) * P3].astype(LD).reshape(P, P, P)  # [k, j, i]
+        g = G[:, e * P3:(e + 1) * P3].astype(LD).reshape(6, P, P, P)
+        ur = np.einsum("il,kjl->kji", D, U)
+        us = np.einsum("jl,kli->kji", D, U)
+        ut = np.einsum("kl,lji->kji", D, U)
+        fr = g[0] * ur + g[3] * us + g[4] * ut
+        fs = g[3] * ur + g[1] * us + g[5] * ut
+        ft = g[4] * ur + g[5] * us + g[2] * ut
+        w = (np.einsum("li,kjl->kji", D, fr) + np.einsum("lj,kli->kji", D, fs)
+             + np.einsum("lk,lji->kji", D, ft))
+        out[e * P3:(e + 1) * P3] = w.reshape(-1)
+    return out
+
+
+@pytest.mark.parametrize("N", [2, 7, 12, 13, 15, 17])
+def test_ax_fp64_against_extended_precision(semlib, N):
+    """The rounding of the FP64 operator itself, measured against an 80-bit
+    evaluation on identical inputs (the library's D and factors): within the
+    1e-12 bar at every order up to the LDS limit, so the order-scaled
+    tolerance of the comparisons on the library's own geometry covers the
+    two geometries' rounding, not the operator's."""
+    nel = _nel_for(N)
+    print(f"case: ax fp64 vs extended precision N={N} nel={nel}", flush=True)
+    V = SI.jittered_box_vertices(nel, seed=N)
+    m = semlib.box_mesh(N, nel, vertices=V)
+    _, _, D = semlib.export_gll(N)
+    G, _, _ = m.export_geom()
+    u = SI.random_local(m.n_local, 100 + N)
+    w = _host(m.ax(_dev(u)))
+    ref = _ax_extended(N, D, G, u, m.E)
+    d = (w.astype(np.longdouble) - ref)
+    e2 = float(np.sqrt(np.sum(d * d) / np.sum(ref * ref)))
+    einf = float(np.max(np.abs(d)) / np.max(np.abs(ref)))
+    print(f"  N={N}: {e2:.2e} norm-wise, {einf:.2e} max-norm", flush=True)
+    assert e2 <= 1e-12 and einf <= 1e-12, (e2, einf)
+    m.close()
 
 
 @pytest.mark.parametrize("N", list(range(1, 18)))
@@ -129,55 +188,6 @@ def test_operator_config_does_not_change_results(semlib, oracle_mod, N, epws):
     assert e2 <= 1e-12
     with pytest.raises(semlib.SemError):
         m.set_operator_config(512 // (N + 1) ** 2 + 1, 0)
-
-
-@pytest.mark.parametrize("N", list(range(1, 8)))
-def test_node_operator_kernel(semlib, oracle_mod, N):
-    """The lane-per-node operator (N <= 7): FP64 and FP32 against the oracle,
-    and against the column kernel, plain and Helmholtz."""
-    nel = (3, 2, 3)
-    print(f"case: node operator N={N}", flush=True)
-    m, om = _box(semlib, oracle_mod, N, nel, seed=40 + N, with_fp32=True)
-    u = SI.random_local(om.nloc, 80 + N)
-    col = _host(m.ax(_dev(u)))
-    m.set_operator_kernel("node")
-    assert m.operator_kernel() == "node"
-    nod = _host(m.ax(_dev(u)))
-    ref = om.ax(u)
-    e2, einf = _relerr(nod, ref)
-    assert e2 <= 1e-12 and einf <= 1e-12, (e2, einf)
-    assert np.linalg.norm(nod - col) <= 1e-14 * np.linalg.norm(col)
-    u32 = u.astype(np.float32)
-    e2, einf = _relerr(_host(m.ax(_dev(u32, torch.float32))), om.ax(u32.astype(np.float64)))
-    assert e2 <= 2e-6 and einf <= 2e-5, (e2, einf)
-    w, dot = m.ax(_dev(u), dot=True)
-    assert abs(float(dot.item()) - float(u @ ref)) <= 1e-12 * np.abs(u * ref).sum()
-    h1 = SI.uniform_local(om.nloc, 90 + N, 0.5, 2.0)
-    h2 = SI.uniform_local(om.nloc, 91 + N, 0.0, 3.0)
-    m.set_helmholtz(_dev(h1), _dev(h2))
-    e2, _ = _relerr(_host(m.ax(_dev(u))), om.ax(u, h1=h1, h2=h2))
-    assert e2 <= 1e-12
-    m.close()
-
-
-def test_node_operator_pcg(semlib, oracle_mod):
-    print("case: pcg with the node operator, box 4x4x4 N=7", flush=True)
-    m, om = _box(semlib, oracle_mod, 7, (4, 4, 4), with_fp32=True)
-    m.set_operator_kernel("node")
-    x, y, z = om.coords()
-    b = om.mass(SI.sin3_forcing(x, y, z))
-    _, ro = om.pcg(b, tol=1e-10)
-    for prec in ("fp64", "mixed"):
-        xg, res = m.solve(_dev(b), tol=1e-10, precision=prec)
-        assert res.ok and om.true_residual(b, _host(xg)) <= 1e-10, (prec, res)
-        if prec == "fp64":
-            assert abs(res.iterations - ro.iterations) <= max(3, 0.05 * ro.iterations)
-    # N > 7 is refused
-    m9, _ = _box(semlib, oracle_mod, 9, (1, 1, 1))
-    with pytest.raises(semlib.SemError):
-        m9.set_operator_kernel("node")
-    m9.close()
-    m.close()
 
 
 def test_ax_dot_and_fp32(semlib, oracle_mod):
@@ -267,6 +277,8 @@ def test_pcg_pipe_small(semlib, oracle_mod):
     print("case: pcg fp64 + mixed pipe 8x8x4 N=7", flush=True)
     m = semlib.pipe_mesh(8, 8, 4, N=7, with_fp32=True)
     om = oracle_mod.pipe_mesh(8, 8, 4, N=7)
+    # the oracle's own factors: its residual is then measured on the operator solved
+    m.load_geometry(*om.geom())
     vg = SI.uniform_global_values(om.nglob, 2)
     b = vg[om.numbering()]
     b[om.local_mask() == 1] = 0
@@ -274,4 +286,4 @@ def test_pcg_pipe_small(semlib, oracle_mod):
         xg, res = m.solve(_dev(b), tol=1e-10, precision=prec, max_iter=20000)
         xh = _host(xg)
         assert res.ok, res
-        assert om.true_residual(b, xh) <= 1e-10 * 1.01, (prec, res)
+        assert om.true_residual(b, xh) <= 1e-10, (prec, res)
