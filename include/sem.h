@@ -230,6 +230,20 @@ sem_status sem_ax(sem_mesh *mesh, int dtype, const void *u, void *w, double *opt
  * the sum of all its copies, summed in ascending local index; nodes on
  * Dirichlet faces get 0.  v: device E-vector of `dtype`. */
 sem_status sem_gs(sem_mesh *mesh, int dtype, void *v, void *stream);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): sem_ax with
+ * the dot product, w = A_L u and *dot = sum u.w, allocating nothing.  The
+ * operator's per-workgroup dot partials go to a fixed array of 16384 doubles
+ * (128 KiB) that each device holds until the process ends, instead of the
+ * mesh's partials buffer; u, w (n_local entries of dtype) and dot (one
+ * double) are caller-owned device memory.  Results are the same bits as
+ * sem_ax(mesh, dtype, u, w, dot, stream).  All calls on one device share
+ * that device's array, so calls that overlap in time on one device (other
+ * streams, other threads) race; calls ordered on one stream do not.
+ * Errors: SEM_EINVAL (null pointers, u == w, unknown dtype, a mesh of another
+ * device, more operator workgroups than 16384 partials -- a larger grid set by
+ * sem_set_operator_config), SEM_EHIP. */
+sem_status sem_ax_noalloc(sem_mesh *mesh, int dtype, const void *u, void *w, double *dot, void *stream);
 
 /* w = mask(Q Q^T A_L u): sem_ax followed by sem_gs. */
 sem_status sem_axgs(sem_mesh *mesh, int dtype, const void *u, void *w, void *stream);

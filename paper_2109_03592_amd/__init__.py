@@ -221,6 +221,19 @@ class Mesh:
                                  _stream_handle(stream)), "sem_ax")
         return (w, dt) if dot else w
 
+    def ax_noalloc(self, u: torch.Tensor, w: torch.Tensor, dot: torch.Tensor, stream=None):
+        """w = A_L u and dot[0] = sum u.w with caller-owned w and dot (one FP64
+        entry); the library allocates nothing (its dot partials use a fixed
+        per-device array)."""
+        pu, pw = self._vec(u, "u"), self._vec(w, "w", dtype=u.dtype)
+        if pu == pw:
+            raise ValueError("ax_noalloc: u and w must be distinct")
+        if dot.dtype != torch.float64 or dot.device != self.device or dot.numel() < 1:
+            raise ValueError("ax_noalloc: dot must be an FP64 tensor on the mesh's device")
+        L.check(self._lib.sem_ax_noalloc(self._h, self._dt(u), pu, pw, dot.data_ptr(), _stream_handle(stream)),
+                "sem_ax_noalloc")
+        return w, dot
+
     def gs(self, v: torch.Tensor, stream=None) -> torch.Tensor:
         """In-place Q Q^T and Dirichlet mask."""
         L.check(self._lib.sem_gs(self._h, self._dt(v), self._vec(v, "v"), _stream_handle(stream)), "sem_gs")

@@ -96,6 +96,7 @@ SIGNATURES = {
     "sem_proj_solve": (_i, [_vp, _vp, _vp, C.POINTER(SolveOpts), C.POINTER(SolveStats), _vp]),
     "sem_ax": (_i, [_vp, _i, _vp, _vp, _vp, _vp]),
     "sem_gs": (_i, [_vp, _i, _vp, _vp]),
+    "sem_ax_noalloc": (_i, [_vp, _i, _vp, _vp, _vp, _vp]),
     "sem_axgs": (_i, [_vp, _i, _vp, _vp, _vp]),
     "sem_mass": (_i, [_vp, _vp, _vp, _vp]),
     "sem_scatter": (_i, [_vp, _vp, _vp, _vp]),

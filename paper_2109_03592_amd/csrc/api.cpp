@@ -8,6 +8,7 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <string>
 
 #include "axgs_host.hpp"
 #include "coarse.hpp"
@@ -256,9 +257,12 @@ static AxParams<T> ax_params(sem_mesh *m, int mode, const T *in, T *out)
 }
 
 template <typename T>
-static int64_t enqueue_ax(sem_mesh *m, int mode, const T *in, T *out, hipStream_t s)
+static int64_t enqueue_ax(sem_mesh *m, int mode, const T *in, T *out, hipStream_t s, double *partial = nullptr,
+                          int64_t partial_cap = 0)
 {
     AxParams<T> a = ax_params<T>(m, mode, in, out);
+    if (partial) a.partial = partial;
+    if (partial_cap > 0 && partial_cap < a.grid_cap) a.grid_cap = (int)partial_cap;  // never more partials
     int64_t grid = 0;
     SEM_HIP(launch_ax<T>(m->h.N, mode, a, s, &grid));
     return grid;
@@ -822,6 +826,35 @@ static sem_status solve_mixed(sem_mesh *m, const double *b, double *x, const sem
 
 using namespace sem;
 
+// --- dot partials of the entry point that allocates nothing -----------------
+// sem_ax_noalloc keeps the operator's per-workgroup dot partials in this fixed
+// device array instead of the mesh's partials buffer.  Each device holds its
+// own copy until the process ends; host code uses only the address that
+// hipGetSymbolAddress returns for the current device.
+constexpr int64_t kNoallocPartials = 16384;  // 128 KiB per device
+static __device__ __align__(256) double scratch[kNoallocPartials];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[kMaxDevices] = {};
+
+// once per device, with that device current (called by sem_setup)
+static void init_scratch(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) fail(SEM_EUNSUPPORTED, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return;
+    void *p = nullptr;
+    SEM_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[dev] = static_cast<double *>(p);
+}
+
+static double *scratch_of(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[dev];
+}
+
 extern "C" {
 
 const char *sem_last_error(void) { return g_err.c_str(); }
@@ -845,6 +878,7 @@ sem_status sem_setup(const sem_mesh_desc *desc, void *stream, sem_mesh **out)
             }
             h.desc.vertices = nullptr;
             SEM_HIP(hipGetDevice(&m->device));
+            init_scratch(m->device);
             m->with_fp32 = (desc->precision_flags & SEM_WITH_FP32) ? 1 : 0;
             m->ax_epw = default_epw(h.N);
             m->ax_epw32 = default_epw(h.N, true);
@@ -1170,6 +1204,33 @@ sem_status sem_ax(sem_mesh *m, int dtype, const void *u, void *w, double *opt_do
         const int64_t grid = dtype == SEM_FP64 ? enqueue_ax<double>(m, mode, (const double *)u, (double *)w, s)
                                                : enqueue_ax<float>(m, mode, (const float *)u, (float *)w, s);
         if (opt_dot) SEM_HIP(launch_reduce_scalar(m->partials, grid, opt_dot, s));
+        return SEM_OK;
+    });
+}
+
+sem_status sem_ax_noalloc(sem_mesh *m, int dtype, const void *u, void *w, double *dot, void *stream)
+{
+    return guarded([&]() -> sem_status {
+        if (!m || !u || !w || !dot) fail(SEM_EINVAL, "sem_ax_noalloc: null argument");
+        if (u == w) fail(SEM_EINVAL, "sem_ax_noalloc: u and w must not overlap");
+        check_dtype(m, dtype);
+        int dev = -1;
+        SEM_HIP(hipGetDevice(&dev));
+        if (dev != m->device) fail(SEM_EINVAL, "sem_ax_noalloc: the mesh lives on another device");
+        double *part = scratch_of(dev);
+        if (!part) fail(SEM_EHIP, "sem_ax_noalloc: no scratch address for this device");
+        // the operator launches min(tiles, grid cap) workgroups, one partial each
+        const int epw = dtype == SEM_FP64 ? op_epw<double>(m) : op_epw<float>(m);
+        const int64_t tiles = (m->h.E + epw - 1) / epw;
+        const int64_t grid = std::min<int64_t>(tiles, m->ax_grid_cap);
+        if (grid > kNoallocPartials)
+            fail(SEM_EINVAL, "sem_ax_noalloc: " + std::to_string(grid) + " operator workgroups exceed the " +
+                                 std::to_string(kNoallocPartials) + " dot partials of the fixed scratch");
+        hipStream_t s = (hipStream_t)stream;
+        const int64_t launched =
+            dtype == SEM_FP64 ? enqueue_ax<double>(m, 1, (const double *)u, (double *)w, s, part, kNoallocPartials)
+                              : enqueue_ax<float>(m, 1, (const float *)u, (float *)w, s, part, kNoallocPartials);
+        SEM_HIP(launch_reduce_scalar(part, launched, dot, s));
         return SEM_OK;
     });
 }
