@@ -71,7 +71,8 @@ def gs_bytes(info, dtype_bytes: int = 8) -> float:
 KERNEL_SOURCES = ("paper_2109_03592_amd/csrc/operator.hpp", "paper_2109_03592_amd/csrc/kernels.hip",
                   "paper_2109_03592_amd/csrc/kernels.hpp", "paper_2109_03592_amd/csrc/axgs_impl.hpp",
                   "paper_2109_03592_amd/csrc/axgs.hpp", "paper_2109_03592_amd/csrc/axgs64.hip")
-TRAFFIC_PROFILE = "profiles/hbm_traffic_pcg_pipe48x48x96_N7.txt"
+TRAFFIC_PROFILES = {((48, 48, 96), 7): "profiles/hbm_traffic_pcg_pipe48x48x96_N7.txt",
+                    ((48, 48, 48), 9): "profiles/hbm_traffic_pcg_pipe48x48x48_N9.txt"}
 
 
 def kernel_source_hash() -> str:
@@ -87,9 +88,10 @@ def measured_traffic(kernel: str, nel, N: int, nL: int):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known size),
     or None when the workload differs or the kernel sources changed since."""
-    path = os.path.join(HERE, TRAFFIC_PROFILE)
-    if tuple(nel) != (48, 48, 96) or N != 7 or not os.path.exists(path):
+    rel = TRAFFIC_PROFILES.get((tuple(nel), N))
+    if rel is None or not os.path.exists(os.path.join(HERE, rel)):
         return None
+    path = os.path.join(HERE, rel)
     digest, row = None, None
     with open(path) as fh:
         for line in fh:
