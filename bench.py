@@ -236,6 +236,21 @@ def axgs_timing(mesh, info, N, torch, SI, stream, applies: int):
              "ax_gbs": bytes_per_point(N, "ax", eb) * nL / t_ax / 1e9, "gs_gbs": gs_bytes(info, eb) / t_gs / 1e9,
              "ax_tflops": flops_per_point(N) * nL / t_ax / 1e12, "algorithmic_bytes": byt, "applies": applies,
              "wall_s": wall, "timing": "median of per-apply events"}
+        r["gs_kernel"] = "lattice" if mesh.gs_kind()[1] else "plan"
+        if r["gs_kernel"] == "lattice":
+            # the CSR plan's gather-scatter on the same vector, for comparison
+            mesh.set_gs_kind("plan")
+            for _ in range(3):
+                mesh.gs(w)
+            evs = [torch.cuda.Event(enable_timing=True) for _ in range(2 * applies)]
+            torch.cuda.synchronize()
+            for q in range(applies):
+                evs[2 * q].record(stream)
+                mesh.gs(w)
+                evs[2 * q + 1].record(stream)
+            torch.cuda.synchronize()
+            r["ms_gs_plan"] = _event_mean(evs, 2, 0, 1, applies) * 1e3
+            mesh.set_gs_kind("auto")
         # the opt-in fused path (lines per workgroup chosen automatically)
         mesh.set_axgs_config(True)
         fused = mesh.axgs_info(dt)

@@ -157,6 +157,22 @@ sem_status sem_load_geometry(sem_mesh *mesh, const double *G, const double *B, v
 sem_status sem_set_operator_config(sem_mesh *mesh, int epw, int grid);
 sem_status sem_get_operator_config(const sem_mesh *mesh, int *epw, int *grid);
 
+/* Which kernel performs the gather-scatter QQ^T (section 2, the exchange and
+ * summation of element face values) on this mesh, for sem_gs, sem_axgs,
+ * sem_mass and every solve:
+ *   SEM_GS_AUTO (default): on the element lattice -- a global node's copies
+ *     follow from its lattice position, so no plan is read -- whenever every
+ *     periodic axis has at least two elements; else the plan.
+ *   SEM_GS_PLAN: the CSR plan sorted by global id.
+ * Both sum a node's copies in ascending local index, from 0, and set
+ * Dirichlet nodes to 0 at every copy: results are bit-identical.  Changing
+ * the kind drops the captured CG iterations (re-captured on the next solve).
+ * sem_get_gs_config returns the kind and whether the lattice kernel runs.
+ * Errors: SEM_EINVAL (null mesh, unknown kind). */
+enum { SEM_GS_AUTO = 0, SEM_GS_PLAN = 1 };
+sem_status sem_set_gs_config(sem_mesh *mesh, int kind);
+sem_status sem_get_gs_config(const sem_mesh *mesh, int *kind, int *lattice_in_use);
+
 
 /* Fused operator and gather-scatter (Algorithm 1 followed by section 2's
  * exchange of element face values, done in one launch for the faces a

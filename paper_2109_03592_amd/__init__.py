@@ -153,6 +153,20 @@ class Mesh:
         L.check(self._lib.sem_get_operator_config(self._h, C.byref(e), C.byref(g)), "sem_get_operator_config")
         return e.value, g.value
 
+    def set_gs_kind(self, kind: str = "auto"):
+        """Gather-scatter kernel: "auto" (the lattice kernel where the mesh
+        allows it) or "plan" (the CSR plan); both give the same bits."""
+        k = {"auto": 0, "plan": 1}.get(kind)
+        if k is None:
+            raise ValueError(f"unknown gather-scatter kind {kind!r}")
+        L.check(self._lib.sem_set_gs_config(self._h, k), "sem_set_gs_config")
+
+    def gs_kind(self):
+        """(kind, lattice kernel in use)."""
+        k, on = C.c_int(), C.c_int()
+        L.check(self._lib.sem_get_gs_config(self._h, C.byref(k), C.byref(on)), "sem_get_gs_config")
+        return ("auto", "plan")[k.value], bool(on.value)
+
     def set_axgs_config(self, enable: bool = True, epw: int = 0, lines_per_wg: int = 0):
         """Fused operator and gather-scatter: on/off, elements per tile and
         x-lines per workgroup (0 = automatic)."""

@@ -83,6 +83,8 @@ SIGNATURES = {
     "sem_set_schwarz": (_i, [_vp, _i, _vp]),
     "sem_get_schwarz_info": (_i, [_vp, C.POINTER(_i), C.POINTER(C.c_int64)]),
     "sem_host_fdm_1d": (_i, [_i, _d, _i, _i, _vp, _vp, C.POINTER(_i), C.POINTER(_i)]),
+    "sem_set_gs_config": (_i, [_vp, _i]),
+    "sem_get_gs_config": (_i, [_vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "sem_set_axgs_config": (_i, [_vp, _i, _i, _i]),
     "sem_get_axgs_info": (_i, [_vp, _i, C.POINTER(AxgsInfo)]),
     "sem_host_axgs_residual": (_i, [C.POINTER(MeshDesc), _i, _i, C.POINTER(C.c_int64), C.POINTER(C.c_int64),

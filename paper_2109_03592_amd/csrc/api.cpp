@@ -271,7 +271,10 @@ static int64_t enqueue_ax(sem_mesh *m, int mode, const T *in, T *out, hipStream_
 template <typename T>
 static void enqueue_gs(sem_mesh *m, T *v, const PcgState *st, hipStream_t s)
 {
-    SEM_HIP(launch_gs<T>(m->gsplan, m->gs_off, m->gs_idx, v, false, st, s));
+    if (m->gs_lattice_ok && m->gs_kind == SEM_GS_AUTO)
+        SEM_HIP(launch_gs_lattice<T>(m->gsl, v, st, s));
+    else
+        SEM_HIP(launch_gs<T>(m->gsplan, m->gs_off, m->gs_idx, v, false, st, s));
 }
 
 // --- fused operator and gather-scatter ---------------------------------------
@@ -892,6 +895,16 @@ sem_status sem_setup(const sem_mesh_desc *desc, void *stream, sem_mesh **out)
             m->gid = dalloc<int32_t>(m, nL);
             m->gsplan.n_sum = h.gs_n_sum;
             m->gsplan.n_ids = h.gs_n_ids;
+            {
+                int faces = desc->dirichlet_faces;  // resolved as the numbering resolves it
+                if (faces < 0) {
+                    faces = 0;
+                    for (int a = 0; a < 3; ++a)
+                        if (!desc->periodic[a]) faces |= 3 << (2 * a);
+                }
+                m->gs_lattice_ok = gs_lattice_make(h.N, h.nel, h.periodic, faces, m->gsl) ? 1 : 0;
+                m->gs_kind = SEM_GS_AUTO;
+            }
             m->gs_off = dalloc<int32_t>(m, h.gs_off.size());
             m->gs_idx = dalloc<int32_t>(m, h.gs_idx.size());
             m->ax_grid_cap = persistent_grid_cap();
@@ -1135,6 +1148,29 @@ sem_status sem_get_operator_config(const sem_mesh *m, int *epw, int *grid)
         if (!m) fail(SEM_EINVAL, "sem_get_operator_config: null mesh");
         if (epw) *epw = m->ax_epw;
         if (grid) *grid = m->ax_grid_cap;
+        return SEM_OK;
+    });
+}
+
+sem_status sem_set_gs_config(sem_mesh *m, int kind)
+{
+    return guarded([&]() -> sem_status {
+        if (!m) fail(SEM_EINVAL, "sem_set_gs_config: null mesh");
+        if (kind != SEM_GS_AUTO && kind != SEM_GS_PLAN) fail(SEM_EINVAL, "sem_set_gs_config: unknown kind");
+        if (kind != m->gs_kind) {
+            drop_graphs(m, nullptr);  // captured iterations hold the old kernel
+            m->gs_kind = kind;
+        }
+        return SEM_OK;
+    });
+}
+
+sem_status sem_get_gs_config(const sem_mesh *m, int *kind, int *lattice_in_use)
+{
+    return guarded([&]() -> sem_status {
+        if (!m) fail(SEM_EINVAL, "sem_get_gs_config: null mesh");
+        if (kind) *kind = m->gs_kind;
+        if (lattice_in_use) *lattice_in_use = m->gs_lattice_ok && m->gs_kind == SEM_GS_AUTO;
         return SEM_OK;
     });
 }

@@ -11,6 +11,8 @@
 //  * gs_kernel: direct-stiffness summation from a plan sorted by global id:
 //    one lane per global id, copies summed in ascending local index and
 //    written back; masked ids get 0.  No atomics.
+//  * gs_lattice_kernel: the same summation with no plan read: a node's
+//    copies follow from its position on the element lattice (GsLattice).
 //  * PCG update / reductions: fused x, r update with the Jacobi-weighted
 //    <r,z> and <r,r>, per-workgroup partials reduced in a fixed order by a
 //    single-workgroup kernel that also forms alpha and beta on the device.
@@ -128,6 +130,119 @@ __global__ __launch_bounds__(256) void gs_kernel(GsPlan plan, int64_t first, con
     const int64_t t = first + (int64_t)lb * blockDim.x + threadIdx.x;
     if (t >= plan.n_ids) return;
     gs_id<T>(t, plan.n_sum, off, idx, v);
+}
+
+// Copies along one axis of the lattice coordinate X (see GsLattice): count,
+// element coordinate and GLL index of each, in ascending element coordinate;
+// `masked` when X lies on a Dirichlet face.
+struct AxisCopies {
+    int c;
+    int e[2], n[2];
+    bool masked;
+};
+
+__device__ inline AxisCopies axis_copies(int X, int N, int nel, int periodic, int ext, int lo_bit, int hi_bit)
+{
+    AxisCopies a;
+    a.masked = false;
+    const int q = X / N, r = X - q * N;
+    if (r != 0) {
+        a.c = 1; a.e[0] = q; a.n[0] = r; a.e[1] = q; a.n[1] = r;
+    } else if (X == 0) {
+        a.e[0] = 0; a.n[0] = 0;
+        if (periodic) {
+            a.c = 2; a.e[1] = nel - 1; a.n[1] = N;
+        } else {
+            a.c = 1; a.e[1] = 0; a.n[1] = 0; a.masked = lo_bit != 0;
+        }
+    } else if (!periodic && X == ext - 1) {
+        a.c = 1; a.e[0] = nel - 1; a.n[0] = N; a.e[1] = nel - 1; a.n[1] = N; a.masked = hi_bit != 0;
+    } else {
+        a.c = 2; a.e[0] = q - 1; a.n[0] = N; a.e[1] = q; a.n[1] = 0;
+    }
+    return a;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void gs_lattice_kernel(GsLattice L, T *__restrict__ v,
+                                                         const PcgState *__restrict__ st)
+{
+    if (st && st->done) return;
+    // the XCD-aware remap of gs_kernel: each XCD walks one contiguous range
+    const unsigned nb = gridDim.x, b = blockIdx.x;
+    const unsigned per = nb / 8, rem = nb % 8, xcd = b % 8, kb = b / 8;
+    const unsigned lb = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + kb;
+    const int64_t t = (int64_t)lb * blockDim.x + threadIdx.x;
+    if (t >= L.n_nodes) return;
+    const int N = L.N;
+    const unsigned ext0 = (unsigned)L.ext[0];
+    unsigned X, Y, Z;
+    {
+        const unsigned u = (unsigned)t;
+        const unsigned zl = u / (unsigned)L.c_layer, r = u - zl * (unsigned)L.c_layer;
+        if (r < (unsigned)L.c_zplane) {
+            Z = zl * N;
+            Y = r / ext0;
+            X = r - Y * ext0;
+        } else {
+            const unsigned r1 = r - (unsigned)L.c_zplane;
+            const unsigned zo = r1 / (unsigned)L.c_zint, r2 = r1 - zo * (unsigned)L.c_zint;
+            Z = zl * N + 1 + zo;
+            const unsigned yl = r2 / (unsigned)L.c_yrow, r3 = r2 - yl * (unsigned)L.c_yrow;
+            if (r3 < ext0) {
+                Y = yl * N;
+                X = r3;
+            } else {
+                const unsigned r4 = r3 - ext0, yo = r4 / (unsigned)L.np0;
+                Y = yl * N + 1 + yo;
+                X = (r4 - yo * (unsigned)L.np0) * N;
+            }
+        }
+    }
+    const AxisCopies cx = axis_copies((int)X, N, L.nel[0], L.periodic[0], L.ext[0], L.faces & 1, L.faces & 2);
+    const AxisCopies cy = axis_copies((int)Y, N, L.nel[1], L.periodic[1], L.ext[1], L.faces & 4, L.faces & 8);
+    const AxisCopies cz = axis_copies((int)Z, N, L.nel[2], L.periodic[2], L.ext[2], L.faces & 16, L.faces & 32);
+    const bool masked = cx.masked || cy.masked || cz.masked;
+    const int cnt = cx.c * cy.c * cz.c;
+    if (!masked && cnt < 2) return;
+    const int P = N + 1;
+    const int64_t P3 = (int64_t)P * P * P;
+    // local indices in ascending order: z outer, then y, then x
+    int64_t a[8];
+#pragma unroll
+    for (int qz = 0; qz < 2; ++qz)
+#pragma unroll
+        for (int qy = 0; qy < 2; ++qy)
+#pragma unroll
+            for (int qx = 0; qx < 2; ++qx) {
+                const int64_t e = ((int64_t)cz.e[qz] * L.nel[1] + cy.e[qy]) * L.nel[0] + cx.e[qx];
+                a[(qz * 2 + qy) * 2 + qx] = e * P3 + ((int64_t)cz.n[qz] * P + cy.n[qy]) * P + cx.n[qx];
+            }
+    if (masked) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int qz = q >> 2, qy = (q >> 1) & 1, qx = q & 1;
+            if (qz < cz.c && qy < cy.c && qx < cx.c) v[a[q]] = T(0);
+        }
+        return;
+    }
+    T val[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int qz = q >> 2, qy = (q >> 1) & 1, qx = q & 1;
+        val[q] = (qz < cz.c && qy < cy.c && qx < cx.c) ? v[a[q]] : T(0);
+    }
+    T s = T(0);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int qz = q >> 2, qy = (q >> 1) & 1, qx = q & 1;
+        if (qz < cz.c && qy < cy.c && qx < cx.c) s = s + val[q];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int qz = q >> 2, qy = (q >> 1) & 1, qx = q & 1;
+        if (qz < cz.c && qy < cy.c && qx < cx.c) v[a[q]] = s;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -608,6 +723,49 @@ template hipError_t launch_gs<double>(const GsPlan &, const int32_t *, const int
                                       const PcgState *, hipStream_t);
 template hipError_t launch_gs<float>(const GsPlan &, const int32_t *, const int32_t *, float *, bool,
                                      const PcgState *, hipStream_t);
+
+bool gs_lattice_make(int N, const int nel[3], const int periodic[3], int faces, GsLattice &L)
+{
+    if (N < 1) return false;
+    L.N = N;
+    L.faces = faces;
+    int64_t ext[3], np[3];
+    for (int a = 0; a < 3; ++a) {
+        if (nel[a] < 1 || (periodic[a] && nel[a] < 2)) return false;
+        L.nel[a] = nel[a];
+        L.periodic[a] = periodic[a] ? 1 : 0;
+        ext[a] = (int64_t)nel[a] * N + (periodic[a] ? 0 : 1);
+        np[a] = periodic[a] ? nel[a] : (int64_t)nel[a] + 1;
+        if (ext[a] >= INT32_MAX) return false;
+        L.ext[a] = (int)ext[a];
+    }
+    const int64_t c_zplane = ext[0] * ext[1];
+    const int64_t c_yrow = ext[0] + (int64_t)(N - 1) * np[0];
+    const int64_t c_zint = np[1] * ext[0] + (int64_t)nel[1] * (N - 1) * np[0];
+    const int64_t c_layer = c_zplane + (int64_t)(N - 1) * c_zint;
+    const int64_t n = (int64_t)nel[2] * c_layer + (periodic[2] ? 0 : c_zplane);
+    // lanes decode positions with 32-bit arithmetic
+    if (n >= INT32_MAX) return false;
+    L.np0 = (int)np[0];
+    L.c_zplane = (int)c_zplane;
+    L.c_yrow = (int)c_yrow;
+    L.c_zint = (int)c_zint;
+    L.c_layer = (int)c_layer;
+    L.n_nodes = n;
+    return true;
+}
+
+template <typename T>
+hipError_t launch_gs_lattice(const GsLattice &L, T *v, const PcgState *st, hipStream_t s)
+{
+    const int64_t n = L.n_nodes;
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL((gs_lattice_kernel<T>), dim3((unsigned)blocks), dim3(256), 0, s, L, v, st);
+    return hipGetLastError();
+}
+template hipError_t launch_gs_lattice<double>(const GsLattice &, double *, const PcgState *, hipStream_t);
+template hipError_t launch_gs_lattice<float>(const GsLattice &, float *, const PcgState *, hipStream_t);
 
 int vec_blocks(int64_t n) { return grid_for(n, 256, 8192); }
 
