@@ -393,6 +393,19 @@ __global__ __launch_bounds__(256) void pcg_update_kernel(int64_t n, const PcgSta
     block_reduce_store<2>(v, partial, 2);
 }
 
+// Elements [e0, e1) of the workgroup in the element-wise update: the
+// workgroups split the elements into contiguous chunks, and the workgroups
+// that run on one XCD (blockIdx mod 8) take neighbouring chunks.
+__device__ inline void update_chunk(int64_t E, int64_t &e0, int64_t &e1)
+{
+    const unsigned nb = gridDim.x, b = blockIdx.x;
+    const unsigned per = nb / 8, rem = nb % 8, xcd = b % 8, kb = b / 8;
+    const unsigned lb = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + kb;
+    const int64_t chunk = (E + nb - 1) / nb;
+    e0 = (int64_t)lb * chunk;
+    e1 = e0 + chunk < E ? e0 + chunk : E;
+}
+
 // The same update element by element: one wavefront per element, each lane
 // P^3/64 nodes at stride 64 (all their loads in flight together); the
 // partial pairs per workgroup of four wavefronts.
@@ -408,7 +421,9 @@ __global__ __launch_bounds__(256) void pcg_update_elem_kernel(int64_t E, const P
     const T alpha = (T)st->alpha;
     const int lane = threadIdx.x & 63;
     double rr = 0.0, rz = 0.0;
-    for (int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); e < E; e += (int64_t)gridDim.x * 4) {
+    int64_t e0, e1;
+    update_chunk(E, e0, e1);
+    for (int64_t e = e0 + (threadIdx.x >> 6); e < e1; e += 4) {
         const int64_t base = e * P3;
 #pragma unroll
         for (int q = lane; q < P3; q += 64) {
@@ -419,6 +434,105 @@ __global__ __launch_bounds__(256) void pcg_update_elem_kernel(int64_t E, const P
             const double rd = (double)rv;
             rr += rd * rd * im;
             if (inv) rz += rd * (double)(ld_stream(inv + o) * rv) * im;
+        }
+    }
+    double v[2] = {rr, rz};
+    block_reduce_store<2>(v, partial, 2);
+}
+
+// Copies along one axis of element coordinate c, GLL index n (see
+// GsLattice), in ascending element coordinate; `masked` on a Dirichlet face.
+template <int N>
+__device__ inline AxisCopies elem_axis_copies(int c, int n, int nel, int periodic, int lo_bit, int hi_bit)
+{
+    AxisCopies a;
+    a.masked = false;
+    a.c = 1;
+    a.e[0] = a.e[1] = c;
+    a.n[0] = a.n[1] = n;
+    if (n == 0) {
+        if (c > 0) {
+            a.c = 2; a.e[0] = c - 1; a.n[0] = N; a.e[1] = c; a.n[1] = 0;
+        } else if (periodic) {
+            a.c = 2; a.e[0] = 0; a.n[0] = 0; a.e[1] = nel - 1; a.n[1] = N;
+        } else {
+            a.masked = lo_bit != 0;
+        }
+    } else if (n == N) {
+        if (c < nel - 1) {
+            a.c = 2; a.e[0] = c; a.n[0] = N; a.e[1] = c + 1; a.n[1] = 0;
+        } else if (periodic) {
+            a.c = 2; a.e[0] = 0; a.n[0] = 0; a.e[1] = nel - 1; a.n[1] = N;
+        } else {
+            a.masked = hi_bit != 0;
+        }
+    }
+    return a;
+}
+
+// The element-wise update with the gather-scatter of w folded in (lattice
+// meshes, Jacobi iteration): a node on an element face sums its copies of w
+// itself -- from 0, in ascending local index, as the gather-scatter would --
+// and uses the sum, so the assembled w is never written and the separate
+// gather-scatter pass disappears; the result is bit-identical to gather-
+// scatter then update.  Each block walks a contiguous chunk of elements
+// (blocks XCD-contiguous; update_chunk), so the neighbours whose faces it
+// reads are being read on the same XCD at about the same time.
+template <typename T, int N>
+__global__ __launch_bounds__(256) void pcg_update_gs_kernel(GsLattice L, int64_t E, const PcgState *__restrict__ st,
+                                                            T *__restrict__ r, const T *__restrict__ w,
+                                                            const T *__restrict__ inv,
+                                                            const uint8_t *__restrict__ mult,
+                                                            double *__restrict__ partial)
+{
+    constexpr int P = N + 1, P2 = P * P, P3 = P2 * P;
+    if (st->done) return;
+    const T alpha = (T)st->alpha;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int64_t e0, e1;
+    update_chunk(E, e0, e1);  // the same elements per workgroup as pcg_update_elem_kernel: the same partials
+    const int nx = L.nel[0], ny = L.nel[1];
+    double rr = 0.0, rz = 0.0;
+    for (int64_t e = e0 + wave; e < e1; e += 4) {
+        const int ex = (int)(e % nx);
+        const int64_t eyz = e / nx;
+        const int ey = (int)(eyz % ny), ez = (int)(eyz / ny);
+        const int64_t base = e * P3;
+#pragma unroll
+        for (int q = lane; q < P3; q += 64) {
+            const int i = q % P, j = (q / P) % P, k = q / P2;
+            const int64_t o = base + q;
+            T ws = w[o];
+            if (i == 0 || i == N || j == 0 || j == N || k == 0 || k == N) {
+                const AxisCopies cx = elem_axis_copies<N>(ex, i, nx, L.periodic[0], L.faces & 1, L.faces & 2);
+                const AxisCopies cy = elem_axis_copies<N>(ey, j, ny, L.periodic[1], L.faces & 4, L.faces & 8);
+                const AxisCopies cz = elem_axis_copies<N>(ez, k, L.nel[2], L.periodic[2], L.faces & 16, L.faces & 32);
+                if (cx.masked || cy.masked || cz.masked) {
+                    ws = T(0);
+                } else if (cx.c * cy.c * cz.c > 1) {
+                    T val[8];
+#pragma unroll
+                    for (int c8 = 0; c8 < 8; ++c8) {
+                        const int qz = c8 >> 2, qy = (c8 >> 1) & 1, qx = c8 & 1;
+                        const int64_t ec = ((int64_t)cz.e[qz] * ny + cy.e[qy]) * nx + cx.e[qx];
+                        const int64_t a = ec * P3 + (cz.n[qz] * P + cy.n[qy]) * P + cx.n[qx];
+                        val[c8] = (qz < cz.c && qy < cy.c && qx < cx.c) ? w[a] : T(0);
+                    }
+                    T sum = T(0);
+#pragma unroll
+                    for (int c8 = 0; c8 < 8; ++c8) {
+                        const int qz = c8 >> 2, qy = (c8 >> 1) & 1, qx = c8 & 1;
+                        if (qz < cz.c && qy < cy.c && qx < cx.c) sum = sum + val[c8];
+                    }
+                    ws = sum;
+                }
+            }
+            const T rv = ld_stream(r + o) - alpha * ws;
+            st_stream(rv, r + o);
+            const double im = inv_mult(ld_stream(mult + o));
+            const double rd = (double)rv;
+            rr += rd * rd * im;
+            rz += rd * (double)(ld_stream(inv + o) * rv) * im;
         }
     }
     double v[2] = {rr, rz};
@@ -905,6 +1019,29 @@ hipError_t launch_pcg_update_elem(int N, int64_t E, const PcgState *st, T *r, co
     }
     return hipGetLastError();
 }
+template <typename T>
+hipError_t launch_pcg_update_gs(const GsLattice &L, int N, int64_t E, const PcgState *st, T *r, const T *w,
+                                const T *inv, const uint8_t *mult, double *partial, hipStream_t s)
+{
+    const int blocks = update_elem_blocks(E);
+    switch (N) {
+#define SEM_UPDGS_CASE(n)                                                                                       \
+    case n:                                                                                                     \
+        hipLaunchKernelGGL((pcg_update_gs_kernel<T, n>), dim3(blocks), dim3(256), 0, s, L, E, st, r, w, inv,     \
+                           mult, partial);                                                                      \
+        break;
+        SEM_UPDGS_CASE(3) SEM_UPDGS_CASE(4) SEM_UPDGS_CASE(5) SEM_UPDGS_CASE(6) SEM_UPDGS_CASE(7)
+        SEM_UPDGS_CASE(8) SEM_UPDGS_CASE(9) SEM_UPDGS_CASE(10) SEM_UPDGS_CASE(11) SEM_UPDGS_CASE(12)
+        SEM_UPDGS_CASE(13) SEM_UPDGS_CASE(14) SEM_UPDGS_CASE(15) SEM_UPDGS_CASE(16) SEM_UPDGS_CASE(17)
+#undef SEM_UPDGS_CASE
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+template hipError_t launch_pcg_update_gs<double>(const GsLattice &, int, int64_t, const PcgState *, double *,
+                                                 const double *, const double *, const uint8_t *, double *,
+                                                 hipStream_t);
+
 template hipError_t launch_pcg_update_elem<double>(int, int64_t, const PcgState *, double *, const double *,
                                                    const double *, const uint8_t *, double *, hipStream_t);
 template hipError_t launch_pcg_update_elem<float>(int, int64_t, const PcgState *, float *, const float *,

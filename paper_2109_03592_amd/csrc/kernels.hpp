@@ -91,6 +91,11 @@ int update_elem_blocks(int64_t E);
 template <typename T>
 hipError_t launch_pcg_update_elem(int N, int64_t E, const PcgState *st, T *r, const T *w, const T *inv,
                                   const uint8_t *mult, double *partial, hipStream_t s);
+// the element-wise update with the gather-scatter of w folded in (lattice
+// meshes, Jacobi; FP64); update_elem_blocks(E) partial pairs
+template <typename T>
+hipError_t launch_pcg_update_gs(const GsLattice &L, int N, int64_t E, const PcgState *st, T *r, const T *w,
+                                const T *inv, const uint8_t *mult, double *partial, hipStream_t s);
 template <typename T>
 hipError_t launch_pcg_finish(int64_t n, const PcgState *st, T *x, const T *p, hipStream_t s);
 hipError_t launch_reduce_sigma(const double *partial, int64_t n, PcgState *st, hipStream_t s);
