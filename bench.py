@@ -722,6 +722,9 @@ def main():
                    "E": mesh.E, "N": N, "n_local": nL, "n_global": nG},
         "roofline": roof,
         "step": {"ms_operator": ax_ms, "ms_gather_scatter": gs_ms, "ms_update_reduce": up_ms,
+                 "gather_scatter": ("summed in the update (lattice)"
+                                    if mesh.gs_kind()[1] and N >= 3 and not fused["enabled"]
+                                    else ("lattice" if mesh.gs_kind()[1] else "plan")),
                  "fused_operator_gs": fused,
                  "hbm_frac_step": step_bytes / (t_steps / args.steps) / 1e9 / HBM_PEAK_GBS,
                  "algorithmic_bytes_per_step": step_bytes,
