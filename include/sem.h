@@ -145,9 +145,10 @@ sem_status sem_host_setup(const sem_mesh_desc *desc, sem_mesh_info *info, int64_
 sem_status sem_load_geometry(sem_mesh *mesh, const double *G, const double *B, void *stream);
 
 /* Launch configuration of the local operator on this mesh: elements per
- * workgroup (1 <= epw, epw (N+1)^2 <= 512, its LDS 3 epw (N+1)^3 values
- * within the device's per-workgroup limit, else the operator calls fail with
- * SEM_EHIP) and the number of persistent
+ * workgroup (1 <= epw, epw (N+1)^2 <= 512, its LDS -- 3 epw (N+1)^3 values,
+ * or 3 epw (N+1)^2 for the plain and CG operators from order 8 on, which run
+ * plane by plane -- within the device's per-workgroup limit, else the
+ * operator calls fail with SEM_EHIP) and the number of persistent
  * workgroups (grid > 0; 0 keeps the default of 16 per compute unit).  Results
  * of sem_ax / sem_axgs do not depend on it; CG dot products do at rounding
  * level (their partial sums follow the workgroups).  Setting it applies to

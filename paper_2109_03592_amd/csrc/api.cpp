@@ -95,7 +95,27 @@ int default_operator_epw(int N, bool fp32)
     return best;
 }
 
-static int default_epw(int N, bool fp32 = false) { return default_operator_epw(N, fp32); }
+// The single-mesh operator from order 8 on runs the plane tile, whose LDS no
+// longer bounds the tile: elements per workgroup measured fastest on pipes of
+// about 10^8 points (CG operator for FP64, plain operator for FP32); beyond
+// order 12 the fullest 64-lane waves.
+static int default_epw(int N, bool fp32 = false)
+{
+    if (N < 8) return default_operator_epw(N, fp32);
+    static const int f64[] = {3, 1, 2, 3, 3}, f32[] = {3, 5, 2, 3, 3};
+    if (N <= 12) return fp32 ? f32[N - 8] : f64[N - 8];
+    const int P2 = (N + 1) * (N + 1);
+    int best = 1;
+    double best_fill = 0.0;
+    for (int epw = 1; epw * P2 <= 512; ++epw) {
+        const int t = epw * P2, tr = (t + 63) / 64 * 64;
+        if ((double)t / tr > best_fill + 0.005) {
+            best_fill = (double)t / tr;
+            best = epw;
+        }
+    }
+    return best;
+}
 
 // Derivative matrices of every order in the kernels' constant table, once
 // per device.

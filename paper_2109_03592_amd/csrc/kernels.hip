@@ -42,7 +42,8 @@ __global__ __launch_bounds__(512) void ax_kernel(AxParams<T> a)
     const int i = ij % P, j = ij / P;
     const bool inblk = el < a.epw;
     const int slot = inblk ? el : a.epw - 1;  // padding lanes read a valid slot
-    T *su = sm + (size_t)slot * 3 * P3;
+    constexpr bool kPlanes = MODE <= 2 && plane_tile<T, N>();
+    T *su = sm + (size_t)slot * 3 * (kPlanes ? P2 : P3);
     const T *__restrict__ D = dtable<T>(N);
     __shared__ T sDt[lane_rows_lds<T, N>()];
     LaneRows<T, N> R;
@@ -92,8 +93,13 @@ __global__ __launch_bounds__(512) void ax_kernel(AxParams<T> a)
                 evn[u] = vert_of(tile + 2 * (int64_t)gridDim.x, q);  // the tile after
             }
         }
-        ax_tile<T, N, MODE, 0, HELM>(R, D, su, e, active, inblk, i, j, a.G, a.in, a.out, a.invdiag, a.p, beta, a.x,
-                                     alpha, dot, a.h1, a.h2b, kCoarse ? szb + cur * kZB + slot * 8 : nullptr, a.cq);
+        if constexpr (kPlanes)
+            ax_tile_planes<T, N, MODE, HELM>(R, D, su, e, active, inblk, i, j, a.G, a.in, a.out, a.invdiag, a.p,
+                                             beta, a.x, alpha, dot, a.h1, a.h2b);
+        else
+            ax_tile<T, N, MODE, 0, HELM>(R, D, su, e, active, inblk, i, j, a.G, a.in, a.out, a.invdiag, a.p, beta,
+                                         a.x, alpha, dot, a.h1, a.h2b,
+                                         kCoarse ? szb + cur * kZB + slot * 8 : nullptr, a.cq);
         if constexpr (kCoarse) {
 #pragma unroll
             for (int u = 0; u < kPer; ++u) {
@@ -706,10 +712,11 @@ int ax_block_threads(int N, int epw)
     return (t + 63) / 64 * 64;
 }
 
-size_t ax_lds_bytes(int N, int epw, size_t elem)
+size_t ax_lds_bytes(int N, int epw, size_t elem, int mode)
 {
-    const size_t P3 = (size_t)(N + 1) * (N + 1) * (N + 1);
-    return (size_t)epw * 3 * P3 * elem;
+    const size_t P2 = (size_t)(N + 1) * (N + 1), P3 = P2 * (N + 1);
+    const bool planes = mode <= 2 && plane_tile_order(N);
+    return (size_t)epw * 3 * (planes ? P2 : P3) * elem;
 }
 
 
@@ -763,7 +770,7 @@ static hipError_t launch_ax_mode(int N, const AxParams<T> &a, hipStream_t s, int
     }
     static const size_t lds_cap = max_dynamic_lds();
     const int threads = ax_block_threads(N, a.epw);
-    const size_t lds = ax_lds_bytes(N, a.epw, sizeof(T));
+    const size_t lds = ax_lds_bytes(N, a.epw, sizeof(T), MODE);
     const int64_t tiles = (a.E + a.epw - 1) / a.epw;
     int64_t blocks = 0;
     if (threads > 512 || lds > lds_cap || tiles < 1 || a.grid_cap < 1) return hipErrorInvalidConfiguration;

@@ -46,7 +46,8 @@ struct AxParams {
 constexpr int kMaxPrecondOrder = 12;  // the coarse term, the Schwarz local solves and modes 3-5
 
 int ax_block_threads(int N, int epw);
-size_t ax_lds_bytes(int N, int epw, size_t elem);
+// dynamic LDS of an operator launch (mode: 0-5)
+size_t ax_lds_bytes(int N, int epw, size_t elem, int mode);
 hipError_t upload_dtables(const double *d64, const float *d32, hipStream_t s);
 int vec_blocks(int64_t n);
 int update_blocks(int64_t n);  // workgroups of the PCG update (one partial pair each)

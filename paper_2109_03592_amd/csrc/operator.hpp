@@ -382,4 +382,114 @@ __device__ inline void ax_tile(const LaneRows<T, N> &R, const T *__restrict__ D,
 }
 
 
+// At high order the whole-element tile's LDS (3 (N+1)^3 values per element)
+// leaves room for one or two workgroups per compute unit; from order 8 on
+// the operator runs plane by plane instead.
+constexpr bool plane_tile_order(int N) { return N >= 8; }
+template <typename T, int N>
+constexpr bool plane_tile() { return plane_tile_order(N); }
+
+// The local operator tile plane by plane (MODE 0-2; the same operator as
+// ax_tile).  LDS holds three planes of the element -- u(., ., k) and the two
+// in-plane fluxes -- instead of three whole elements: per plane k the lanes
+// stage u(i,j,k), form the r-, s- and t-derivatives and the fluxes of the
+// combine step, stage the r- and s-fluxes, and apply the in-plane transposed
+// derivatives; the t-direction part of the transposed derivative is
+// accumulated in registers as the planes pass.  Two barriers per plane; the
+// plane loop is not unrolled (unrolled, the compiler hoists every plane's
+// factor loads above the barriers and spills).  The caller provides the LDS
+// slot of this lane's element (3 (N+1)^2 values at least).  Sink as for
+// ax_tile: outputs go to sink(k, w) in ascending k once all planes have
+// passed, and the tile then ends without the trailing barrier.
+template <typename T, int N, int MODE, bool HELM = false, typename Sink = NoSink>
+__device__ inline void ax_tile_planes(const LaneRows<T, N> &R, const T *__restrict__ D, T *sp, int64_t e,
+                                      bool active, bool inblk, int i, int j, const T *__restrict__ G,
+                                      const T *__restrict__ in, T *__restrict__ out, const T *__restrict__ invdiag,
+                                      T *__restrict__ p, T beta, T *__restrict__ x, T alpha, double &dot,
+                                      const T *__restrict__ h1 = nullptr, const T *__restrict__ h2b = nullptr,
+                                      const Sink &sink = Sink())
+{
+    static_assert(MODE <= 2, "plane tile: the plain and CG modes");
+    constexpr int P = N + 1, P2 = P * P, P3 = P2 * P;
+    T *su = sp;
+    T *sr = sp + P2;
+    T *ss = sr + P2;
+    const int ij = i + P * j;
+    const int64_t eb = (active ? e : 0) * P3;
+    T uc[P];
+    if (MODE >= 2) {
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            T v = 0;
+            if (active) {
+                const int64_t o = eb + ij + k * P2;
+                const T pold = ld_stream(p + o);
+                // the previous iteration's x step, deferred to here where p is read anyway
+                st_stream(ld_stream(x + o) + alpha * pold, x + o);
+                v = ld_stream(invdiag + o) * ld_stream(in + o) + beta * pold;
+                st_stream(v, p + o);
+            }
+            uc[k] = v;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < P; ++k) uc[k] = active ? ld_stream(in + eb + ij + k * P2) : T(0);
+    }
+    const T *__restrict__ Ge = G + (active ? e : 0) * 6 * P3 + ij;
+    T acc[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) acc[k] = 0;
+#pragma unroll 1
+    for (int k = 0; k < P; ++k) {
+        T uk = uc[0];
+#pragma unroll
+        for (int l = 1; l < P; ++l) uk = l == k ? uc[l] : uk;
+        if (inblk) su[ij] = uk;
+        __syncthreads();
+        T ur = 0, us = 0, ut = 0;
+#pragma unroll
+        for (int l = 0; l < P; ++l) {
+            ur += R.di(l) * su[j * P + l];
+            us += R.dj(l) * su[l * P + i];
+            ut += R.dk(D, k, l) * uc[l];
+        }
+        T g1 = 0, g2 = 0, g3 = 0, g4 = 0, g5 = 0, g6 = 0;
+        if (active) {
+            const T *g = Ge + k * P2;
+            g1 = ld_stream(g + 0 * P3); g2 = ld_stream(g + 1 * P3); g3 = ld_stream(g + 2 * P3);
+            g4 = ld_stream(g + 3 * P3); g5 = ld_stream(g + 4 * P3); g6 = ld_stream(g + 5 * P3);
+        }
+        T wr = g1 * ur + g4 * us + g5 * ut;
+        T ws = g2 * us + g4 * ur + g6 * ut;
+        T wt = g3 * ut + g5 * ur + g6 * us;
+        if (HELM) {
+            const T h = active ? ld_stream(h1 + eb + ij + k * P2) : T(0);
+            wr *= h;
+            ws *= h;
+            wt *= h;
+        }
+        if (inblk) {
+            sr[ij] = wr;
+            ss[ij] = ws;
+        }
+        __syncthreads();
+        T a = 0;
+#pragma unroll
+        for (int l = 0; l < P; ++l) a += R.dti(l) * sr[j * P + l] + R.dtj(l) * ss[l * P + i];
+        // D^T in t: plane k's flux reaches every output plane kk with D[k][kk]
+#pragma unroll
+        for (int kk = 0; kk < P; ++kk) acc[kk] += R.dk(D, k, kk) * wt + (kk == k ? a : T(0));
+    }
+    constexpr bool kSink = !std::is_same<Sink, NoSink>::value;
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        T v = acc[k];
+        if (HELM && active) v += ld_stream(h2b + eb + ij + k * P2) * uc[k];
+        if constexpr (kSink) sink(k, v);
+        else if (active) st_stream(v, out + eb + ij + k * P2);
+        if (MODE != 0) dot += (double)uc[k] * (double)v;
+    }
+    if constexpr (!kSink) __syncthreads();  // the next tile rewrites the planes
+}
+
 }  // namespace sem
