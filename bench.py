@@ -575,6 +575,27 @@ def batched_section(sem, torch, SI):
                      "gdofs_aggregate": dof_iters / dt / 1e9}
         log(f"batched {prec}: {len(meshes)} solves in {dt:.3f} s ({len(meshes) / dt:.1f} solves/s), "
             f"{ok} converged, aggregate {res[prec]['gdofs_aggregate']:.2f} GDOF/s")
+    # FP64 with the coarse term of Eq. 6 on the meshes of 512 elements or more
+    big = [m for m in meshes if m.E >= 512]
+    t0 = time.perf_counter()
+    for m in big:
+        m.set_coarse(4, 0.05)
+    t_coarse = time.perf_counter() - t0
+    B.solve(meshes, bs, tol=1e-10, poll_every=16)   # warm-up (graph capture)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xs, rs = B.solve(meshes, bs, tol=1e-10, poll_every=16, raise_on_error=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ok = sum(r.ok and r.rel_residual <= 1e-10 for r in rs)
+    res["fp64_coarse"] = {"seconds": dt, "solves_per_s": len(meshes) / dt, "converged": ok,
+                          "coarse_meshes": len(big), "coarse_setup_s": t_coarse,
+                          "iterations_max": max(r.iterations for r in rs),
+                          "iterations_sum": sum(r.iterations for r in rs)}
+    log(f"batched fp64 + coarse term on {len(big)} meshes: {dt:.3f} s ({len(meshes) / dt:.1f} solves/s), "
+        f"{ok} converged, iterations max {res['fp64_coarse']['iterations_max']}")
+    for m in big:
+        m.set_coarse(0)
     # steady CG iteration rate with every slot active (tolerances no run reaches)
     for prec in ("fp64", "mixed"):
         xs = [m.zeros() for m in meshes]
@@ -627,6 +648,8 @@ def main():
     ap.add_argument("--no-n9", action="store_true", help="skip the N=9 pipe (48x48x48)")
     ap.add_argument("--serve-rates", default="10,100,1000")
     ap.add_argument("--serve-duration", type=float, default=5.0)
+    ap.add_argument("--serve-coarse-min-elems", type=int, default=512,
+                    help="serving: meshes of at least this many elements carry the coarse term (0: Jacobi only)")
     ap.add_argument("--serve-drain", type=float, default=20.0)
     ap.add_argument("--sweep", action="store_true",
                     help="only run the Ax+gs sweep over orders and element counts (one JSON line)")
@@ -818,7 +841,8 @@ def main():
     if not args.no_serve:
         from paper_2109_03592_amd.serve import serve_rates
         out["serving"] = serve_rates([float(v) for v in args.serve_rates.split(",")], duration=args.serve_duration,
-                                     max_requests=2000, drain_limit=args.serve_drain, max_slots=64, budget_gb=200.0)
+                                     max_requests=2000, drain_limit=args.serve_drain, max_slots=64, budget_gb=200.0,
+                                     coarse_min_elems=args.serve_coarse_min_elems)
 
     # ---- CPU oracle on a bounded sample ---------------------------------------
     if not args.no_cpu:

@@ -346,11 +346,16 @@ sem_status sem_pcg_solve(sem_mesh *mesh, const double *b, double *x, const sem_s
  *     polynomial, so M is symmetric positive definite.
  * The coarse term runs inside the CG iteration: restriction, Chebyshev and
  * the coarse part of <r, z> after the residual update, the prolongation in
- * the operator's prologue (the column kernel; SEM_OPK_NODE is not used while
- * a coarse space is set).  The coarse data and the Chebyshev solve stay FP64
+ * the operator's prologue.  The coarse data and the Chebyshev solve stay FP64
  * in both precisions; an FP32 inner solve restricts its FP32 residual and adds
- * the rounded correction.  Batched solves (sem_batch_*) do not take meshes
- * with a coarse space (SEM_EUNSUPPORTED).
+ * the rounded correction.  Batched solves (sem_batch_*): an FP64 slot of a
+ * mesh with a coarse space takes the coarse term too, with its own coarse
+ * vectors (several slots may share the mesh) -- its restriction, Chebyshev
+ * solve and prolongation P z0 run per slot after the batched update, and the
+ * batched operator adds P z0 in its p update, so the preconditioner is the
+ * same M (prolongation summed in another order: the same to rounding); a
+ * mixed-precision slot of such a mesh runs Jacobi.  The coarse space must not
+ * change (sem_set_coarse) while the mesh has slots in a batch.
  */
 typedef struct {
     int64_t n_vertices;   /* element vertices (periodic images merged)          */
@@ -463,7 +468,11 @@ sem_status sem_proj_solve(sem_proj *proj, const double *b, double *x, const sem_
  * small kernels inside the kernel (section 3) -- and poll_every iterations
  * are replayed as one hipGraph.  Each slot's dot
  * products are summed from its own items in a fixed order, so a slot's result
- * does not depend on which other slots share the launches.
+ * does not depend on which other slots share the launches.  The
+ * preconditioner is Jacobi, plus the coarse term of Eq. 6 for FP64 slots of
+ * a mesh with a coarse space (sem_set_coarse; its per-slot phases are
+ * launched slot by slot); meshes with the Helmholtz form or the Schwarz local
+ * solves are refused (SEM_EUNSUPPORTED).
  *
  * Ownership: the batch owns its slot vectors (allocated within
  * device_budget bytes, 0 = unlimited, reused after retirement); meshes, b and

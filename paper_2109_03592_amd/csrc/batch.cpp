@@ -18,6 +18,7 @@
 #include <new>
 
 #include "batch.hpp"
+#include "coarse.hpp"
 #include "kernels.hpp"
 
 namespace sem {
@@ -40,6 +41,11 @@ struct HostSlot {
     sem_status status = SEM_OK;
     void *buf = nullptr;     // slot-owned device vectors
     size_t buf_bytes = 0;
+    // coarse term (FP64 slots of a mesh with a coarse space): zc = P z0 and
+    // the coarse work vectors, in a second slot-owned buffer
+    void *cbuf = nullptr;
+    size_t cbuf_bytes = 0;
+    CoarseWork cw{};
     std::chrono::steady_clock::time_point t0;
     double seconds = 0.0;
 };
@@ -62,6 +68,8 @@ struct Group {
     hipGraphExec_t graph = nullptr;
     int graph_k = 0;
     unsigned graph_orders = 0;    // orders the cached graph launches
+    // the coarse-term launches the cached graph holds: (slot, its zc buffer)
+    std::vector<std::pair<int, const void *>> graph_coarse;
     GroupDev dev() const
     {
         GroupDev g;
@@ -252,16 +260,43 @@ static void upload_desc(sem_batch *B, int id, hipStream_t s)
     SEM_HIP(hipMemcpyAsync(B->d_desc + id, &B->h_desc[id], sizeof(SlotDesc), hipMemcpyHostToDevice, s));
 }
 
+// The coarse term of one FP64 slot from its current r: restriction, the
+// Chebyshev coarse solve with r0.z0 reduced into crz, and zc = masked P z0.
+// Launched per slot (the coarse vectors are small); the kernels of a
+// converged slot skip or rewrite its own buffers only.
+static void slot_coarse(sem_batch *B, int id, hipStream_t s)
+{
+    HostSlot &h = B->slots[id];
+    const SlotDesc &d = B->h_desc[id];
+    sem_mesh *m = h.mesh;
+    coarse_restrict_w<double>(m, h.cw, static_cast<const double *>(d.r[0]), m->inv64, s);
+    const int pairs = coarse_solve_w(m, h.cw, h.cw.dot, d.st, s);
+    SEM_HIP(launch_reduce_scalar(h.cw.dot, 2 * (int64_t)pairs, h.cw.rz, s));
+    coarse_prolong_w(m, h.cw, const_cast<double *>(d.zc), false, s);
+}
+
+// the group's slots that take the coarse term in precision prec
+static std::vector<std::pair<int, const void *>> coarse_slots(const sem_batch *B, const Group &g, int prec)
+{
+    std::vector<std::pair<int, const void *>> out;
+    if (prec != 0) return out;
+    for (int32_t id : g.h_slots)
+        if (B->h_desc[id].zc) out.emplace_back(id, B->h_desc[id].zc);
+    return out;
+}
+
 // one CG iteration of every slot in g, precision prec
 static void enqueue_batch_iters(sem_batch *B, Group &g, int prec, int k, unsigned orders, hipStream_t s)
 {
     const GroupDev gd = g.dev();
     const BatchLaunch L = launch_for(B, orders, g.prec);
+    const auto cs = coarse_slots(B, g, prec);
     for (int it = 0; it < k; ++it) {
         SEM_HIP(batch_ax(prec, 2, B->d_desc, gd, L, s));
         SEM_HIP(batch_gs(prec, 1, B->d_desc, gd, L, s));
         SEM_HIP(batch_reduce_sigma(prec, B->d_desc, gd, L, s));
         SEM_HIP(batch_update(prec, B->d_desc, gd, L, s));
+        for (const auto &c : cs) slot_coarse(B, c.first, s);
         SEM_HIP(batch_reduce_rho(prec, B->d_desc, gd, L, s));
     }
 }
@@ -274,8 +309,9 @@ static void run_batch_iters(sem_batch *B, Group &g, int prec, int k, bool use_gr
         return;
     }
     // a cached graph serves any membership whose orders it launches (an
-    // order without items exits at once)
-    if (!g.graph || g.graph_k != k || (g.orders & ~g.graph_orders) != 0) {
+    // order without items exits at once) and whose coarse-term slots it holds
+    const auto cs = coarse_slots(B, g, prec);
+    if (!g.graph || g.graph_k != k || (g.orders & ~g.graph_orders) != 0 || cs != g.graph_coarse) {
         const unsigned orders = g.orders | (g.graph ? g.graph_orders : 0u);
         if (g.graph) {
             SEM_HIP(hipGraphExecDestroy(g.graph));
@@ -299,6 +335,7 @@ static void run_batch_iters(sem_batch *B, Group &g, int prec, int k, bool use_gr
         g.graph = ex;
         g.graph_k = k;
         g.graph_orders = orders;
+        g.graph_coarse = cs;
     }
     SEM_HIP(hipGraphLaunch(g.graph, s));
 }
@@ -324,6 +361,8 @@ static void start_cg(sem_batch *B, const std::vector<int> &ids, int prec, hipStr
     if (ids.empty()) return;
     Group &g = B->gres;
     group_build(B, g, ids, s);
+    // the coarse term of the start residual; its r0.z0 joins rho
+    for (const auto &c : coarse_slots(B, g, prec)) slot_coarse(B, c.first, s);
     SEM_HIP(batch_cg_init(prec, B->d_desc, g.dev(), launch_for(B, g), s));
 }
 
@@ -537,20 +576,25 @@ static int admit_slot(sem_batch *B, sem_mesh *m, const double *b, double *x, con
     if (m->device != B->device) fail(SEM_EINVAL, "mesh is on another device");
     if (o.precision == SEM_PREC_MIXED && !m->with_fp32) fail(SEM_EINVAL, "mixed precision needs SEM_WITH_FP32");
     if (m->helm) fail(SEM_EUNSUPPORTED, "batched solves take the Poisson operator only (sem_set_helmholtz is set)");
-    if (m->coarse) fail(SEM_EUNSUPPORTED, "batched solves use Jacobi only (sem_set_coarse is set)");
-    if (m->schwarz) fail(SEM_EUNSUPPORTED, "batched solves use Jacobi only (sem_set_schwarz is set)");
+    if (m->schwarz) fail(SEM_EUNSUPPORTED, "batched solves take Jacobi or Jacobi + coarse term (sem_set_schwarz is set)");
     const int id = free_slot_index(B);
     if (id < 0) fail(SEM_EBUDGET, "no free slot");
+    // FP64 slots of a mesh with a coarse space take the coarse term (mixed
+    // slots of such a mesh run Jacobi in their FP32 inner iterations)
+    const bool coarse = m->coarse != nullptr && o.precision == SEM_PREC_FP64;
     const size_t need = slot_bytes(m, o.precision);
-    void *buf = nullptr;
-    auto itb = B->free_bufs.lower_bound(need);
-    if (itb != B->free_bufs.end() && itb->first <= 2 * need) {
-        buf = itb->second;
-        const size_t have = itb->first;
-        B->free_bufs.erase(itb);
-        B->slots[id].buf_bytes = have;
-    } else {
-        if (B->budget && B->used + need > B->budget) {
+    const size_t zc_bytes = ((size_t)m->h.nL * 8 + 255) / 256 * 256;
+    const size_t cneed = coarse ? zc_bytes + (size_t)coarse_work_doubles(m->coarse, m->h.E) * 8 : 0;
+    // a cached buffer of at least `bytes` (at most twice as large), else a new one
+    auto acquire = [&](size_t bytes, size_t &have) -> void * {
+        auto itb = B->free_bufs.lower_bound(bytes);
+        if (itb != B->free_bufs.end() && itb->first <= 2 * bytes) {
+            void *p = itb->second;
+            have = itb->first;
+            B->free_bufs.erase(itb);
+            return p;
+        }
+        if (B->budget && B->used + bytes > B->budget) {
             // drop cached free buffers before refusing
             for (auto &fb : B->free_bufs) {
                 hipFree(fb.second);
@@ -558,14 +602,32 @@ static int admit_slot(sem_batch *B, sem_mesh *m, const double *b, double *x, con
                 B->used -= fb.first;
             }
             B->free_bufs.clear();
-            if (B->used + need > B->budget) fail(SEM_EBUDGET, "slot vectors exceed the batch budget");
+            if (B->used + bytes > B->budget) fail(SEM_EBUDGET, "slot vectors exceed the batch budget");
         }
-        buf = balloc(B, need);
-        B->used += need;
-        B->slots[id].buf_bytes = need;
+        void *p = balloc(B, bytes);
+        B->used += bytes;
+        have = bytes;
+        return p;
+    };
+    size_t have = 0, chave = 0;
+    void *buf = acquire(need, have);
+    void *cbuf = nullptr;
+    if (coarse) {
+        try {
+            cbuf = acquire(cneed, chave);
+        } catch (...) {
+            B->free_bufs.emplace(have, buf);
+            throw;
+        }
     }
-    if (B->slots[id].buf_bytes < need) fail(SEM_EINVAL, "slot buffer smaller than its layout");
+    if (have < need || chave < cneed) fail(SEM_EINVAL, "slot buffer smaller than its layout");
     HostSlot &h = B->slots[id];
+    h.buf_bytes = have;
+    h.cbuf = cbuf;
+    h.cbuf_bytes = chave;
+    h.cw = coarse ? coarse_work_carve(m->coarse, m->h.E,
+                                      reinterpret_cast<double *>(static_cast<char *>(cbuf) + zc_bytes))
+                  : CoarseWork{};
     h.mesh = m;
     h.opts = o;
     h.b = b;
@@ -610,6 +672,8 @@ static int admit_slot(sem_batch *B, sem_mesh *m, const double *b, double *x, con
     }
     d.st = B->d_state + 2 * id;
     d.scal = B->d_scal + 2 * id;
+    d.zc = coarse ? static_cast<const double *>(cbuf) : nullptr;
+    d.crz = coarse ? h.cw.rz : nullptr;
     SEM_HIP(hipMemsetAsync(d.st, 0, 2 * sizeof(PcgState), s));
     // mixed slots start with a residual of the caller's x: zero it unless it
     // is the initial guess (FP64 slots without a guess zero it themselves)
@@ -622,6 +686,7 @@ static void retire_slot(sem_batch *B, int id)
 {
     HostSlot &h = B->slots[id];
     if (h.buf) B->free_bufs.emplace(h.buf_bytes, h.buf);
+    if (h.cbuf) B->free_bufs.emplace(h.cbuf_bytes, h.cbuf);
     h = HostSlot();
 }
 

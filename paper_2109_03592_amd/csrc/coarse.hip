@@ -288,23 +288,26 @@ __global__ __launch_bounds__(256) void cheb_kernel(int64_t nv, const int32_t *__
     }
 }
 
-// z += masked P z0
-__global__ __launch_bounds__(256) void prolong_add_kernel(int64_t E, int P, const int32_t *__restrict__ evert,
-                                                          const double *__restrict__ z0,
-                                                          const double *__restrict__ qw,
-                                                          const double *__restrict__ inv, double *__restrict__ z)
+// ADD: z += masked P z0; else z = masked P z0 (0 on masked nodes)
+template <bool ADD>
+__global__ __launch_bounds__(256) void prolong_kernel(int64_t E, int P, const int32_t *__restrict__ evert,
+                                                      const double *__restrict__ z0, const double *__restrict__ qw,
+                                                      const double *__restrict__ inv, double *__restrict__ z)
 {
     const int P3 = P * P * P;
     const int64_t n = E * P3;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
-        if (!(inv[q] > 0.0)) continue;
+        if (!(inv[q] > 0.0)) {
+            if (!ADD) z[q] = 0.0;
+            continue;
+        }
         const int64_t e = q / P3;
         double phi[8];
         hat_weights(qw, P, (int)(q - e * P3), phi);
         double s = 0.0;
 #pragma unroll
         for (int c = 0; c < 8; ++c) s += phi[c] * z0[evert[e * 8 + c]];
-        z[q] += s;
+        z[q] = ADD ? z[q] + s : s;
     }
 }
 
@@ -536,37 +539,85 @@ template int coarse_update<double>(sem_mesh *, double *, const double *, const d
 template int coarse_update<float>(sem_mesh *, float *, const float *, const float *, const PcgState *, double *,
                                   bool, hipStream_t);
 
+static int64_t round32(int64_t n) { return (n + 31) / 32 * 32; }
+
+int64_t coarse_work_doubles(const CoarseSpace *C, int64_t E)
+{
+    return round32(E * 8) + 5 * round32(C->nvert) + round32(2 * (int64_t)C->dot_blocks) + 32;
+}
+
+CoarseWork coarse_work_carve(const CoarseSpace *C, int64_t E, double *base)
+{
+    CoarseWork W;
+    double *q = base;
+    auto take = [&](int64_t n) {
+        double *r = q;
+        q += round32(n);
+        return r;
+    };
+    W.partial8 = take(E * 8);
+    W.r0 = take(C->nvert);
+    W.z0 = take(C->nvert);
+    W.res = take(C->nvert);
+    W.d = take(C->nvert);
+    W.tmp = take(C->nvert);
+    W.dot = take(2 * (int64_t)C->dot_blocks);
+    W.rz = take(1);
+    return W;
+}
+
+CoarseWork coarse_work_own(const CoarseSpace *C)
+{
+    CoarseWork W;
+    W.partial8 = C->partial8;
+    W.r0 = C->r0;
+    W.z0 = C->z0;
+    W.res = C->res;
+    W.d = C->d;
+    W.tmp = C->tmp;
+    W.dot = nullptr;
+    W.rz = nullptr;
+    return W;
+}
+
 template <typename T>
-void coarse_restrict(sem_mesh *m, const T *r, const T *inv, hipStream_t s)
+void coarse_restrict_w(sem_mesh *m, const CoarseWork &W, const T *r, const T *inv, hipStream_t s)
 {
     CoarseSpace *C = m->coarse;
     const int64_t E = m->h.E;
 #define SEM_RES(n)                                                                                                  \
     hipLaunchKernelGGL((restrict_elem_kernel<T, n>), dim3(elem_blocks(E)), dim3(256), 0, s, E, r, m->mult, inv, \
-                       C->qw, C->partial8)
+                       C->qw, W.partial8)
     SEM_COARSE_ORDER_SWITCH(m->h.N, SEM_RES)
 #undef SEM_RES
     SEM_HIP(hipGetLastError());
 }
+template void coarse_restrict_w<double>(sem_mesh *, const CoarseWork &, const double *, const double *, hipStream_t);
+
+template <typename T>
+void coarse_restrict(sem_mesh *m, const T *r, const T *inv, hipStream_t s)
+{
+    coarse_restrict_w<T>(m, coarse_work_own(m->coarse), r, inv, s);
+}
 template void coarse_restrict<double>(sem_mesh *, const double *, const double *, hipStream_t);
 template void coarse_restrict<float>(sem_mesh *, const float *, const float *, hipStream_t);
 
-int coarse_solve(sem_mesh *m, double *dot_pairs, const PcgState *st, hipStream_t s)
+int coarse_solve_w(sem_mesh *m, const CoarseWork &W, double *dot_pairs, const PcgState *st, hipStream_t s)
 {
     CoarseSpace *C = m->coarse;
     const int64_t nv = C->nvert;
     hipLaunchKernelGGL(restrict_vert_kernel, dim3(cgrid(nv, 4096)), dim3(256), 0, s, nv, C->v_off, C->v_idx,
-                       C->partial8, C->d0inv, C->inv_theta, C->r0, C->z0, C->res, C->d, st);
+                       W.partial8, C->d0inv, C->inv_theta, W.r0, W.z0, W.res, W.d, st);
     SEM_HIP(hipGetLastError());
-    double *din = C->d, *dout = C->tmp;
+    double *din = W.d, *dout = W.tmp;
     for (int j = 0; j < C->k; ++j) {
         if (j + 1 < C->k) {
             hipLaunchKernelGGL(cheb_kernel<false>, dim3(C->dot_blocks), dim3(256), 0, s, nv, C->a_off, C->a_col,
-                               C->a_val, C->c1[j], C->c2[j], C->d0inv, din, dout, C->z0, C->res, C->r0, nullptr, st);
+                               C->a_val, C->c1[j], C->c2[j], C->d0inv, din, dout, W.z0, W.res, W.r0, nullptr, st);
             std::swap(din, dout);
         } else {
             hipLaunchKernelGGL(cheb_kernel<true>, dim3(C->dot_blocks), dim3(256), 0, s, nv, C->a_off, C->a_col,
-                               C->a_val, C->c1[j], C->c2[j], C->d0inv, din, dout, C->z0, C->res, C->r0, dot_pairs,
+                               C->a_val, C->c1[j], C->c2[j], C->d0inv, din, dout, W.z0, W.res, W.r0, dot_pairs,
                                st);
         }
     }
@@ -574,13 +625,27 @@ int coarse_solve(sem_mesh *m, double *dot_pairs, const PcgState *st, hipStream_t
     return C->dot_blocks;
 }
 
-void coarse_prolong_add(sem_mesh *m, double *z, hipStream_t s)
+int coarse_solve(sem_mesh *m, double *dot_pairs, const PcgState *st, hipStream_t s)
+{
+    return coarse_solve_w(m, coarse_work_own(m->coarse), dot_pairs, st, s);
+}
+
+void coarse_prolong_w(sem_mesh *m, const CoarseWork &W, double *z, bool add, hipStream_t s)
 {
     CoarseSpace *C = m->coarse;
     const int64_t nL = m->h.nL;
-    hipLaunchKernelGGL(prolong_add_kernel, dim3(vec_blocks(nL)), dim3(256), 0, s, m->h.E, m->h.N + 1, C->evert, C->z0,
-                       C->qw, m->inv64, z);
+    if (add)
+        hipLaunchKernelGGL(prolong_kernel<true>, dim3(vec_blocks(nL)), dim3(256), 0, s, m->h.E, m->h.N + 1, C->evert,
+                           W.z0, C->qw, m->inv64, z);
+    else
+        hipLaunchKernelGGL(prolong_kernel<false>, dim3(vec_blocks(nL)), dim3(256), 0, s, m->h.E, m->h.N + 1,
+                           C->evert, W.z0, C->qw, m->inv64, z);
     SEM_HIP(hipGetLastError());
+}
+
+void coarse_prolong_add(sem_mesh *m, double *z, hipStream_t s)
+{
+    coarse_prolong_w(m, coarse_work_own(m->coarse), z, true, s);
 }
 
 void launch_jacobi(int64_t n, const double *inv, const double *r, double *z, hipStream_t s)

@@ -36,6 +36,23 @@ struct CoarseSpace {
     std::vector<void *> allocations;
 };
 
+// Work vectors of one solve's coarse term: the mesh's own (coarse_work_own,
+// for its single-mesh solves) or a batched slot's, carved from one buffer of
+// coarse_work_doubles values in this order: element restriction sums [E][8],
+// r0, z0, res, d, tmp [nvert each], the coarse dot's partial pairs and their
+// sum rz (the last two only in carved sets).
+struct CoarseWork {
+    double *partial8, *r0, *z0, *res, *d, *tmp, *dot, *rz;
+};
+int64_t coarse_work_doubles(const CoarseSpace *C, int64_t E);
+CoarseWork coarse_work_carve(const CoarseSpace *C, int64_t E, double *base);
+CoarseWork coarse_work_own(const CoarseSpace *C);
+template <typename T>
+void coarse_restrict_w(sem_mesh *m, const CoarseWork &W, const T *r, const T *inv, hipStream_t s);
+int coarse_solve_w(sem_mesh *m, const CoarseWork &W, double *dot_pairs, const PcgState *st, hipStream_t s);
+// add: z += masked P z0; else z = masked P z0
+void coarse_prolong_w(sem_mesh *m, const CoarseWork &W, double *z, bool add, hipStream_t s);
+
 // Builds the coarse space of the mesh's current operator (synchronises s).
 CoarseSpace *coarse_build(sem_mesh *m, int k, double frac, hipStream_t s);
 void coarse_free(CoarseSpace *C);

@@ -268,6 +268,8 @@ struct ColumnIndex {
 // caller).
 // MODE 4 (CG with a preconditioned residual given, e.g. by the Schwarz local
 // solves): p <- in + beta*p.  MODE 5: MODE 4 plus the coarse correction.
+// addv (MODE 2): a correction added to invdiag*r + beta*p at every node, the
+// coarse term a batched slot has prolonged beforehand (0 on masked nodes).
 // Sink: with a callable other than NoSink, each output w(i,j,k) of the lane
 // goes to sink(k, w) as it is formed instead of to `out`, and the tile ends
 // without the trailing barrier (the caller's epilogue barrier orders the LDS
@@ -282,7 +284,8 @@ __device__ inline void ax_tile(const LaneRows<T, N> &R, const T *__restrict__ D,
                                T *__restrict__ out, const T *__restrict__ invdiag, T *__restrict__ p, T beta,
                                T *__restrict__ x, T alpha, double &dot, const T *__restrict__ h1 = nullptr,
                                const T *__restrict__ h2b = nullptr, const double *zcl = nullptr,
-                               const double *__restrict__ cq = nullptr, const Sink &sink = Sink())
+                               const double *__restrict__ cq = nullptr, const Sink &sink = Sink(),
+                               const T *__restrict__ addv = nullptr)
 {
     constexpr int P = N + 1, P2 = P * P, P3 = P2 * P;
     T *sr = su + P3;
@@ -318,6 +321,8 @@ __device__ inline void ax_tile(const LaneRows<T, N> &R, const T *__restrict__ D,
                     const T iv = ld_stream(invdiag + o);
                     v = iv * ld_stream(in + o) + beta * pold;
                     if (kCoarse && iv > T(0)) v += (T)(cq[k] * cs0 + cq[P + k] * cs1);
+                    // MODE 2 with a precomputed correction (a batched slot's P z0)
+                    if (MODE == 2 && addv) v += ld_stream(addv + o);
                 }
                 st_stream(v, p + o);
             }

@@ -196,7 +196,8 @@ class GpuEngine:
     (each mesh with a base right-hand side) and one Batch."""
 
     def __init__(self, max_slots: int, budget_bytes: int, tol: float = 1e-10, inner_tol: float = 1e-4,
-                 max_iter: int = 20000, seed0: int = 1000, tune_keys: Sequence[Tuple] = ()):
+                 max_iter: int = 20000, seed0: int = 1000, tune_keys: Sequence[Tuple] = (),
+                 coarse_min_elems: int = 0, coarse_steps: int = 4, coarse_fraction: float = 0.05):
         import torch
         import paper_2109_03592_amd as sem
         self.torch, self.sem = torch, sem
@@ -204,6 +205,10 @@ class GpuEngine:
         self.batch = sem.Batch(max_slots=max_slots, budget_bytes=budget_bytes)
         self.tol, self.inner_tol, self.max_iter = tol, inner_tol, max_iter
         self.seed0 = seed0
+        # meshes of at least coarse_min_elems elements (0: none) carry the
+        # coarse term of Eq. 6; their FP64 requests take it in the batch
+        self.coarse_min_elems = int(coarse_min_elems)
+        self.coarse_steps, self.coarse_fraction = int(coarse_steps), float(coarse_fraction)
         self.meshes: Dict[Tuple, object] = {}
         self.base_rhs: Dict[Tuple, object] = {}
         self.jobs: Dict[int, Tuple] = {}
@@ -229,16 +234,26 @@ class GpuEngine:
             self._bytes[key] = int(nl * (48 + 24 + 8 + 8 + 4 + 1 + 4 + 4 + 8))
         return self._bytes[key]
 
+    def _coarse(self, key) -> bool:
+        N, nel = key
+        return self.coarse_min_elems > 0 and nel[0] * nel[1] * nel[2] >= self.coarse_min_elems
+
     def slot_bytes(self, key, mixed: bool) -> int:
         N, nel = key
-        nl = (N + 1) ** 3 * nel[0] * nel[1] * nel[2]
-        return int(nl * (8 * 3 + (16 if mixed else 0) + 8 + 8))   # slot vectors + b + x
+        E = nel[0] * nel[1] * nel[2]
+        nl = (N + 1) ** 3 * E
+        extra = 0
+        if self._coarse(key) and not mixed:
+            extra = nl * 8 + E * 8 * 14   # P z0 and the slot's coarse vectors
+        return int(nl * (8 * 3 + (16 if mixed else 0) + 8 + 8) + extra)   # slot vectors + b + x
 
     def resident(self, key) -> bool:
         return key in self.meshes
 
     def load(self, key):
         m = self._build(key)
+        if self._coarse(key):
+            m.set_coarse(self.coarse_steps, self.coarse_fraction)
         xyz = self.torch.from_numpy(m.export_coords()).cuda()
         f = self._forcing(xyz)
         self.base_rhs[key] = m.mass(f)
@@ -290,8 +305,11 @@ class GpuEngine:
 def serve_rates(rates: Sequence[float], duration: float = 10.0, max_requests: int = 2000,
                 drain_limit: float = 20.0, max_slots: int = 64, budget_gb: float = 200.0,
                 catalog: int = 24, emin: float = 64, emax: float = 32768, orders=(5, 7),
-                iterations_per_step: int = 8, seed: int = 7, tune: bool = True) -> List[Dict]:
-    """Serve Poisson arrival streams at each rate; returns one summary per rate."""
+                iterations_per_step: int = 8, seed: int = 7, tune: bool = True,
+                coarse_min_elems: int = 0) -> List[Dict]:
+    """Serve Poisson arrival streams at each rate; returns one summary per rate
+    (coarse_min_elems > 0: meshes of that many elements or more carry the
+    coarse term of Eq. 6, taken by their FP64 requests)."""
     import seeded_inputs as SI
     budget = int(budget_gb * 2 ** 30)
     # catalog keys = every (N, nel) the streams can draw
@@ -308,7 +326,7 @@ def serve_rates(rates: Sequence[float], duration: float = 10.0, max_requests: in
         for N in sorted({k[0] for k in keys}):
             ks = sorted((k for k in keys if k[0] == N), key=lambda k: k[1][0] * k[1][1] * k[1][2])
             tune_keys.append(ks[len(ks) // 2])
-    eng = GpuEngine(max_slots, budget, tune_keys=tune_keys)
+    eng = GpuEngine(max_slots, budget, tune_keys=tune_keys, coarse_min_elems=coarse_min_elems)
     base = [time.perf_counter()]
     sched = Scheduler(eng, budget, clock=lambda: time.perf_counter() - base[0],
                       iterations_per_step=iterations_per_step)
@@ -327,7 +345,8 @@ def serve_rates(rates: Sequence[float], duration: float = 10.0, max_requests: in
             st = sched.run(jobs, horizon=duration, drain_limit=drain_limit,
                            on_done=lambda j: bad.append(j) if (j.status != 0 or j.rel_residual > 1e-10) else None)
             sm = st.summary()
-            sm.update({"rate": lam, "requests": len(jobs), "failed": len(bad)})
+            sm.update({"rate": lam, "requests": len(jobs), "failed": len(bad),
+                       "coarse_min_elems": coarse_min_elems})
             out.append(sm)
             print(json.dumps(sm), file=sys.stderr, flush=True)
     finally:
@@ -343,9 +362,12 @@ def main(argv=None):
     ap.add_argument("--drain", type=float, default=20.0)
     ap.add_argument("--slots", type=int, default=64)
     ap.add_argument("--budget-gb", type=float, default=200.0)
+    ap.add_argument("--coarse-min-elems", type=int, default=0,
+                    help="meshes of at least this many elements carry the coarse term (0: Jacobi only)")
     a = ap.parse_args(argv)
     res = serve_rates([float(v) for v in a.rates.split(",")], duration=a.duration, max_requests=a.max_requests,
-                      drain_limit=a.drain, max_slots=a.slots, budget_gb=a.budget_gb)
+                      drain_limit=a.drain, max_slots=a.slots, budget_gb=a.budget_gb,
+                      coarse_min_elems=a.coarse_min_elems)
     print(json.dumps({"serving": res}))
 
 

@@ -216,9 +216,12 @@ def test_coarse_errors(semlib):
     b = m.zeros()
     b.fill_(1.0)
     batch = semlib.Batch(max_slots=2)
+    # batched slots take the coarse term, not the Schwarz local solves
+    m.set_schwarz(True)
     with pytest.raises(L.SemError) as e:
         batch.admit(m, b)
     assert e.value.status == L.SEM_EUNSUPPORTED
+    m.set_schwarz(False)
     batch.close()
     r = m.zeros()
     with pytest.raises(ValueError):
