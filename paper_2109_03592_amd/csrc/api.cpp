@@ -512,9 +512,9 @@ static void enqueue_iterations(sem_mesh *m, int k, hipStream_t s, Profiler *prof
     if constexpr (sizeof(T) == 8) zs = schwarz ? m->schwarz->zs : nullptr;
     // the Jacobi iteration runs the fused operator and gather-scatter where it applies
     AxgsShape *fused = mode == 2 ? axgs_shape<T>(m) : nullptr;
-    // FP64 Jacobi on a lattice mesh: the update sums w's copies itself
-    const bool update_gs = sizeof(T) == 8 && mode == 2 && !fused && !coarse && !schwarz && m->h.N >= 3 &&
-                           m->gs_lattice_ok && m->gs_kind == SEM_GS_AUTO;
+    // Jacobi on a lattice mesh: the update sums w's copies itself
+    const bool update_gs = mode == 2 && !fused && !coarse && !schwarz && m->h.N >= 3 && m->gs_lattice_ok &&
+                           m->gs_kind == SEM_GS_AUTO;
     for (int it = 0; it < k; ++it) {
         if (prof) prof->mark(s);
         int64_t axb = 0;
@@ -536,12 +536,13 @@ static void enqueue_iterations(sem_mesh *m, int k, hipStream_t s, Profiler *prof
             pairs = coarse_update<T>(m, Prec<T>::r(m), Prec<T>::w(m), Prec<T>::inv(m), st, m->partials, !schwarz, s);
             pairs += coarse_solve(m, m->partials + 2 * pairs, st, s);
         } else if (update_gs) {
-            if constexpr (sizeof(T) == 8)
-                SEM_HIP(launch_pcg_update_gs<double>(m->gsl, m->h.N, m->h.E, st, m->r64, m->w64, m->inv64, m->mult,
-                                                     m->partials, s));
+            SEM_HIP(launch_pcg_update_gs<T>(m->gsl, m->h.N, m->h.E, st, Prec<T>::r(m), Prec<T>::w(m), Prec<T>::inv(m),
+                                            m->mult, m->partials, s));
             pairs = update_elem_blocks(m->h.E);
-        } else if (sizeof(T) == 8 && m->h.N >= 3) {
-            // FP64: element by element (FP32 keeps the paired-entry update)
+        } else if (m->h.N >= 3 && (sizeof(T) == 8 || m->gs_lattice_ok)) {
+            // element by element (the FP32 update of a non-lattice mesh keeps
+            // the paired entries); on a lattice mesh the same workgroup
+            // partials as the update with the gather-scatter folded in
             SEM_HIP(launch_pcg_update_elem<T>(m->h.N, m->h.E, st, Prec<T>::r(m), Prec<T>::w(m), jinv, m->mult,
                                               m->partials, s));
             pairs = update_elem_blocks(m->h.E);

@@ -1048,6 +1048,8 @@ hipError_t launch_pcg_update_gs(const GsLattice &L, int N, int64_t E, const PcgS
 template hipError_t launch_pcg_update_gs<double>(const GsLattice &, int, int64_t, const PcgState *, double *,
                                                  const double *, const double *, const uint8_t *, double *,
                                                  hipStream_t);
+template hipError_t launch_pcg_update_gs<float>(const GsLattice &, int, int64_t, const PcgState *, float *,
+                                                const float *, const float *, const uint8_t *, double *, hipStream_t);
 
 template hipError_t launch_pcg_update_elem<double>(int, int64_t, const PcgState *, double *, const double *,
                                                    const double *, const uint8_t *, double *, hipStream_t);

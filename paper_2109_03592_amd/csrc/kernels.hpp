@@ -93,7 +93,7 @@ template <typename T>
 hipError_t launch_pcg_update_elem(int N, int64_t E, const PcgState *st, T *r, const T *w, const T *inv,
                                   const uint8_t *mult, double *partial, hipStream_t s);
 // the element-wise update with the gather-scatter of w folded in (lattice
-// meshes, Jacobi; FP64); update_elem_blocks(E) partial pairs
+// meshes, Jacobi; FP64 and FP32); update_elem_blocks(E) partial pairs
 template <typename T>
 hipError_t launch_pcg_update_gs(const GsLattice &L, int N, int64_t E, const PcgState *st, T *r, const T *w,
                                 const T *inv, const uint8_t *mult, double *partial, hipStream_t s);
