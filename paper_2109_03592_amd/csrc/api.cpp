@@ -101,6 +101,9 @@ int default_operator_epw(int N, bool fp32)
 // order 12 the fullest 64-lane waves.
 static int default_epw(int N, bool fp32 = false)
 {
+    // FP64 N=7: the plane-tile plain operator is fastest at 4 elements per
+    // workgroup, and the CG operator (whole-element tile) runs as fast there
+    if (N == 7 && !fp32) return 4;
     if (N < 8) return default_operator_epw(N, fp32);
     static const int f64[] = {3, 1, 2, 3, 3}, f32[] = {3, 5, 2, 3, 3};
     if (N <= 12) return fp32 ? f32[N - 8] : f64[N - 8];
@@ -346,27 +349,40 @@ static void axgs_build_shape(sem_mesh *m)
     SEM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     SEM_HIP(hipDeviceGetAttribute(&lds_cap, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     const size_t lds_limit = (size_t)lds_cap - 4096;  // static LDS of the kernel
-    // elements per tile: the count that keeps the most waves resident (then
-    // the fuller waves, then the smaller count), with or without the y line
-    // buffer
+    // elements per tile, with or without the y line buffer, among the counts
+    // that keep at least three quarters of the most resident waves any count
+    // reaches: the largest of at most 256 lanes if its lanes fill at least
+    // 90% of its waves, else the fullest waves (then the larger count).
+    // Larger tiles carry fewer per-tile costs: on the pipe at N=7 four
+    // elements per tile and nine lines per workgroup ran 1.92 ms, one
+    // element 2.29 ms, eight 2.23 ms; at N=9 five (500 of 512 lanes) ran
+    // 2.33 ms, two (200 of 256) 2.76 ms.
     auto pick = [&](bool yon, int &best_e, int &best_blocks) {
         best_e = 0;
         best_blocks = 0;
-        double best_score = -1.0;
+        int resident[513] = {0};
+        int most = 0;
         for (int e = 1; e * P2 <= 512; ++e) {
             if (A->req_epw && e != A->req_epw) continue;
             const size_t lds = axgs_lds_bytes(h.N, e, h.nel[0], yon, elem);
             if (lds > lds_limit) continue;
             const int blocks = axgs_blocks_per_cu<T>(h.N, 2, m->helm != 0, e, lds);
             if (blocks < 1) continue;
-            const int lanes = e * P2, waves = (lanes + 63) / 64;
-            const double score = (double)blocks * waves + (double)lanes / (waves * 64) * 1e-3;
-            if (score > best_score + 1e-9) {
-                best_score = score;
-                best_e = e;
-                best_blocks = blocks;
-            }
+            resident[e] = blocks * ((e * P2 + 63) / 64);
+            most = std::max(most, resident[e]);
         }
+        auto fill = [&](int e) { return (double)(e * P2) / (((e * P2 + 63) / 64) * 64); };
+        for (int e = 1; e * P2 <= 256; ++e)
+            if (resident[e] > 0 && 4 * resident[e] >= 3 * most && fill(e) >= 0.9) best_e = e;
+        if (best_e == 0) {
+            double best_fill = -1.0;
+            for (int e = 1; e * P2 <= 512; ++e)
+                if (resident[e] > 0 && 4 * resident[e] >= 3 * most && fill(e) >= best_fill - 1e-9) {
+                    best_fill = fill(e);
+                    best_e = e;
+                }
+        }
+        if (best_e > 0) best_blocks = resident[best_e] / ((best_e * P2 + 63) / 64);
     };
     const int64_t n_lines = (int64_t)h.nel[1] * h.nel[2];
     const int64_t cap = m->n_partials - 64;

@@ -101,7 +101,8 @@ int axgs_pick_lines(int64_t n_lines, int64_t resident, int64_t grid_cap)
         const int64_t wgs = (n_lines + Lw - 1) / Lw;
         if (wgs > grid_cap) continue;
         const int64_t cost = (wgs + resident - 1) / resident * Lw;
-        if (best == 0 || cost < best_cost) {
+        // equal cost: the larger count (more y-faces summed on chip)
+        if (best == 0 || cost <= best_cost) {
             best = Lw;
             best_cost = cost;
         }

@@ -133,7 +133,7 @@ __global__ __launch_bounds__(512) void axgs_kernel(AxParams<T> a, AxgsLattice L)
             my_stage[kk] = part;
         };
         // the tile of the operator kernel, so that the results keep its bits
-        if constexpr (plane_tile<T, N>())
+        if constexpr (plane_tile<T, N, MODE>())
             ax_tile_planes<T, N, MODE, HELM>(R, D, su, e, active, inblk, i, j, a.G, a.in, a.out, a.invdiag, a.p,
                                              beta, a.x, alpha, dot, a.h1, a.h2b, sink);
         else

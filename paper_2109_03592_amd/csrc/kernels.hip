@@ -42,7 +42,7 @@ __global__ __launch_bounds__(512) void ax_kernel(AxParams<T> a)
     const int i = ij % P, j = ij / P;
     const bool inblk = el < a.epw;
     const int slot = inblk ? el : a.epw - 1;  // padding lanes read a valid slot
-    constexpr bool kPlanes = MODE <= 2 && plane_tile<T, N>();
+    constexpr bool kPlanes = plane_tile<T, N, MODE>();
     T *su = sm + (size_t)slot * 3 * (kPlanes ? P2 : P3);
     const T *__restrict__ D = dtable<T>(N);
     __shared__ T sDt[lane_rows_lds<T, N>()];
@@ -715,7 +715,7 @@ int ax_block_threads(int N, int epw)
 size_t ax_lds_bytes(int N, int epw, size_t elem, int mode)
 {
     const size_t P2 = (size_t)(N + 1) * (N + 1), P3 = P2 * (N + 1);
-    const bool planes = mode <= 2 && plane_tile_order(N);
+    const bool planes = plane_tile_use(N, mode, (int)elem);
     return (size_t)epw * 3 * (planes ? P2 : P3) * elem;
 }
 

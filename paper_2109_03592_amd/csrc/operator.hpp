@@ -387,12 +387,17 @@ __device__ inline void ax_tile(const LaneRows<T, N> &R, const T *__restrict__ D,
 }
 
 
-// At high order the whole-element tile's LDS (3 (N+1)^3 values per element)
-// leaves room for one or two workgroups per compute unit; from order 8 on
-// the operator runs plane by plane instead.
-constexpr bool plane_tile_order(int N) { return N >= 8; }
-template <typename T, int N>
-constexpr bool plane_tile() { return plane_tile_order(N); }
+// Which tile an operator launch runs (mode 0-2, values of value_bytes).  At
+// high order the whole-element tile's LDS (3 (N+1)^3 values per element)
+// leaves room for one or two workgroups per compute unit, so from order 8 on
+// the operator runs plane by plane; at N = 7 the plane tile is the faster one
+// for the FP64 plain operator (modes 0, 1) only.
+constexpr bool plane_tile_use(int N, int mode, int value_bytes)
+{
+    return mode <= 2 && (N >= 8 || (N == 7 && mode <= 1 && value_bytes == 8));
+}
+template <typename T, int N, int MODE>
+constexpr bool plane_tile() { return plane_tile_use(N, MODE, (int)sizeof(T)); }
 
 // The local operator tile plane by plane (MODE 0-2; the same operator as
 // ax_tile).  LDS holds three planes of the element -- u(., ., k) and the two
