@@ -160,7 +160,7 @@ sem_status sem_get_operator_config(const sem_mesh *mesh, int *epw, int *grid);
 
 /* Which kernel performs the gather-scatter QQ^T (section 2, the exchange and
  * summation of element face values) on this mesh, for sem_gs, sem_axgs,
- * sem_mass and every solve:
+ * sem_mass, every solve and the mesh's batched slots (the kind at admission):
  *   SEM_GS_AUTO (default): on the element lattice -- a global node's copies
  *     follow from its lattice position, so no plan is read -- whenever every
  *     periodic axis has at least two elements; else the plan.

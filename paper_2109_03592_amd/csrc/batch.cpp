@@ -219,7 +219,7 @@ static void group_build(sem_batch *B, Group &g, const std::vector<int> &ids, hip
     }
     for (int id : ids) {
         const SlotDesc &d = B->h_desc[id];
-        const int64_t ng = (d.gs_n_ids + kGsChunk - 1) / kGsChunk;
+        const int64_t ng = ((d.gs_lattice ? d.gsl.n_nodes : d.gs_n_ids) + kGsChunk - 1) / kGsChunk;
         for (int64_t t = 0; t < ng; ++t) g.h_gs.push_back(Item{id, (int32_t)t});
         const int64_t nv = (d.nL + kVecChunk - 1) / kVecChunk;
         g.h_vf[id] = (int64_t)g.h_vec.size();
@@ -655,6 +655,9 @@ static int admit_slot(sem_batch *B, sem_mesh *m, const double *b, double *x, con
     d.gs_idx = m->gs_idx;
     d.gs_n_sum = hm.gs_n_sum;
     d.gs_n_ids = hm.gs_n_ids;
+    // the mesh's gather-scatter kind: the lattice kernel (same bits as the plan) where it runs
+    d.gsl = m->gsl;
+    d.gs_lattice = m->gs_lattice_ok && m->gs_kind == SEM_GS_AUTO ? 1 : 0;
     d.b = b;
     d.x64 = x;
     size_t off[7];

@@ -60,7 +60,8 @@ __global__ __launch_bounds__(512) void batch_ax_kernel(const SlotDesc *slots_, G
     const int ij = tid - el * P2;
     const int i = ij % P, j = ij / P;
     const bool inblk = el < epw;
-    T *su = sm + (size_t)(inblk ? el : epw - 1) * 3 * P3;
+    constexpr bool kPlanes = plane_tile<T, N, MODE>();  // the single-mesh operator's tile
+    T *su = sm + (size_t)(inblk ? el : epw - 1) * 3 * (kPlanes ? P2 : P3);
     const T *__restrict__ D = dtable<T>(N);
     __shared__ T sDt[lane_rows_lds<T, N>()];
     LaneRows<T, N> R;
@@ -72,18 +73,30 @@ __global__ __launch_bounds__(512) void batch_ax_kernel(const SlotDesc *slots_, G
         const bool active = inblk && e < sd.E;
         double dot = 0.0;
         if (MODE == 0) {
-            ax_tile<T, N, 0>(R, D, su, e, active, inblk, i, j, static_cast<const T *>(sd.G[0]),
-                             reinterpret_cast<const T *>(sd.x64), static_cast<T *>(sd.w[0]), nullptr, nullptr, T(0),
-                             nullptr, T(0), dot);
+            if constexpr (kPlanes)
+                ax_tile_planes<T, N, 0>(R, D, su, e, active, inblk, i, j, static_cast<const T *>(sd.G[0]),
+                                        reinterpret_cast<const T *>(sd.x64), static_cast<T *>(sd.w[0]), nullptr,
+                                        nullptr, T(0), nullptr, T(0), dot);
+            else
+                ax_tile<T, N, 0>(R, D, su, e, active, inblk, i, j, static_cast<const T *>(sd.G[0]),
+                                 reinterpret_cast<const T *>(sd.x64), static_cast<T *>(sd.w[0]), nullptr, nullptr,
+                                 T(0), nullptr, T(0), dot);
         } else {
             if (uniform_int(sd.st[prec].done) == 0) {
                 const T beta = (T)sd.st[prec].beta, alpha = (T)sd.st[prec].alpha;
                 const T *zc = prec == 0 ? reinterpret_cast<const T *>(sd.zc) : nullptr;
-                ax_tile<T, N, 2>(R, D, su, e, active, inblk, i, j, static_cast<const T *>(sd.G[prec]),
-                                 static_cast<const T *>(sd.r[prec]), static_cast<T *>(sd.w[prec]),
-                                 static_cast<const T *>(sd.inv[prec]), static_cast<T *>(sd.p[prec]), beta,
-                                 static_cast<T *>(sd.x[prec]), alpha, dot, nullptr, nullptr, nullptr, nullptr,
-                                 NoSink(), zc);
+                if constexpr (kPlanes)
+                    ax_tile_planes<T, N, 2>(R, D, su, e, active, inblk, i, j, static_cast<const T *>(sd.G[prec]),
+                                            static_cast<const T *>(sd.r[prec]), static_cast<T *>(sd.w[prec]),
+                                            static_cast<const T *>(sd.inv[prec]), static_cast<T *>(sd.p[prec]),
+                                            beta, static_cast<T *>(sd.x[prec]), alpha, dot, nullptr, nullptr,
+                                            NoSink(), zc);
+                else
+                    ax_tile<T, N, 2>(R, D, su, e, active, inblk, i, j, static_cast<const T *>(sd.G[prec]),
+                                     static_cast<const T *>(sd.r[prec]), static_cast<T *>(sd.w[prec]),
+                                     static_cast<const T *>(sd.inv[prec]), static_cast<T *>(sd.p[prec]), beta,
+                                     static_cast<T *>(sd.x[prec]), alpha, dot, nullptr, nullptr, nullptr, nullptr,
+                                     NoSink(), zc);
             }
             double v[1] = {dot};
             block_reduce_store<1>(v, g.ax_partial + it, 0);
@@ -106,6 +119,10 @@ __global__ __launch_bounds__(kBatchBlock) void batch_gs_kernel(const SlotDesc *s
         if (check_done && uniform_int(sd.st[prec].done)) continue;
         T *v = static_cast<T *>(which == 0 ? sd.w[prec] : sd.w[0]);
         const int64_t t = (int64_t)item.local * kGsChunk + threadIdx.x;
+        if (sd.gs_lattice) {
+            if (t < sd.gsl.n_nodes) gs_lattice_node<T>(sd.gsl, t, v);
+            continue;
+        }
         if (t >= sd.gs_n_ids) continue;
         gs_id<T>(t, sd.gs_n_sum, sd.gs_off, sd.gs_idx, v);
     }
@@ -401,10 +418,11 @@ __global__ __launch_bounds__(kBatchBlock) void batch_reduce_residual_kernel(Slot
 }
 
 // ---------------------------------------------------------------------------
-size_t batch_ax_lds(int N, int epw, int prec)
+size_t batch_ax_lds(int N, int epw, int prec, int mode)
 {
-    const size_t P3 = (size_t)(N + 1) * (N + 1) * (N + 1);
-    return (size_t)epw * 3 * P3 * (prec == 0 ? 8 : 4);
+    const size_t P2 = (size_t)(N + 1) * (N + 1), P3 = P2 * (N + 1);
+    const int bytes = prec == 0 ? 8 : 4;
+    return (size_t)epw * 3 * (plane_tile_use(N, mode, bytes) ? P2 : P3) * bytes;
 }
 
 template <typename T, int MODE>
@@ -413,7 +431,7 @@ static hipError_t batch_ax_order(int N, const SlotDesc *slots, const GroupDev &g
     const int epw = L.epw[N];
     const int threads = ax_block_threads(N, epw);
     if (epw < 1 || threads > 512) return hipErrorInvalidConfiguration;
-    const size_t lds = batch_ax_lds(N, epw, prec_of_host<T>());
+    const size_t lds = batch_ax_lds(N, epw, prec_of_host<T>(), MODE);
     switch (N) {
 #define SEM_BCASE(n) \
     case n: hipLaunchKernelGGL((batch_ax_kernel<T, n, MODE>), dim3(L.ax_grid), dim3(threads), lds, s, slots, g, epw); break;

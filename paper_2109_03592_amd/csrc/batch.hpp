@@ -35,6 +35,9 @@ struct SlotDesc {
     const uint8_t *mult;
     const int32_t *gs_off, *gs_idx;
     int64_t gs_n_sum, gs_n_ids;
+    GsLattice gsl;      // the lattice gather-scatter of the mesh, used when gs_lattice
+    int gs_lattice;
+    int pad2;
     const double *b;    // right-hand side (caller's)
     double *x64;        // solution (caller's)
     void *x[2];         // CG iterate per precision ([0] aliases x64, [1] the FP32 correction)

@@ -123,6 +123,114 @@ __device__ inline void gs_id(int64_t t, int64_t n_sum, const int32_t *__restrict
     }
 }
 
+// Copies along one axis of the lattice coordinate X (see GsLattice): count,
+// element coordinate and GLL index of each, in ascending element coordinate;
+// `masked` when X lies on a Dirichlet face.
+struct AxisCopies {
+    int c;
+    int e[2], n[2];
+    bool masked;
+};
+
+__device__ inline AxisCopies axis_copies(int X, int N, int nel, int periodic, int ext, int lo_bit, int hi_bit)
+{
+    AxisCopies a;
+    a.masked = false;
+    const int q = X / N, r = X - q * N;
+    if (r != 0) {
+        a.c = 1; a.e[0] = q; a.n[0] = r; a.e[1] = q; a.n[1] = r;
+    } else if (X == 0) {
+        a.e[0] = 0; a.n[0] = 0;
+        if (periodic) {
+            a.c = 2; a.e[1] = nel - 1; a.n[1] = N;
+        } else {
+            a.c = 1; a.e[1] = 0; a.n[1] = 0; a.masked = lo_bit != 0;
+        }
+    } else if (!periodic && X == ext - 1) {
+        a.c = 1; a.e[0] = nel - 1; a.n[0] = N; a.e[1] = nel - 1; a.n[1] = N; a.masked = hi_bit != 0;
+    } else {
+        a.c = 2; a.e[0] = q - 1; a.n[0] = N; a.e[1] = q; a.n[1] = 0;
+    }
+    return a;
+}
+
+// Node t (in global-id order) of the face lattice: its copies summed from
+// 0 in ascending local index and written back, 0 on a Dirichlet node, an
+// unmasked single copy left alone (see GsLattice).  Requires t < L.n_nodes.
+template <typename T>
+__device__ inline void gs_lattice_node(const GsLattice &L, int64_t t, T *__restrict__ v)
+{
+    const int N = L.N;
+    const unsigned ext0 = (unsigned)L.ext[0];
+    unsigned X, Y, Z;
+    {
+        const unsigned u = (unsigned)t;
+        const unsigned zl = u / (unsigned)L.c_layer, r = u - zl * (unsigned)L.c_layer;
+        if (r < (unsigned)L.c_zplane) {
+            Z = zl * N;
+            Y = r / ext0;
+            X = r - Y * ext0;
+        } else {
+            const unsigned r1 = r - (unsigned)L.c_zplane;
+            const unsigned zo = r1 / (unsigned)L.c_zint, r2 = r1 - zo * (unsigned)L.c_zint;
+            Z = zl * N + 1 + zo;
+            const unsigned yl = r2 / (unsigned)L.c_yrow, r3 = r2 - yl * (unsigned)L.c_yrow;
+            if (r3 < ext0) {
+                Y = yl * N;
+                X = r3;
+            } else {
+                const unsigned r4 = r3 - ext0, yo = r4 / (unsigned)L.np0;
+                Y = yl * N + 1 + yo;
+                X = (r4 - yo * (unsigned)L.np0) * N;
+            }
+        }
+    }
+    const AxisCopies cx = axis_copies((int)X, N, L.nel[0], L.periodic[0], L.ext[0], L.faces & 1, L.faces & 2);
+    const AxisCopies cy = axis_copies((int)Y, N, L.nel[1], L.periodic[1], L.ext[1], L.faces & 4, L.faces & 8);
+    const AxisCopies cz = axis_copies((int)Z, N, L.nel[2], L.periodic[2], L.ext[2], L.faces & 16, L.faces & 32);
+    const bool masked = cx.masked || cy.masked || cz.masked;
+    const int cnt = cx.c * cy.c * cz.c;
+    if (!masked && cnt < 2) return;
+    const int P = N + 1;
+    const int64_t P3 = (int64_t)P * P * P;
+    // local indices in ascending order: z outer, then y, then x
+    int64_t a[8];
+#pragma unroll
+    for (int qz = 0; qz < 2; ++qz)
+#pragma unroll
+        for (int qy = 0; qy < 2; ++qy)
+#pragma unroll
+            for (int qx = 0; qx < 2; ++qx) {
+                const int64_t e = ((int64_t)cz.e[qz] * L.nel[1] + cy.e[qy]) * L.nel[0] + cx.e[qx];
+                a[(qz * 2 + qy) * 2 + qx] = e * P3 + ((int64_t)cz.n[qz] * P + cy.n[qy]) * P + cx.n[qx];
+            }
+    if (masked) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int qz = q >> 2, qy = (q >> 1) & 1, qx = q & 1;
+            if (qz < cz.c && qy < cy.c && qx < cx.c) v[a[q]] = T(0);
+        }
+        return;
+    }
+    T val[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int qz = q >> 2, qy = (q >> 1) & 1, qx = q & 1;
+        val[q] = (qz < cz.c && qy < cy.c && qx < cx.c) ? v[a[q]] : T(0);
+    }
+    T s = T(0);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int qz = q >> 2, qy = (q >> 1) & 1, qx = q & 1;
+        if (qz < cz.c && qy < cy.c && qx < cx.c) s = s + val[q];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int qz = q >> 2, qy = (q >> 1) & 1, qx = q & 1;
+        if (qz < cz.c && qy < cy.c && qx < cx.c) v[a[q]] = s;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // GLL derivative matrices of every order in constant memory: the uniform
 // D[k][l] of the t-direction become scalar loads, the per-lane rows vector
@@ -410,14 +518,15 @@ constexpr bool plane_tile() { return plane_tile_use(N, MODE, (int)sizeof(T)); }
 // factor loads above the barriers and spills).  The caller provides the LDS
 // slot of this lane's element (3 (N+1)^2 values at least).  Sink as for
 // ax_tile: outputs go to sink(k, w) in ascending k once all planes have
-// passed, and the tile then ends without the trailing barrier.
+// passed, and the tile then ends without the trailing barrier.  addv as for
+// ax_tile (MODE 2).
 template <typename T, int N, int MODE, bool HELM = false, typename Sink = NoSink>
 __device__ inline void ax_tile_planes(const LaneRows<T, N> &R, const T *__restrict__ D, T *sp, int64_t e,
                                       bool active, bool inblk, int i, int j, const T *__restrict__ G,
                                       const T *__restrict__ in, T *__restrict__ out, const T *__restrict__ invdiag,
                                       T *__restrict__ p, T beta, T *__restrict__ x, T alpha, double &dot,
                                       const T *__restrict__ h1 = nullptr, const T *__restrict__ h2b = nullptr,
-                                      const Sink &sink = Sink())
+                                      const Sink &sink = Sink(), const T *__restrict__ addv = nullptr)
 {
     static_assert(MODE <= 2, "plane tile: the plain and CG modes");
     constexpr int P = N + 1, P2 = P * P, P3 = P2 * P;
@@ -437,6 +546,7 @@ __device__ inline void ax_tile_planes(const LaneRows<T, N> &R, const T *__restri
                 // the previous iteration's x step, deferred to here where p is read anyway
                 st_stream(ld_stream(x + o) + alpha * pold, x + o);
                 v = ld_stream(invdiag + o) * ld_stream(in + o) + beta * pold;
+                if (MODE == 2 && addv) v += ld_stream(addv + o);  // as ax_tile's addv
                 st_stream(v, p + o);
             }
             uc[k] = v;

@@ -138,3 +138,38 @@ def test_gs_kind_validation(semlib):
         assert m.gs_kind() == ("auto", True)
     finally:
         m.close()
+
+
+def test_batched_slots_lattice_vs_plan(semlib, oracle_mod):
+    """Batched slots sum with the lattice kernel when their mesh does: the same
+    bits as with the plan, FP64 and mixed, and the oracle's true residual."""
+    print("case: batched slots, lattice vs plan gather-scatter", flush=True)
+    cases = []
+    for N, nel, per in ((5, (3, 4, 2), (0, 0, 0)), (7, (2, 3, 4), (0, 0, 1)), (9, (2, 2, 2), (1, 0, 0))):
+        V = None if any(per) else SI.jittered_box_vertices(nel, seed=N)
+        m = semlib.box_mesh(N, nel, vertices=V, periodic=per, with_fp32=True)
+        om = oracle_mod.OracleMesh(N, nel, vertices=V, periodic=per)
+        b = SI.uniform_global_values(om.nglob, 50 + N)[om.numbering()]
+        b[om.local_mask() == 1] = 0.0
+        cases.append((m, om, b))
+    B = semlib.Batch(max_slots=8)
+    try:
+        meshes = [c[0] for c in cases]
+        bs = [torch.from_numpy(c[2]).cuda() for c in cases]
+        for prec in ("fp64", "mixed"):
+            out = {}
+            for kind in ("auto", "plan"):
+                for m in meshes:
+                    m.set_gs_kind(kind)
+                xs, res = B.solve(meshes, bs, tol=1e-10, precision=prec)
+                out[kind] = (xs, [r.iterations for r in res])
+            assert out["auto"][1] == out["plan"][1], prec
+            for (m, om, b), xa, xp in zip(cases, out["auto"][0], out["plan"][0]):
+                assert torch.equal(xa, xp), (prec, m.N)
+                assert om.true_residual(b, xa.cpu().numpy()) <= 1e-10
+    finally:
+        for m in meshes:
+            m.set_gs_kind("auto")
+        B.close()
+        for m, _, _ in cases:
+            m.close()
