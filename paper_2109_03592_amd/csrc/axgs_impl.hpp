@@ -137,7 +137,7 @@ __global__ __launch_bounds__(512) void axgs_kernel(AxParams<T> a, AxgsLattice L)
             ax_tile_planes<T, N, MODE, HELM>(R, D, su, e, active, inblk, i, j, a.G, a.in, a.out, a.invdiag, a.p,
                                              beta, a.x, alpha, dot, a.h1, a.h2b, sink);
         else
-            ax_tile<T, N, MODE, 0, HELM>(R, D, su, e, active, inblk, i, j, a.G, a.in, a.out, a.invdiag, a.p, beta,
+            ax_tile<T, N, MODE, HELM>(R, D, su, e, active, inblk, i, j, a.G, a.in, a.out, a.invdiag, a.p, beta,
                                          a.x, alpha, dot, a.h1, a.h2b, nullptr, nullptr, sink);
         __syncthreads();
         if constexpr (K > 0) {

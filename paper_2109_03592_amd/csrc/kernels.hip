@@ -97,7 +97,7 @@ __global__ __launch_bounds__(512) void ax_kernel(AxParams<T> a)
             ax_tile_planes<T, N, MODE, HELM>(R, D, su, e, active, inblk, i, j, a.G, a.in, a.out, a.invdiag, a.p,
                                              beta, a.x, alpha, dot, a.h1, a.h2b);
         else
-            ax_tile<T, N, MODE, 0, HELM>(R, D, su, e, active, inblk, i, j, a.G, a.in, a.out, a.invdiag, a.p, beta,
+            ax_tile<T, N, MODE, HELM>(R, D, su, e, active, inblk, i, j, a.G, a.in, a.out, a.invdiag, a.p, beta,
                                          a.x, alpha, dot, a.h1, a.h2b,
                                          kCoarse ? szb + cur * kZB + slot * 8 : nullptr, a.cq);
         if constexpr (kCoarse) {

@@ -327,44 +327,6 @@ struct LaneRows {
 template <typename T, int N>
 constexpr int lane_rows_lds() { return LaneRows<T, N>::kDtLds ? (N + 1) * (N + 1) : 1; }
 
-// Position of point (i,j,k) inside an element's block of (N+1)^3 vector
-// entries.  LAYOUT 0 (element order): i + (N+1) j + (N+1)^2 k.  LAYOUT 1
-// (boundary first): the face k=0, the face k=N, then per interior plane the
-// ring of (i,j) with i or j in {0,N} -- together every point on the element
-// boundary -- and after them the interior points in element order.  The
-// gather-scatter only touches element-boundary points, which the second
-// layout keeps in the first 1 - ((N-1)/(N+1))^3 of each block.
-template <int N, int LAYOUT>
-struct ColumnIndex {
-    static constexpr int P = N + 1, P2 = P * P, R = 4 * N, I2 = (N - 1) * (N - 1);
-    static constexpr int NB = 2 * P2 + (N - 1) * R;  // boundary points per element
-    int ij, base, stride;
-    __device__ inline ColumnIndex(int i, int j)
-    {
-        ij = i + P * j;
-        if (LAYOUT == 1) {
-            const bool ring = i == 0 || i == N || j == 0 || j == N;
-            int rpos;
-            if (j == 0) rpos = i;
-            else if (j == N) rpos = P + 2 * (N - 1) + i;
-            else rpos = P + 2 * (j - 1) + (i == N ? 1 : 0);
-            const int ipos = (j - 1) * (N - 1) + (i - 1);
-            base = ring ? 2 * P2 - R + rpos : NB - I2 + ipos;
-            stride = ring ? R : I2;
-        } else {
-            base = ij;
-            stride = P2;
-        }
-    }
-    __device__ inline int off(int k) const
-    {
-        if (LAYOUT == 0) return ij + k * P2;
-        if (k == 0) return ij;
-        if (k == N) return P2 + ij;
-        return base + k * stride;
-    }
-};
-
 // HELM: Helmholtz form -- the three products of the combine step are scaled
 // by h1 at the point (Algorithm 1's h1) and h2*B*u is added to the output
 // (the h2 term of Eq. 4); h2b holds h2*B per point.
@@ -386,7 +348,7 @@ struct NoSink {
     template <typename T>
     __device__ void operator()(int, T) const {}
 };
-template <typename T, int N, int MODE, int LAYOUT = 0, bool HELM = false, typename Sink = NoSink>
+template <typename T, int N, int MODE, bool HELM = false, typename Sink = NoSink>
 __device__ inline void ax_tile(const LaneRows<T, N> &R, const T *__restrict__ D, T *su, int64_t e, bool active,
                                bool inblk, int i, int j, const T *__restrict__ G, const T *__restrict__ in,
                                T *__restrict__ out, const T *__restrict__ invdiag, T *__restrict__ p, T beta,
@@ -399,7 +361,6 @@ __device__ inline void ax_tile(const LaneRows<T, N> &R, const T *__restrict__ D,
     T *sr = su + P3;
     T *ss = sr + P3;
     const int ij = i + P * j;
-    const ColumnIndex<N, LAYOUT> ci(i, j);
     const int64_t eb = (active ? e : 0) * P3;
     T uc[P];
     constexpr bool kCoarse = MODE == 3 || MODE == 5;
@@ -418,7 +379,7 @@ __device__ inline void ax_tile(const LaneRows<T, N> &R, const T *__restrict__ D,
         for (int k = 0; k < P; ++k) {
             T v = 0;
             if (active) {
-                const int64_t o = eb + ci.off(k);
+                const int64_t o = eb + ij + k * P2;
                 const T pold = ld_stream(p + o);
                 // the previous iteration's x step, deferred to here where p is read anyway
                 st_stream(ld_stream(x + o) + alpha * pold, x + o);
@@ -438,7 +399,7 @@ __device__ inline void ax_tile(const LaneRows<T, N> &R, const T *__restrict__ D,
         }
     } else {
 #pragma unroll
-        for (int k = 0; k < P; ++k) uc[k] = active ? ld_stream(in + eb + ci.off(k)) : T(0);
+        for (int k = 0; k < P; ++k) uc[k] = active ? ld_stream(in + eb + ij + k * P2) : T(0);
     }
     if (inblk) {
 #pragma unroll
@@ -467,7 +428,7 @@ __device__ inline void ax_tile(const LaneRows<T, N> &R, const T *__restrict__ D,
         T ws = g2 * us + g4 * ur + g6 * ut;
         wt[k] = g3 * ut + g5 * ur + g6 * us;
         if (HELM) {
-            const T h = active ? ld_stream(h1 + eb + ci.off(k)) : T(0);
+            const T h = active ? ld_stream(h1 + eb + ij + k * P2) : T(0);
             wr *= h;
             ws *= h;
             wt[k] *= h;
@@ -485,10 +446,10 @@ __device__ inline void ax_tile(const LaneRows<T, N> &R, const T *__restrict__ D,
 #pragma unroll
         for (int l = 0; l < P; ++l)
             acc += R.dti(l) * sr[k * P2 + j * P + l] + R.dtj(l) * ss[k * P2 + l * P + i] + R.dk(D, l, k) * wt[l];
-        if (HELM && active) acc += ld_stream(h2b + eb + ci.off(k)) * uc[k];
+        if (HELM && active) acc += ld_stream(h2b + eb + ij + k * P2) * uc[k];
         constexpr bool kSink = !std::is_same<Sink, NoSink>::value;
         if constexpr (kSink) sink(k, acc);
-        else if (active) st_stream(acc, out + eb + ci.off(k));
+        else if (active) st_stream(acc, out + eb + ij + k * P2);
         if (MODE != 0) dot += (double)uc[k] * (double)acc;
     }
     if constexpr (std::is_same<Sink, NoSink>::value) __syncthreads();  // the LDS slot is rewritten by the next tile
