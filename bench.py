@@ -736,6 +736,12 @@ def main():
             "algorithmic_bytes_per_launch": ax_bytes, "ms_per_launch": ax_ms}
     roof["frac"] = roof["achieved"] / roof["peak"]
     step_bytes = ax_bytes + gs_bytes(info) + bytes_per_point(N, "update") * nL
+    # as run: with the gather-scatter folded into the update there is no gs
+    # pass; the iteration needs the operator's and the update's bytes only
+    gs_folded = mesh.gs_kind()[1] and N >= 3 and not fused["enabled"]
+    step_bytes_run = ax_bytes + bytes_per_point(N, "update") * nL + (0 if gs_folded else gs_bytes(info))
+    upd_name = f"pcg_update_gs_kernel<double, {N}>" if gs_folded else f"pcg_update_elem_kernel<double, {N}>"
+    upd_traffic = measured_traffic(upd_name, (nx, ny, nz), N, nL)
 
     out = {
         "metric": METRIC, "value": value, "unit": "GDOF/s", "n_gpus": 1, "steps": args.steps,
@@ -751,6 +757,11 @@ def main():
                  "fused_operator_gs": fused,
                  "hbm_frac_step": step_bytes / (t_steps / args.steps) / 1e9 / HBM_PEAK_GBS,
                  "algorithmic_bytes_per_step": step_bytes,
+                 "algorithmic_bytes_per_step_as_run": step_bytes_run,
+                 "bytes_per_point_as_run": step_bytes_run / nL,
+                 "hbm_frac_step_as_run": step_bytes_run / (t_steps / args.steps) / 1e9 / HBM_PEAK_GBS,
+                 "measured_bytes_per_step": (roof["traffic"] + upd_traffic
+                                             if roof["traffic"] is not None and upd_traffic is not None else None),
                  "ms_per_step_graph": t_graph / args.steps * 1e3,
                  "gdofs_graph": nG * args.steps / t_graph / 1e9},
     }
