@@ -113,7 +113,14 @@ __global__ __launch_bounds__(kBatchBlock) void batch_gs_kernel(const SlotDesc *s
     cptr<Item> items = (cptr<Item>)g.gs_items;
     const int64_t n = ((cptr<int64_t>)g.counts)[2];
     const int prec = prec_of<T>();
-    for (int64_t it = blockIdx.x; it < n; it += gridDim.x) {
+    // the workgroups of one XCD (blockIdx mod 8) walk one contiguous eighth of
+    // the items, so the lines that neighbouring chunks share stay in its L2
+    // (with fewer than 8 workgroups, each walks its own contiguous range)
+    const int64_t nb = gridDim.x, groups = nb < 8 ? nb : 8;
+    const int64_t grp = blockIdx.x % groups, kb = blockIdx.x / groups;
+    const int64_t per_g = nb / groups + (grp < nb % groups ? 1 : 0);  // workgroups of this group, >= 1
+    const int64_t lo = n * grp / groups, hi = n * (grp + 1) / groups;
+    for (int64_t it = lo + kb; it < hi; it += per_g) {
         const Item item = items[it];
         const SlotDesc sd = slots[item.slot];
         if (check_done && uniform_int(sd.st[prec].done)) continue;
