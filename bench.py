@@ -575,25 +575,27 @@ def batched_section(sem, torch, SI):
                      "gdofs_aggregate": dof_iters / dt / 1e9}
         log(f"batched {prec}: {len(meshes)} solves in {dt:.3f} s ({len(meshes) / dt:.1f} solves/s), "
             f"{ok} converged, aggregate {res[prec]['gdofs_aggregate']:.2f} GDOF/s")
-    # FP64 with the coarse term of Eq. 6 on the meshes of 512 elements or more
+    # FP64 and mixed with the coarse term of Eq. 6 on the meshes of 512 elements or more
     big = [m for m in meshes if m.E >= 512]
     t0 = time.perf_counter()
     for m in big:
         m.set_coarse(4, 0.05)
     t_coarse = time.perf_counter() - t0
-    B.solve(meshes, bs, tol=1e-10, poll_every=16)   # warm-up (graph capture)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    xs, rs = B.solve(meshes, bs, tol=1e-10, poll_every=16, raise_on_error=False)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ok = sum(r.ok and r.rel_residual <= 1e-10 for r in rs)
-    res["fp64_coarse"] = {"seconds": dt, "solves_per_s": len(meshes) / dt, "converged": ok,
-                          "coarse_meshes": len(big), "coarse_setup_s": t_coarse,
-                          "iterations_max": max(r.iterations for r in rs),
-                          "iterations_sum": sum(r.iterations for r in rs)}
-    log(f"batched fp64 + coarse term on {len(big)} meshes: {dt:.3f} s ({len(meshes) / dt:.1f} solves/s), "
-        f"{ok} converged, iterations max {res['fp64_coarse']['iterations_max']}")
+    for prec in ("fp64", "mixed"):
+        B.solve(meshes, bs, tol=1e-10, precision=prec, poll_every=16)   # warm-up (graph capture)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xs, rs = B.solve(meshes, bs, tol=1e-10, precision=prec, poll_every=16, raise_on_error=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ok = sum(r.ok and r.rel_residual <= 1e-10 for r in rs)
+        key = f"{prec}_coarse"
+        res[key] = {"seconds": dt, "solves_per_s": len(meshes) / dt, "converged": ok,
+                    "coarse_meshes": len(big), "coarse_setup_s": t_coarse,
+                    "iterations_max": max(r.iterations for r in rs),
+                    "iterations_sum": sum(r.iterations for r in rs)}
+        log(f"batched {prec} + coarse term on {len(big)} meshes: {dt:.3f} s ({len(meshes) / dt:.1f} solves/s), "
+            f"{ok} converged, iterations max {res[key]['iterations_max']}")
     for m in big:
         m.set_coarse(0)
     # steady CG iteration rate with every slot active (tolerances no run reaches)

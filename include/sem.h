@@ -348,14 +348,15 @@ sem_status sem_pcg_solve(sem_mesh *mesh, const double *b, double *x, const sem_s
  * the coarse part of <r, z> after the residual update, the prolongation in
  * the operator's prologue.  The coarse data and the Chebyshev solve stay FP64
  * in both precisions; an FP32 inner solve restricts its FP32 residual and adds
- * the rounded correction.  Batched solves (sem_batch_*): an FP64 slot of a
- * mesh with a coarse space takes the coarse term too, with its own coarse
- * vectors (several slots may share the mesh) -- its restriction, Chebyshev
- * solve and prolongation P z0 run per slot after the batched update, and the
- * batched operator adds P z0 in its p update, so the preconditioner is the
- * same M (prolongation summed in another order: the same to rounding); a
- * mixed-precision slot of such a mesh runs Jacobi.  The coarse space must not
- * change (sem_set_coarse) while the mesh has slots in a batch.
+ * the rounded correction.  Batched solves (sem_batch_*): a slot of a mesh
+ * with a coarse space takes the coarse term too, in its CG (FP64, or the
+ * FP32 inner iterations of a mixed slot), with its own coarse vectors
+ * (several slots may share the mesh) -- its restriction, Chebyshev solve
+ * (FP64) and prolongation P z0 (rounded to the CG's precision) run per slot
+ * after the batched update, and the batched operator adds P z0 in its p
+ * update, so the preconditioner is the same M (prolongation summed in
+ * another order: the same to rounding).  The coarse space must not change
+ * (sem_set_coarse) while the mesh has slots in a batch.
  */
 typedef struct {
     int64_t n_vertices;   /* element vertices (periodic images merged)          */
@@ -469,7 +470,7 @@ sem_status sem_proj_solve(sem_proj *proj, const double *b, double *x, const sem_
  * are replayed as one hipGraph.  Each slot's dot
  * products are summed from its own items in a fixed order, so a slot's result
  * does not depend on which other slots share the launches.  The
- * preconditioner is Jacobi, plus the coarse term of Eq. 6 for FP64 slots of
+ * preconditioner is Jacobi, plus the coarse term of Eq. 6 for the slots of
  * a mesh with a coarse space (sem_set_coarse; its per-slot phases are
  * launched slot by slot); meshes with the Helmholtz form or the Schwarz local
  * solves are refused (SEM_EUNSUPPORTED).

@@ -41,11 +41,12 @@ struct HostSlot {
     sem_status status = SEM_OK;
     void *buf = nullptr;     // slot-owned device vectors
     size_t buf_bytes = 0;
-    // coarse term (FP64 slots of a mesh with a coarse space): zc = P z0 and
+    // coarse term (slots of a mesh with a coarse space): zc = P z0 and
     // the coarse work vectors, in a second slot-owned buffer
     void *cbuf = nullptr;
     size_t cbuf_bytes = 0;
     CoarseWork cw{};
+    uint64_t serial = 0;     // unique per admission (keys the graphs that bake this slot's launches)
     std::chrono::steady_clock::time_point t0;
     double seconds = 0.0;
 };
@@ -68,8 +69,8 @@ struct Group {
     hipGraphExec_t graph = nullptr;
     int graph_k = 0;
     unsigned graph_orders = 0;    // orders the cached graph launches
-    // the coarse-term launches the cached graph holds: (slot, its zc buffer)
-    std::vector<std::pair<int, const void *>> graph_coarse;
+    // the coarse-term launches the cached graph holds: (slot, its admission serial)
+    std::vector<std::pair<int, uint64_t>> graph_coarse;
     GroupDev dev() const
     {
         GroupDev g;
@@ -105,6 +106,7 @@ struct sem_batch {
     hipStream_t capture = nullptr;
     std::vector<void *> allocations;
     std::multimap<size_t, void *> free_bufs;
+    uint64_t next_serial = 0;           // admissions so far (HostSlot::serial)
     std::vector<sem::PcgState> h_state;
 };
 
@@ -264,24 +266,31 @@ static void upload_desc(sem_batch *B, int id, hipStream_t s)
 // Chebyshev coarse solve with r0.z0 reduced into crz, and zc = masked P z0.
 // Launched per slot (the coarse vectors are small); the kernels of a
 // converged slot skip or rewrite its own buffers only.
-static void slot_coarse(sem_batch *B, int id, hipStream_t s)
+// at_start: the CG start -- the kernels run whatever the slot's state says
+// (a mixed slot's FP32 state still holds the previous inner solve's flag).
+static void slot_coarse(sem_batch *B, int id, hipStream_t s, bool at_start = false)
 {
     HostSlot &h = B->slots[id];
     const SlotDesc &d = B->h_desc[id];
     sem_mesh *m = h.mesh;
-    coarse_restrict_w<double>(m, h.cw, static_cast<const double *>(d.r[0]), m->inv64, s);
-    const int pairs = coarse_solve_w(m, h.cw, h.cw.dot, d.st, s);
+    const int p = d.zc_prec;  // the precision of the slot's CG: FP64, or FP32 inner iterations
+    if (p == 0) coarse_restrict_w<double>(m, h.cw, static_cast<const double *>(d.r[0]), m->inv64, s);
+    else coarse_restrict_w<float>(m, h.cw, static_cast<const float *>(d.r[1]), m->inv32, s);
+    const int pairs = coarse_solve_w(m, h.cw, h.cw.dot, at_start ? nullptr : d.st + p, s);
     SEM_HIP(launch_reduce_scalar(h.cw.dot, 2 * (int64_t)pairs, h.cw.rz, s));
-    coarse_prolong_w(m, h.cw, const_cast<double *>(d.zc), false, s);
+    if (p == 0) coarse_prolong_w(m, h.cw, static_cast<double *>(const_cast<void *>(d.zc)), false, s);
+    else coarse_prolong_w32(m, h.cw, static_cast<float *>(const_cast<void *>(d.zc)), s);
 }
 
-// the group's slots that take the coarse term in precision prec
-static std::vector<std::pair<int, const void *>> coarse_slots(const sem_batch *B, const Group &g, int prec)
+// the group's slots that take the coarse term in precision prec, with their
+// admission serials: a graph that baked a slot's coarse launches (its mesh's
+// coarse arrays, its work vectors) is replayed only for that same admission,
+// never for a later one that reuses the slot and its cached buffers
+static std::vector<std::pair<int, uint64_t>> coarse_slots(const sem_batch *B, const Group &g, int prec)
 {
-    std::vector<std::pair<int, const void *>> out;
-    if (prec != 0) return out;
+    std::vector<std::pair<int, uint64_t>> out;
     for (int32_t id : g.h_slots)
-        if (B->h_desc[id].zc) out.emplace_back(id, B->h_desc[id].zc);
+        if (B->h_desc[id].zc && B->h_desc[id].zc_prec == prec) out.emplace_back(id, B->slots[id].serial);
     return out;
 }
 
@@ -362,7 +371,7 @@ static void start_cg(sem_batch *B, const std::vector<int> &ids, int prec, hipStr
     Group &g = B->gres;
     group_build(B, g, ids, s);
     // the coarse term of the start residual; its r0.z0 joins rho
-    for (const auto &c : coarse_slots(B, g, prec)) slot_coarse(B, c.first, s);
+    for (const auto &c : coarse_slots(B, g, prec)) slot_coarse(B, c.first, s, true);
     SEM_HIP(batch_cg_init(prec, B->d_desc, g.dev(), launch_for(B, g), s));
 }
 
@@ -473,6 +482,8 @@ static void step_batch(sem_batch *B, int k, bool use_graph, hipStream_t s)
         Group &g = B->gres;
         group_build(B, g, to32, s);
         SEM_HIP(batch_to_fp32(B->d_desc, g.dev(), launch_for(B, g), s));
+        // the coarse term of the FP32 start residual; its r0.z0 joins rho
+        for (const auto &c : coarse_slots(B, g, 1)) slot_coarse(B, c.first, s, true);
         SEM_HIP(batch_cg_init(1, B->d_desc, g.dev(), launch_for(B, g), s));
     }
     // 3. CG iterations
@@ -579,11 +590,12 @@ static int admit_slot(sem_batch *B, sem_mesh *m, const double *b, double *x, con
     if (m->schwarz) fail(SEM_EUNSUPPORTED, "batched solves take Jacobi or Jacobi + coarse term (sem_set_schwarz is set)");
     const int id = free_slot_index(B);
     if (id < 0) fail(SEM_EBUDGET, "no free slot");
-    // FP64 slots of a mesh with a coarse space take the coarse term (mixed
-    // slots of such a mesh run Jacobi in their FP32 inner iterations)
-    const bool coarse = m->coarse != nullptr && o.precision == SEM_PREC_FP64;
+    // slots of a mesh with a coarse space take the coarse term in their CG
+    // (FP64, or the FP32 inner iterations of a mixed slot)
+    const bool coarse = m->coarse != nullptr;
+    const int zc_prec = o.precision == SEM_PREC_MIXED ? 1 : 0;
     const size_t need = slot_bytes(m, o.precision);
-    const size_t zc_bytes = ((size_t)m->h.nL * 8 + 255) / 256 * 256;
+    const size_t zc_bytes = ((size_t)m->h.nL * (zc_prec ? 4 : 8) + 255) / 256 * 256;
     const size_t cneed = coarse ? zc_bytes + (size_t)coarse_work_doubles(m->coarse, m->h.E) * 8 : 0;
     // a cached buffer of at least `bytes` (at most twice as large), else a new one
     auto acquire = [&](size_t bytes, size_t &have) -> void * {
@@ -625,6 +637,7 @@ static int admit_slot(sem_batch *B, sem_mesh *m, const double *b, double *x, con
     h.buf_bytes = have;
     h.cbuf = cbuf;
     h.cbuf_bytes = chave;
+    h.serial = ++B->next_serial;
     h.cw = coarse ? coarse_work_carve(m->coarse, m->h.E,
                                       reinterpret_cast<double *>(static_cast<char *>(cbuf) + zc_bytes))
                   : CoarseWork{};
@@ -675,8 +688,9 @@ static int admit_slot(sem_batch *B, sem_mesh *m, const double *b, double *x, con
     }
     d.st = B->d_state + 2 * id;
     d.scal = B->d_scal + 2 * id;
-    d.zc = coarse ? static_cast<const double *>(cbuf) : nullptr;
+    d.zc = coarse ? cbuf : nullptr;
     d.crz = coarse ? h.cw.rz : nullptr;
+    d.zc_prec = zc_prec;
     SEM_HIP(hipMemsetAsync(d.st, 0, 2 * sizeof(PcgState), s));
     // mixed slots start with a residual of the caller's x: zero it unless it
     // is the initial guess (FP64 slots without a guess zero it themselves)

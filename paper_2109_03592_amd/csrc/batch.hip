@@ -84,7 +84,7 @@ __global__ __launch_bounds__(512) void batch_ax_kernel(const SlotDesc *slots_, G
         } else {
             if (uniform_int(sd.st[prec].done) == 0) {
                 const T beta = (T)sd.st[prec].beta, alpha = (T)sd.st[prec].alpha;
-                const T *zc = prec == 0 ? reinterpret_cast<const T *>(sd.zc) : nullptr;
+                const T *zc = sd.zc_prec == prec ? static_cast<const T *>(sd.zc) : nullptr;
                 if constexpr (kPlanes)
                     ax_tile_planes<T, N, 2>(R, D, su, e, active, inblk, i, j, static_cast<const T *>(sd.G[prec]),
                                             static_cast<const T *>(sd.r[prec]), static_cast<T *>(sd.w[prec]),
@@ -375,7 +375,7 @@ __global__ __launch_bounds__(kBatchBlock) void batch_reduce_rho_kernel(SlotDesc 
     if (st->done) return;
     double s[2];
     slot_sum<2>(g.vec_partial, g.vec_first[sl], g.vec_count[sl], s);
-    if (prec == 0 && slots[sl].crz) s[1] += *slots[sl].crz;  // <r, P z0> = r0.z0
+    if (slots[sl].crz && slots[sl].zc_prec == prec) s[1] += *slots[sl].crz;  // <r, P z0> = r0.z0
     if (threadIdx.x == 0) {
         st->iters += 1;
         st->rr = s[0];
@@ -396,7 +396,7 @@ __global__ __launch_bounds__(kBatchBlock) void batch_reduce_init_kernel(SlotDesc
     PcgState *st = sd.st + prec;
     double s[2];
     slot_sum<2>(g.vec_partial, g.vec_first[sl], g.vec_count[sl], s);
-    if (prec == 0 && sd.crz) s[1] += *sd.crz;
+    if (sd.crz && sd.zc_prec == prec) s[1] += *sd.crz;
     if (threadIdx.x == 0) {
         st->rr = s[0];
         st->rho = s[1];

@@ -46,11 +46,14 @@ struct SlotDesc {
     double *scal;       // [0] <b,b>, [1] <r,r> of the last FP64 residual
     double stop2[2];    // stopping threshold on <r,r> per precision
     int limit[2];       // iteration limit per precision
-    // coarse term of Eq. 6 (FP64 CG of a mesh with a coarse space; else null):
-    // zc = masked P z0 of the current r, added in the operator's p update;
-    // crz = r0.z0, added to <r, z> after the slot's partials
-    const double *zc;
+    // coarse term of Eq. 6 (a mesh with a coarse space; else null): zc =
+    // masked P z0 of the current r, in the precision zc_prec of the slot's CG
+    // (0 FP64, 1 FP32 for a mixed slot's inner iterations), added in the
+    // operator's p update; crz = r0.z0, added to <r, z> after the slot's partials
+    const void *zc;
     const double *crz;
+    int zc_prec;
+    int pad3;
 };
 
 // counts[] of a group: [0] n_slots, [1] ax items, [2] gs items, [3] vec

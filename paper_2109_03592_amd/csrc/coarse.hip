@@ -288,17 +288,18 @@ __global__ __launch_bounds__(256) void cheb_kernel(int64_t nv, const int32_t *__
     }
 }
 
-// ADD: z += masked P z0; else z = masked P z0 (0 on masked nodes)
-template <bool ADD>
+// ADD: z += masked P z0; else z = masked P z0 (0 on masked nodes), rounded
+// to the precision of z
+template <bool ADD, typename TZ>
 __global__ __launch_bounds__(256) void prolong_kernel(int64_t E, int P, const int32_t *__restrict__ evert,
                                                       const double *__restrict__ z0, const double *__restrict__ qw,
-                                                      const double *__restrict__ inv, double *__restrict__ z)
+                                                      const double *__restrict__ inv, TZ *__restrict__ z)
 {
     const int P3 = P * P * P;
     const int64_t n = E * P3;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
         if (!(inv[q] > 0.0)) {
-            if (!ADD) z[q] = 0.0;
+            if (!ADD) z[q] = TZ(0);
             continue;
         }
         const int64_t e = q / P3;
@@ -307,7 +308,7 @@ __global__ __launch_bounds__(256) void prolong_kernel(int64_t E, int P, const in
         double s = 0.0;
 #pragma unroll
         for (int c = 0; c < 8; ++c) s += phi[c] * z0[evert[e * 8 + c]];
-        z[q] = ADD ? z[q] + s : s;
+        z[q] = ADD ? (TZ)(z[q] + s) : (TZ)s;
     }
 }
 
@@ -593,6 +594,7 @@ void coarse_restrict_w(sem_mesh *m, const CoarseWork &W, const T *r, const T *in
     SEM_HIP(hipGetLastError());
 }
 template void coarse_restrict_w<double>(sem_mesh *, const CoarseWork &, const double *, const double *, hipStream_t);
+template void coarse_restrict_w<float>(sem_mesh *, const CoarseWork &, const float *, const float *, hipStream_t);
 
 template <typename T>
 void coarse_restrict(sem_mesh *m, const T *r, const T *inv, hipStream_t s)
@@ -635,11 +637,20 @@ void coarse_prolong_w(sem_mesh *m, const CoarseWork &W, double *z, bool add, hip
     CoarseSpace *C = m->coarse;
     const int64_t nL = m->h.nL;
     if (add)
-        hipLaunchKernelGGL(prolong_kernel<true>, dim3(vec_blocks(nL)), dim3(256), 0, s, m->h.E, m->h.N + 1, C->evert,
-                           W.z0, C->qw, m->inv64, z);
-    else
-        hipLaunchKernelGGL(prolong_kernel<false>, dim3(vec_blocks(nL)), dim3(256), 0, s, m->h.E, m->h.N + 1,
+        hipLaunchKernelGGL((prolong_kernel<true, double>), dim3(vec_blocks(nL)), dim3(256), 0, s, m->h.E, m->h.N + 1,
                            C->evert, W.z0, C->qw, m->inv64, z);
+    else
+        hipLaunchKernelGGL((prolong_kernel<false, double>), dim3(vec_blocks(nL)), dim3(256), 0, s, m->h.E,
+                           m->h.N + 1, C->evert, W.z0, C->qw, m->inv64, z);
+    SEM_HIP(hipGetLastError());
+}
+
+void coarse_prolong_w32(sem_mesh *m, const CoarseWork &W, float *z, hipStream_t s)
+{
+    CoarseSpace *C = m->coarse;
+    const int64_t nL = m->h.nL;
+    hipLaunchKernelGGL((prolong_kernel<false, float>), dim3(vec_blocks(nL)), dim3(256), 0, s, m->h.E, m->h.N + 1,
+                       C->evert, W.z0, C->qw, m->inv64, z);
     SEM_HIP(hipGetLastError());
 }
 

@@ -52,6 +52,8 @@ void coarse_restrict_w(sem_mesh *m, const CoarseWork &W, const T *r, const T *in
 int coarse_solve_w(sem_mesh *m, const CoarseWork &W, double *dot_pairs, const PcgState *st, hipStream_t s);
 // add: z += masked P z0; else z = masked P z0
 void coarse_prolong_w(sem_mesh *m, const CoarseWork &W, double *z, bool add, hipStream_t s);
+// z = masked P z0 rounded to FP32 (a mixed-precision batched slot's correction)
+void coarse_prolong_w32(sem_mesh *m, const CoarseWork &W, float *z, hipStream_t s);
 
 // Builds the coarse space of the mesh's current operator (synchronises s).
 CoarseSpace *coarse_build(sem_mesh *m, int k, double frac, hipStream_t s);

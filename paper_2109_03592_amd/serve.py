@@ -206,7 +206,7 @@ class GpuEngine:
         self.tol, self.inner_tol, self.max_iter = tol, inner_tol, max_iter
         self.seed0 = seed0
         # meshes of at least coarse_min_elems elements (0: none) carry the
-        # coarse term of Eq. 6; their FP64 requests take it in the batch
+        # coarse term of Eq. 6; their requests (FP64 and mixed) take it in the batch
         self.coarse_min_elems = int(coarse_min_elems)
         self.coarse_steps, self.coarse_fraction = int(coarse_steps), float(coarse_fraction)
         self.meshes: Dict[Tuple, object] = {}
@@ -243,8 +243,8 @@ class GpuEngine:
         E = nel[0] * nel[1] * nel[2]
         nl = (N + 1) ** 3 * E
         extra = 0
-        if self._coarse(key) and not mixed:
-            extra = nl * 8 + E * 8 * 14   # P z0 and the slot's coarse vectors
+        if self._coarse(key):
+            extra = nl * (4 if mixed else 8) + E * 8 * 14   # P z0 and the slot's coarse vectors
         return int(nl * (8 * 3 + (16 if mixed else 0) + 8 + 8) + extra)   # slot vectors + b + x
 
     def resident(self, key) -> bool:
@@ -309,7 +309,7 @@ def serve_rates(rates: Sequence[float], duration: float = 10.0, max_requests: in
                 coarse_min_elems: int = 0) -> List[Dict]:
     """Serve Poisson arrival streams at each rate; returns one summary per rate
     (coarse_min_elems > 0: meshes of that many elements or more carry the
-    coarse term of Eq. 6, taken by their FP64 requests)."""
+    coarse term of Eq. 6, taken by their requests)."""
     import seeded_inputs as SI
     budget = int(budget_gb * 2 ** 30)
     # catalog keys = every (N, nel) the streams can draw

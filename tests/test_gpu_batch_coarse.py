@@ -9,7 +9,9 @@ carry a coarse space), against the oracle.
   different right-hand sides correctly, and each keeps the bits of its
   alone-solve among Jacobi and coarse co-residents, by graph replay and by
   plain launches;
-* a mixed-precision slot of a coarse mesh runs Jacobi and still converges;
+* mixed-precision slots of coarse meshes take the coarse term in their FP32
+  inner iterations (fewer iterations than Jacobi, the oracle's residual, and
+  their alone-solve bits among co-residents);
 * continuous admission: coarse slots admitted while others run keep their
   alone-solve bits.
 """
@@ -101,17 +103,34 @@ def test_batch_coarse_shared_mesh_and_bits(semlib, cases):
     B.close()
 
 
-def test_batch_coarse_mesh_mixed_slot_runs_jacobi(semlib, cases):
-    print("case: batched mixed slot of a coarse mesh", flush=True)
-    m, om, b = cases[0]
-    B = semlib.Batch(max_slots=4)
-    (x,), (r,) = B.solve([m], [torch.from_numpy(b).cuda()], tol=1e-10, precision="mixed")
-    assert r.ok and om.true_residual(b, x.cpu().numpy()) <= 1e-10
-    m.set_coarse(0)
-    (x2,), (r2,) = B.solve([m], [torch.from_numpy(b).cuda()], tol=1e-10, precision="mixed")
-    m.set_coarse(4, 0.05)
-    assert torch.equal(x, x2) and r.iterations == r2.iterations  # Jacobi either way
-    B.close()
+def test_batch_coarse_mixed_slots(semlib, cases):
+    """Mixed-precision slots of coarse meshes take the coarse term in their
+    FP32 inner iterations: they meet the oracle in about the inner iterations
+    of the single-mesh mixed solve with the coarse term, far fewer than with
+    Jacobi, and keep their alone-solve bits among co-residents."""
+    print("case: batched mixed slots with the coarse term", flush=True)
+    B = semlib.Batch(max_slots=16)
+    try:
+        for q in range(4):
+            m, om, b = cases[q]
+            bd = torch.from_numpy(b).cuda()
+            (x,), (r,) = B.solve([m], [bd], tol=1e-10, precision="mixed")
+            assert r.ok and om.true_residual(b, x.cpu().numpy()) <= 1e-10
+            _, r1 = m.solve(bd, tol=1e-10, precision="mixed")
+            m.set_coarse(0)
+            (xj,), (rj,) = B.solve([m], [bd], tol=1e-10, precision="mixed")
+            m.set_coarse(4, 0.05)
+            print(f"  N={m.N} E={m.E}: batch mixed + coarse {r.iterations} inner it, single-mesh {r1.iterations}, "
+                  f"batch mixed Jacobi {rj.iterations}", flush=True)
+            assert r.iterations < rj.iterations, (q, r.iterations, rj.iterations)
+            assert abs(r.iterations - r1.iterations) <= max(3, 0.1 * r1.iterations), (q, r.iterations, r1.iterations)
+            # among co-residents (FP64 and mixed, coarse and Jacobi): the same bits
+            meshes = [cases[4][0], m, cases[5][0], cases[(q + 1) % 4][0]]
+            bs = [torch.from_numpy(c[2]).cuda() for c in (cases[4], cases[q], cases[5], cases[(q + 1) % 4])]
+            xs, res = B.solve(meshes, bs, tol=1e-10, precision="mixed")
+            assert res[1].iterations == r.iterations and torch.equal(xs[1], x), q
+    finally:
+        B.close()
 
 
 def test_batch_coarse_continuous_admission(semlib, cases):
@@ -150,7 +169,7 @@ def test_batch_coarse_continuous_admission(semlib, cases):
 def test_serving_with_coarse_term(semlib):
     """The serving loop with the coarse term on its larger catalog meshes:
     every request of a short Poisson stream completes with a true 1e-10
-    residual (the FP64 ones of those meshes through the batched coarse term)."""
+    residual (those of the larger meshes through the batched coarse term)."""
     print("case: serving loop with the coarse term", flush=True)
     from paper_2109_03592_amd.serve import serve_rates
     res = serve_rates([100.0], duration=1.5, max_requests=150, drain_limit=30.0, max_slots=32, budget_gb=8.0,
@@ -159,3 +178,40 @@ def test_serving_with_coarse_term(semlib):
     r = res[0]
     assert r["failed"] == 0 and r["unfinished"] == 0 and r["refused"] == 0, r
     assert r["completed"] == r["requests"] > 50 and r["coarse_min_elems"] == 64
+
+
+def test_batch_coarse_slot_reuse_across_meshes(semlib, oracle_mod):
+    """A slot and its cached buffers reused by a later admission on another
+    coarse mesh (the first mesh already closed): the later solve must not
+    replay the graph captured for the earlier admission -- each solve meets
+    the oracle and equals its solve in a fresh batch, FP64 and mixed."""
+    print("case: batched coarse slot reuse across meshes", flush=True)
+    B = semlib.Batch(max_slots=8)
+    try:
+        for nel_a, nel_b in (((7, 7, 6), (7, 7, 7)), ((5, 5, 4), (6, 6, 6))):
+            ms = {}
+            for nel in (nel_a, nel_b):
+                V = SI.jittered_box_vertices(nel, seed=sum(nel))
+                m = semlib.box_mesh(5, nel, vertices=V, with_fp32=True)
+                om = oracle_mod.OracleMesh(5, nel, vertices=V)
+                b = SI.uniform_global_values(om.nglob, 80 + sum(nel))[om.numbering()]
+                b[om.local_mask() == 1] = 0.0
+                m.set_coarse(4, 0.05)
+                ms[nel] = (m, om, b)
+            for prec in ("fp64", "mixed"):
+                m, om, b = ms[nel_a]
+                for sc in (0.5, 1.0):
+                    (xa,), (ra,) = B.solve([m], [torch.from_numpy(b * sc).cuda()], tol=1e-10, precision=prec)
+                    assert ra.ok and om.true_residual(b * sc, xa.cpu().numpy()) <= 1e-10
+            ms[nel_a][0].close()
+            m, om, b = ms[nel_b]
+            for prec in ("fp64", "mixed"):
+                (xb,), (rb,) = B.solve([m], [torch.from_numpy(b).cuda()], tol=1e-10, precision=prec)
+                assert rb.ok and om.true_residual(b, xb.cpu().numpy()) <= 1e-10, (nel_b, prec)
+                F = semlib.Batch(max_slots=2)
+                (xf,), (rf,) = F.solve([m], [torch.from_numpy(b).cuda()], tol=1e-10, precision=prec)
+                F.close()
+                assert rb.iterations == rf.iterations and torch.equal(xb, xf), (nel_b, prec)
+            m.close()
+    finally:
+        B.close()
