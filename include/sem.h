@@ -265,12 +265,25 @@ sem_status sem_ax_noalloc(sem_mesh *mesh, int dtype, const void *u, void *w, dou
 /* w = mask(Q Q^T A_L u): sem_ax followed by sem_gs. */
 sem_status sem_axgs(sem_mesh *mesh, int dtype, const void *u, void *w, void *stream);
 
-/* b = mask(Q Q^T (B f)): weak-form right-hand side of a forcing f (device
- * FP64 E-vectors). */
+/* Weak-form right-hand side of the pressure Poisson problem (Eq. 5 on the
+ * spectral-element discretisation of section 2): b = mask(Q Q^T (B f)), where
+ * B is the diagonal mass matrix that Gauss-Lobatto-Legendre quadrature on
+ * the tensor-product Lagrange basis gives, B_e(i,j,k) = w_i w_j w_k |J|(i,j,k),
+ * and Q Q^T is the direct-stiffness summation of sem_gs.  f, b: device FP64
+ * E-vectors (n_local, the element-major local layout of sem_ax), caller-owned;
+ * f is read, b written (f == b is allowed: the scaling is pointwise).  Enqueued
+ * on `stream`, no synchronisation.  Errors: SEM_EINVAL (null argument),
+ * SEM_EHIP. */
 sem_status sem_mass(sem_mesh *mesh, const double *f, double *b, void *stream);
 
-/* u_local = mask(Q v): copy one value per global node (device FP64, n_global,
- * indexed by the glob_id of sem_export_maps) to every local copy. */
+/* u_local = mask(Q v): the scatter Q of section 2's split into global and
+ * element-local work, the transpose of the gather Q^T that sums a global
+ * node's copies.  It copies one value per global node to every local copy of
+ * that node and sets the copies on Dirichlet faces to 0.  v_global: device
+ * FP64, n_global entries indexed by the glob_id of sem_export_maps; u_local:
+ * device FP64 E-vector (n_local); both caller-owned and not overlapping.
+ * Enqueued on `stream`, no synchronisation.  Errors: SEM_EINVAL (null
+ * argument), SEM_EHIP. */
 sem_status sem_scatter(sem_mesh *mesh, const double *v_global, double *u_local, void *stream);
 
 /* Solve options.  sem_solve_opts_default fills tol=1e-10, max_iter=5000,
