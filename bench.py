@@ -128,11 +128,15 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(seconds_target: float = 10.0):
+def cpu_baseline(seconds_target: float = 10.0, solve_iterations=None):
     """The oracle, as it stands, on the host cores.  `value`: FP64 Jacobi-PCG
     iterations on a 48x48x8 slab of the pipe (the step's unit, GDOF/s) with
     every OpenMP thread; beside it the full 48x48x96 pipe's Ax+gs apply
-    (median of 3 on every thread, and one apply on 1 thread)."""
+    (median of 3 on every thread, and one apply on 1 thread).  With
+    `solve_iterations` (the FP64 solve's iteration count to 1e-10 on the
+    full pipe), the full-pipe FP64 solve is stated as iterations x the slab's
+    time per iteration scaled by the element count (96/8): a solve the oracle
+    would take hours to run."""
     from oracle import oracle as O
     import seeded_inputs as SI
     threads = O.threads(0)
@@ -154,6 +158,12 @@ def cpu_baseline(seconds_target: float = 10.0):
     _, res = om.pcg(b, tol=1e-30, max_iter=iters)
     dt = time.perf_counter() - t0
     out["value"] = om.nglob * res.iterations / dt / 1e9
+    if solve_iterations:
+        s_it = dt / res.iterations * (96 / nz)
+        out["full_pipe_fp64_solve_estimate"] = {
+            "iterations": int(solve_iterations), "s_per_iteration": s_it, "seconds": s_it * solve_iterations,
+            "basis": f"slab time per iteration (2 residual applies included) x 96/{nz} elements x the FP64 "
+                     f"Jacobi-PCG iteration count to 1e-10 of the full-pipe solve"}
     sample = (f"pipe 48x48x{nz} N=7 ({om.E} elements, {om.nglob} global nodes), {res.iterations} FP64 "
               f"Jacobi-PCG iterations in {dt:.2f} s (plus 2 residual applies) on {threads} threads; "
               f"OpenMP over elements, gather-scatter and dots sequential")
@@ -860,8 +870,13 @@ def main():
     # ---- CPU oracle on a bounded sample ---------------------------------------
     if not args.no_cpu:
         log("cpu baseline: oracle on a pipe slab ...")
-        out["cpu_baseline"] = cpu_baseline()
+        its = out.get("solve", {}).get("fp64", {}).get("iterations")
+        out["cpu_baseline"] = cpu_baseline(solve_iterations=its)
         cb = out["cpu_baseline"]
+        if "full_pipe_fp64_solve_estimate" in cb:
+            e = cb["full_pipe_fp64_solve_estimate"]
+            log(f"cpu baseline: full-pipe FP64 solve ~ {e['iterations']} it x {e['s_per_iteration']:.2f} s "
+                f"= {e['seconds'] / 3600:.1f} h")
         log(f"cpu baseline ({cb['cpu_model']}, {cb['cores']} threads): PCG {cb['value']:.4f} GDOF/s; "
             f"full-pipe Ax+gs {cb['axgs_full_pipe']['gdofs']:.4f} GDOF/s, 1 thread "
             f"{cb['axgs_full_pipe']['gdofs_1_thread']:.4f} GDOF/s")
