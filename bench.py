@@ -70,7 +70,8 @@ def gs_bytes(info, dtype_bytes: int = 8) -> float:
 # records their hash, and its traffic figure is used only while they match.
 KERNEL_SOURCES = ("paper_2109_03592_amd/csrc/operator.hpp", "paper_2109_03592_amd/csrc/kernels.hip",
                   "paper_2109_03592_amd/csrc/kernels.hpp", "paper_2109_03592_amd/csrc/axgs_impl.hpp",
-                  "paper_2109_03592_amd/csrc/axgs.hpp", "paper_2109_03592_amd/csrc/axgs64.hip")
+                  "paper_2109_03592_amd/csrc/axgs.hpp", "paper_2109_03592_amd/csrc/axgs64.hip",
+                  "paper_2109_03592_amd/csrc/lattice.hpp")
 TRAFFIC_PROFILES = {((48, 48, 96), 7): "profiles/hbm_traffic_pcg_pipe48x48x96_N7.txt",
                     ((48, 48, 48), 9): "profiles/hbm_traffic_pcg_pipe48x48x48_N9.txt"}
 

@@ -745,37 +745,6 @@ template hipError_t launch_gs<double>(const GsPlan &, const int32_t *, const int
 template hipError_t launch_gs<float>(const GsPlan &, const int32_t *, const int32_t *, float *, bool,
                                      const PcgState *, hipStream_t);
 
-bool gs_lattice_make(int N, const int nel[3], const int periodic[3], int faces, GsLattice &L)
-{
-    if (N < 1) return false;
-    L.N = N;
-    L.faces = faces;
-    int64_t ext[3], np[3];
-    for (int a = 0; a < 3; ++a) {
-        if (nel[a] < 1 || (periodic[a] && nel[a] < 2)) return false;
-        L.nel[a] = nel[a];
-        L.periodic[a] = periodic[a] ? 1 : 0;
-        ext[a] = (int64_t)nel[a] * N + (periodic[a] ? 0 : 1);
-        np[a] = periodic[a] ? nel[a] : (int64_t)nel[a] + 1;
-        if (ext[a] >= INT32_MAX) return false;
-        L.ext[a] = (int)ext[a];
-    }
-    const int64_t c_zplane = ext[0] * ext[1];
-    const int64_t c_yrow = ext[0] + (int64_t)(N - 1) * np[0];
-    const int64_t c_zint = np[1] * ext[0] + (int64_t)nel[1] * (N - 1) * np[0];
-    const int64_t c_layer = c_zplane + (int64_t)(N - 1) * c_zint;
-    const int64_t n = (int64_t)nel[2] * c_layer + (periodic[2] ? 0 : c_zplane);
-    // lanes decode positions with 32-bit arithmetic
-    if (n >= INT32_MAX) return false;
-    L.np0 = (int)np[0];
-    L.c_zplane = (int)c_zplane;
-    L.c_yrow = (int)c_yrow;
-    L.c_zint = (int)c_zint;
-    L.c_layer = (int)c_layer;
-    L.n_nodes = n;
-    return true;
-}
-
 template <typename T>
 hipError_t launch_gs_lattice(const GsLattice &L, T *v, const PcgState *st, hipStream_t s)
 {

@@ -57,7 +57,6 @@ int update_blocks(int64_t n);  // workgroups of the PCG update (one partial pair
 template <typename T>
 hipError_t launch_ax(int N, int mode, const AxParams<T> &a, hipStream_t s, int64_t *grid = nullptr);
 // false when the mesh has a periodic axis of one element or the counts do not fit
-bool gs_lattice_make(int N, const int nel[3], const int periodic[3], int faces, GsLattice &L);
 template <typename T>
 hipError_t launch_gs_lattice(const GsLattice &L, T *v, const PcgState *st, hipStream_t s);
 

@@ -123,92 +123,24 @@ __device__ inline void gs_id(int64_t t, int64_t n_sum, const int32_t *__restrict
     }
 }
 
-// Copies along one axis of the lattice coordinate X (see GsLattice): count,
-// element coordinate and GLL index of each, in ascending element coordinate;
-// `masked` when X lies on a Dirichlet face.
-struct AxisCopies {
-    int c;
-    int e[2], n[2];
-    bool masked;
-};
-
-__device__ inline AxisCopies axis_copies(int X, int N, int nel, int periodic, int ext, int lo_bit, int hi_bit)
-{
-    AxisCopies a;
-    a.masked = false;
-    const int q = X / N, r = X - q * N;
-    if (r != 0) {
-        a.c = 1; a.e[0] = q; a.n[0] = r; a.e[1] = q; a.n[1] = r;
-    } else if (X == 0) {
-        a.e[0] = 0; a.n[0] = 0;
-        if (periodic) {
-            a.c = 2; a.e[1] = nel - 1; a.n[1] = N;
-        } else {
-            a.c = 1; a.e[1] = 0; a.n[1] = 0; a.masked = lo_bit != 0;
-        }
-    } else if (!periodic && X == ext - 1) {
-        a.c = 1; a.e[0] = nel - 1; a.n[0] = N; a.e[1] = nel - 1; a.n[1] = N; a.masked = hi_bit != 0;
-    } else {
-        a.c = 2; a.e[0] = q - 1; a.n[0] = N; a.e[1] = q; a.n[1] = 0;
-    }
-    return a;
-}
-
-// Node t (in global-id order) of the face lattice: its copies summed from
-// 0 in ascending local index and written back, 0 on a Dirichlet node, an
-// unmasked single copy left alone (see GsLattice).  Requires t < L.n_nodes.
+// Node t of the face lattice (enumerated as GsLattice describes): its
+// copies summed from 0 in ascending local index and written back, 0 on a
+// Dirichlet node, an unmasked single copy left alone.  Requires
+// t < L.n_nodes.
 template <typename T>
 __device__ inline void gs_lattice_node(const GsLattice &L, int64_t t, T *__restrict__ v)
 {
-    const int N = L.N;
-    const unsigned ext0 = (unsigned)L.ext[0];
     unsigned X, Y, Z;
-    {
-        const unsigned u = (unsigned)t;
-        const unsigned zl = u / (unsigned)L.c_layer, r = u - zl * (unsigned)L.c_layer;
-        if (r < (unsigned)L.c_zplane) {
-            Z = zl * N;
-            Y = r / ext0;
-            X = r - Y * ext0;
-        } else {
-            const unsigned r1 = r - (unsigned)L.c_zplane;
-            const unsigned zo = r1 / (unsigned)L.c_zint, r2 = r1 - zo * (unsigned)L.c_zint;
-            Z = zl * N + 1 + zo;
-            const unsigned yl = r2 / (unsigned)L.c_yrow, r3 = r2 - yl * (unsigned)L.c_yrow;
-            if (r3 < ext0) {
-                Y = yl * N;
-                X = r3;
-            } else {
-                const unsigned r4 = r3 - ext0, yo = r4 / (unsigned)L.np0;
-                Y = yl * N + 1 + yo;
-                X = (r4 - yo * (unsigned)L.np0) * N;
-            }
-        }
-    }
-    const AxisCopies cx = axis_copies((int)X, N, L.nel[0], L.periodic[0], L.ext[0], L.faces & 1, L.faces & 2);
-    const AxisCopies cy = axis_copies((int)Y, N, L.nel[1], L.periodic[1], L.ext[1], L.faces & 4, L.faces & 8);
-    const AxisCopies cz = axis_copies((int)Z, N, L.nel[2], L.periodic[2], L.ext[2], L.faces & 16, L.faces & 32);
-    const bool masked = cx.masked || cy.masked || cz.masked;
-    const int cnt = cx.c * cy.c * cz.c;
-    if (!masked && cnt < 2) return;
-    const int P = N + 1;
-    const int64_t P3 = (int64_t)P * P * P;
-    // local indices in ascending order: z outer, then y, then x
-    int64_t a[8];
-#pragma unroll
-    for (int qz = 0; qz < 2; ++qz)
-#pragma unroll
-        for (int qy = 0; qy < 2; ++qy)
-#pragma unroll
-            for (int qx = 0; qx < 2; ++qx) {
-                const int64_t e = ((int64_t)cz.e[qz] * L.nel[1] + cy.e[qy]) * L.nel[0] + cx.e[qx];
-                a[(qz * 2 + qy) * 2 + qx] = e * P3 + ((int64_t)cz.n[qz] * P + cy.n[qy]) * P + cx.n[qx];
-            }
+    gs_lattice_pos(L, (unsigned)t, X, Y, Z);
+    const LatticeCopies c = gs_lattice_copies(L, X, Y, Z);
+    const AxisCopies &cx = c.cx, &cy = c.cy, &cz = c.cz;
+    const bool masked = c.masked;
+    if (!masked && c.cnt < 2) return;
     if (masked) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int qz = q >> 2, qy = (q >> 1) & 1, qx = q & 1;
-            if (qz < cz.c && qy < cy.c && qx < cx.c) v[a[q]] = T(0);
+            if (qz < cz.c && qy < cy.c && qx < cx.c) v[c.a[q]] = T(0);
         }
         return;
     }
@@ -216,7 +148,7 @@ __device__ inline void gs_lattice_node(const GsLattice &L, int64_t t, T *__restr
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int qz = q >> 2, qy = (q >> 1) & 1, qx = q & 1;
-        val[q] = (qz < cz.c && qy < cy.c && qx < cx.c) ? v[a[q]] : T(0);
+        val[q] = (qz < cz.c && qy < cy.c && qx < cx.c) ? v[c.a[q]] : T(0);
     }
     T s = T(0);
 #pragma unroll
@@ -227,7 +159,7 @@ __device__ inline void gs_lattice_node(const GsLattice &L, int64_t t, T *__restr
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int qz = q >> 2, qy = (q >> 1) & 1, qx = q & 1;
-        if (qz < cz.c && qy < cy.c && qx < cx.c) v[a[q]] = s;
+        if (qz < cz.c && qy < cy.c && qx < cx.c) v[c.a[q]] = s;
     }
 }
 

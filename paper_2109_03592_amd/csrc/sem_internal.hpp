@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/sem.h"
+#include "lattice.hpp"
 
 namespace sem {
 
@@ -76,36 +77,6 @@ struct GsPlan {
     int64_t n_ids;
 };
 
-// Gather-scatter on the element lattice.  Every mesh here is a lattice of
-// nel[0] x nel[1] x nel[2] hexahedra, and the global node at lattice position
-// (X, Y, Z) has its copies at the elements and GLL indices that the position
-// fixes: along each axis one copy inside an element (X mod N != 0), or the
-// two ends of neighbouring elements (X mod N == 0), or one end at a
-// non-periodic boundary.  The kernel therefore reads no plan: one lane per
-// node of the face lattice (some coordinate a multiple of N), met in global
-// id order (Z, then Y, then X), the order of the plan, so that the lines of
-// one element layer are touched close together in time.  Per element layer
-// in z: a z-plane of ext[0] ext[1] nodes, then N - 1 layers of
-// c_zint nodes each (rows Y mod N == 0 whole, other rows at X mod N == 0
-// only); per element row in y inside such a layer: ext[0] + (N - 1) np[0].
-// Copies are summed in ascending local index (nested z, y, x over each
-// axis's copies in ascending element), which is the plan's order whenever
-// a node's copies lie in distinct elements, i.e. every periodic axis has at
-// least two elements.  Masked (Dirichlet) nodes get 0 at every copy; an
-// unmasked node with one copy is left untouched, as the plan leaves it.
-struct GsLattice {
-    int N;
-    int nel[3];
-    int periodic[3];
-    int faces;          // Dirichlet face bits: axis a low face 1 << 2a, high face 1 << (2a + 1)
-    int ext[3];         // distinct lattice coordinates per axis
-    int np0;            // x coordinates that are multiples of N
-    int c_zplane;       // nodes of a z-plane: ext[0] ext[1]
-    int c_zint;         // face-lattice nodes of a z-layer off the planes
-    int c_yrow;         // ... of one element row in y of such a layer
-    int c_layer;        // c_zplane + (N - 1) c_zint
-    int64_t n_nodes;    // face-lattice nodes in all
-};
 
 // ---------------------------------------------------------------------------
 struct DeviceBuf {
