@@ -408,7 +408,8 @@ constexpr bool plane_tile() { return plane_tile_use(N, MODE, (int)sizeof(T)); }
 // derivatives; the t-direction part of the transposed derivative is
 // accumulated in registers as the planes pass.  Two barriers per plane; the
 // plane loop is not unrolled (unrolled, the compiler hoists every plane's
-// factor loads above the barriers and spills).  The caller provides the LDS
+// factor loads above the barriers and spills); instead the factors of the
+// next plane are loaded one plane ahead.  The caller provides the LDS
 // slot of this lane's element (3 (N+1)^2 values at least).  Sink as for
 // ax_tile: outputs go to sink(k, w) in ascending k once all planes have
 // passed, and the tile then ends without the trailing barrier.  addv as for
@@ -452,8 +453,19 @@ __device__ inline void ax_tile_planes(const LaneRows<T, N> &R, const T *__restri
     T acc[P];
 #pragma unroll
     for (int k = 0; k < P; ++k) acc[k] = 0;
+    // the factors of plane k + 1 are loaded while plane k is worked on, so
+    // that their latency overlaps a whole plane's barriers and LDS products
+    T gn[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) gn[c] = active ? ld_stream(Ge + c * P3) : T(0);
 #pragma unroll 1
     for (int k = 0; k < P; ++k) {
+        const T g1 = gn[0], g2 = gn[1], g3 = gn[2], g4 = gn[3], g5 = gn[4], g6 = gn[5];
+        if (active && k + 1 < P) {
+            const T *g = Ge + (k + 1) * P2;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) gn[c] = ld_stream(g + c * P3);
+        }
         T uk = uc[0];
 #pragma unroll
         for (int l = 1; l < P; ++l) uk = l == k ? uc[l] : uk;
@@ -465,12 +477,6 @@ __device__ inline void ax_tile_planes(const LaneRows<T, N> &R, const T *__restri
             ur += R.di(l) * su[j * P + l];
             us += R.dj(l) * su[l * P + i];
             ut += R.dk(D, k, l) * uc[l];
-        }
-        T g1 = 0, g2 = 0, g3 = 0, g4 = 0, g5 = 0, g6 = 0;
-        if (active) {
-            const T *g = Ge + k * P2;
-            g1 = ld_stream(g + 0 * P3); g2 = ld_stream(g + 1 * P3); g3 = ld_stream(g + 2 * P3);
-            g4 = ld_stream(g + 3 * P3); g5 = ld_stream(g + 4 * P3); g6 = ld_stream(g + 5 * P3);
         }
         T wr = g1 * ur + g4 * us + g5 * ut;
         T ws = g2 * us + g4 * ur + g6 * ut;
