@@ -152,9 +152,10 @@ sem_status sem_load_geometry(sem_mesh *mesh, const double *G, const double *B, v
  * workgroups (grid > 0; 0 keeps the default of 16 per compute unit).  Results
  * of sem_ax / sem_axgs do not depend on it; CG dot products do at rounding
  * level (their partial sums follow the workgroups).  Setting it applies to
- * the FP64 and FP32 operators; by default each precision has its own count
- * (the one that fills 64-lane waves best).  sem_get_operator_config reads the
- * FP64 one. */
+ * the FP64 and FP32 operators, plain and CG; by default each precision has
+ * its own count (the one that fills 64-lane waves best; for the FP64 plain
+ * operator at N = 9 the measured best, five, while the CG operator keeps
+ * one).  sem_get_operator_config reads the FP64 CG one. */
 sem_status sem_set_operator_config(sem_mesh *mesh, int epw, int grid);
 sem_status sem_get_operator_config(const sem_mesh *mesh, int *epw, int *grid);
 

@@ -131,6 +131,7 @@ struct sem_mesh {
     double *scal = nullptr;          // small device scratch for norms
     int ax_epw = 1;                  // elements per workgroup of the FP64 operator
     int ax_epw32 = 1;                // ... of the FP32 operator
+    int ax_epw_plain = 1;            // ... of the FP64 plain operator (modes 0, 1)
     int ax_grid_cap = 4096;          // persistent operator grid
     std::vector<hipEvent_t> events;  // profiling event pool
     hipStream_t capture_stream = nullptr;
