@@ -541,7 +541,7 @@ static void enqueue_iterations(sem_mesh *m, int k, hipStream_t s, Profiler *prof
     AxgsShape *fused = mode == 2 ? axgs_shape<T>(m) : nullptr;
     // Jacobi on a lattice mesh: the update sums w's copies itself
     const bool update_gs = mode == 2 && !fused && !coarse && !schwarz && m->h.N >= 3 && m->gs_lattice_ok &&
-                           m->gs_kind == SEM_GS_AUTO;
+                           m->gs_kind == SEM_GS_AUTO && m->h.nL < INT32_MAX;
     for (int it = 0; it < k; ++it) {
         if (prof) prof->mark(s);
         int64_t axb = 0;

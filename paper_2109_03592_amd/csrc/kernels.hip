@@ -346,34 +346,61 @@ __global__ __launch_bounds__(256) void pcg_update_elem_kernel(int64_t E, const P
     block_reduce_store<2>(v, partial, 2);
 }
 
-// Copies along one axis of element coordinate c, GLL index n (see
-// GsLattice), in ascending element coordinate; `masked` on a Dirichlet face.
+// The copies of a face node along one axis, for an element at coordinate c
+// of nel: on its low face (GLL index 0) and on its high face (index N), as
+// in GsLattice: count, and per copy the element offset from c and the GLL
+// index, in ascending element coordinate; `masked` on a Dirichlet face.
+// Off the faces a node has one copy, itself.
+struct AxisSide {
+    int c;
+    int de[2], n[2];
+    bool masked;
+};
+struct ElemAxis {
+    AxisSide lo, hi;
+};
 template <int N>
-__device__ inline AxisCopies elem_axis_copies(int c, int n, int nel, int periodic, int lo_bit, int hi_bit)
+__device__ inline ElemAxis elem_axis(int c, int nel, int periodic, int lo_bit, int hi_bit)
 {
-    AxisCopies a;
-    a.masked = false;
-    a.c = 1;
-    a.e[0] = a.e[1] = c;
-    a.n[0] = a.n[1] = n;
-    if (n == 0) {
-        if (c > 0) {
-            a.c = 2; a.e[0] = c - 1; a.n[0] = N; a.e[1] = c; a.n[1] = 0;
-        } else if (periodic) {
-            a.c = 2; a.e[0] = 0; a.n[0] = 0; a.e[1] = nel - 1; a.n[1] = N;
-        } else {
-            a.masked = lo_bit != 0;
-        }
-    } else if (n == N) {
-        if (c < nel - 1) {
-            a.c = 2; a.e[0] = c; a.n[0] = N; a.e[1] = c + 1; a.n[1] = 0;
-        } else if (periodic) {
-            a.c = 2; a.e[0] = 0; a.n[0] = 0; a.e[1] = nel - 1; a.n[1] = N;
-        } else {
-            a.masked = hi_bit != 0;
-        }
+    ElemAxis a;
+    a.lo.masked = a.hi.masked = false;
+    if (c > 0) {
+        a.lo.c = 2; a.lo.de[0] = -1; a.lo.n[0] = N; a.lo.de[1] = 0; a.lo.n[1] = 0;
+    } else if (periodic) {
+        a.lo.c = 2; a.lo.de[0] = 0; a.lo.n[0] = 0; a.lo.de[1] = nel - 1; a.lo.n[1] = N;
+    } else {
+        a.lo.c = 1; a.lo.de[0] = a.lo.de[1] = 0; a.lo.n[0] = a.lo.n[1] = 0; a.lo.masked = lo_bit != 0;
+    }
+    if (c < nel - 1) {
+        a.hi.c = 2; a.hi.de[0] = 0; a.hi.n[0] = N; a.hi.de[1] = 1; a.hi.n[1] = 0;
+    } else if (periodic) {
+        a.hi.c = 2; a.hi.de[0] = -(nel - 1); a.hi.n[0] = 0; a.hi.de[1] = 0; a.hi.n[1] = N;
+    } else {
+        a.hi.c = 1; a.hi.de[0] = a.hi.de[1] = 0; a.hi.n[0] = a.hi.n[1] = N; a.hi.masked = hi_bit != 0;
     }
     return a;
+}
+
+// This lane's copies along one axis (GLL index n): count, and per copy the
+// offset from the lane's own value (element offset x element stride + GLL
+// index change x index stride), in 32 bits (the caller keeps the E-vector
+// below 2^31 values).
+struct LaneAxis {
+    int c;
+    int d[2];
+    bool masked;
+};
+template <int N>
+__device__ inline LaneAxis lane_axis(const ElemAxis &a, int n, int estride, int nstride)
+{
+    LaneAxis l;
+    const AxisSide &sd = n == 0 ? a.lo : a.hi;
+    const bool face = n == 0 || n == N;
+    l.c = face ? sd.c : 1;
+    l.masked = face && sd.masked;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) l.d[q] = face ? sd.de[q] * estride + (sd.n[q] - n) * nstride : 0;
+    return l;
 }
 
 // The element-wise update with the gather-scatter of w folded in (lattice
@@ -383,7 +410,9 @@ __device__ inline AxisCopies elem_axis_copies(int c, int n, int nel, int periodi
 // gather-scatter pass disappears; the result is bit-identical to gather-
 // scatter then update.  Each block walks a contiguous chunk of elements
 // (blocks XCD-contiguous; update_chunk), so the neighbours whose faces it
-// reads are being read on the same XCD at about the same time.
+// reads are being read on the same XCD at about the same time.  A
+// wavefront's element is uniform across its lanes, so each axis's copy rule
+// is formed once per element and a lane only selects its side.
 template <typename T, int N>
 __global__ __launch_bounds__(256) void pcg_update_gs_kernel(GsLattice L, int64_t E, const PcgState *__restrict__ st,
                                                             T *__restrict__ r, const T *__restrict__ w,
@@ -398,11 +427,15 @@ __global__ __launch_bounds__(256) void pcg_update_gs_kernel(GsLattice L, int64_t
     int64_t e0, e1;
     update_chunk(E, e0, e1);  // the same elements per workgroup as pcg_update_elem_kernel: the same partials
     const int nx = L.nel[0], ny = L.nel[1];
+    const int sy = nx * P3, sz = nx * ny * P3;  // E P3 < 2^31 (launch_pcg_update_gs)
     double rr = 0.0, rz = 0.0;
     for (int64_t e = e0 + wave; e < e1; e += 4) {
         const int ex = (int)(e % nx);
         const int64_t eyz = e / nx;
         const int ey = (int)(eyz % ny), ez = (int)(eyz / ny);
+        const ElemAxis ax = elem_axis<N>(ex, nx, L.periodic[0], L.faces & 1, L.faces & 2);
+        const ElemAxis ay = elem_axis<N>(ey, ny, L.periodic[1], L.faces & 4, L.faces & 8);
+        const ElemAxis az = elem_axis<N>(ez, L.nel[2], L.periodic[2], L.faces & 16, L.faces & 32);
         const int64_t base = e * P3;
 #pragma unroll
         for (int q = lane; q < P3; q += 64) {
@@ -410,9 +443,9 @@ __global__ __launch_bounds__(256) void pcg_update_gs_kernel(GsLattice L, int64_t
             const int64_t o = base + q;
             T ws = w[o];
             if (i == 0 || i == N || j == 0 || j == N || k == 0 || k == N) {
-                const AxisCopies cx = elem_axis_copies<N>(ex, i, nx, L.periodic[0], L.faces & 1, L.faces & 2);
-                const AxisCopies cy = elem_axis_copies<N>(ey, j, ny, L.periodic[1], L.faces & 4, L.faces & 8);
-                const AxisCopies cz = elem_axis_copies<N>(ez, k, L.nel[2], L.periodic[2], L.faces & 16, L.faces & 32);
+                const LaneAxis cx = lane_axis<N>(ax, i, P3, 1);
+                const LaneAxis cy = lane_axis<N>(ay, j, sy, P);
+                const LaneAxis cz = lane_axis<N>(az, k, sz, P2);
                 if (cx.masked || cy.masked || cz.masked) {
                     ws = T(0);
                 } else if (cx.c * cy.c * cz.c > 1) {
@@ -420,8 +453,7 @@ __global__ __launch_bounds__(256) void pcg_update_gs_kernel(GsLattice L, int64_t
 #pragma unroll
                     for (int c8 = 0; c8 < 8; ++c8) {
                         const int qz = c8 >> 2, qy = (c8 >> 1) & 1, qx = c8 & 1;
-                        const int64_t ec = ((int64_t)cz.e[qz] * ny + cy.e[qy]) * nx + cx.e[qx];
-                        const int64_t a = ec * P3 + (cz.n[qz] * P + cy.n[qy]) * P + cx.n[qx];
+                        const int64_t a = o + (cz.d[qz] + cy.d[qy] + cx.d[qx]);
                         val[c8] = (qz < cz.c && qy < cy.c && qx < cx.c) ? w[a] : T(0);
                     }
                     T sum = T(0);
@@ -899,6 +931,8 @@ template <typename T>
 hipError_t launch_pcg_update_gs(const GsLattice &L, int N, int64_t E, const PcgState *st, T *r, const T *w,
                                 const T *inv, const uint8_t *mult, double *partial, hipStream_t s)
 {
+    // copy offsets are formed in 32 bits
+    if (E * (int64_t)(N + 1) * (N + 1) * (N + 1) >= INT32_MAX) return hipErrorInvalidValue;
     const int blocks = update_elem_blocks(E);
     switch (N) {
 #define SEM_UPDGS_CASE(n)                                                                                       \
