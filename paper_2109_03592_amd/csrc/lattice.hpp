@@ -47,16 +47,16 @@ __host__ __device__ inline uint32_t udiv(const UDiv &u, uint32_t n)
 // non-periodic boundary.  The kernel therefore reads no plan: one lane per
 // node of the face lattice (some coordinate a multiple of N), met element
 // layer by element layer in z.  Per layer zl: the z-plane Z = zl N (ext[0]
-// ext[1] nodes, x fastest); then per element row yl in y: the N - 1 y-rows
-// at Y = yl N off the z-planes (ext[0] nodes each, x fastest), followed,
-// while yl < nel[1], by the x-face nodes of the element row (zl, yl) that
-// lie off both (X mod N == 0, Y and Z not) face by face: per x-face q its
-// (N - 1)^2 nodes with y fastest, so that consecutive lanes read consecutive
-// rows of the two elements that share the face and the next face's lanes
-// the other end of the same rows, while the y-rows just before touch the
-// neighbouring rows of the same elements.  Copies are summed in ascending
-// local index (nested z,
-// y, x over each axis's copies in ascending element), which is the plan's
+// ext[1] nodes, x fastest); then per element row yl in y: the N - 1 rows
+// Y = yl N, Z = zl N + 1 .. zl N + N - 1 (ext[0] nodes each, x fastest),
+// followed, while yl < nel[1], by the x-face nodes of the element row
+// (zl, yl) that lie off both (X mod N == 0, Y and Z not) face by face: per
+// x-face q its (N - 1)^2 nodes with y fastest, so that consecutive lanes
+// read consecutive rows of the two elements that share the face and the next
+// face's lanes the other end of the same rows, while the y-rows just before
+// touch the neighbouring rows of the same elements.  Copies are summed in
+// ascending local index (nested z, y, x over each axis's copies in
+// ascending element), which is the plan's
 // order whenever a node's copies lie in distinct elements, i.e. every
 // periodic axis has at least two elements.  Masked (Dirichlet) nodes get 0
 // at every copy; an unmasked node with one copy is left untouched, as the
