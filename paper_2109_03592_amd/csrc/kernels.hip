@@ -346,63 +346,6 @@ __global__ __launch_bounds__(256) void pcg_update_elem_kernel(int64_t E, const P
     block_reduce_store<2>(v, partial, 2);
 }
 
-// The copies of a face node along one axis, for an element at coordinate c
-// of nel: on its low face (GLL index 0) and on its high face (index N), as
-// in GsLattice: count, and per copy the element offset from c and the GLL
-// index, in ascending element coordinate; `masked` on a Dirichlet face.
-// Off the faces a node has one copy, itself.
-struct AxisSide {
-    int c;
-    int de[2], n[2];
-    bool masked;
-};
-struct ElemAxis {
-    AxisSide lo, hi;
-};
-template <int N>
-__device__ inline ElemAxis elem_axis(int c, int nel, int periodic, int lo_bit, int hi_bit)
-{
-    ElemAxis a;
-    a.lo.masked = a.hi.masked = false;
-    if (c > 0) {
-        a.lo.c = 2; a.lo.de[0] = -1; a.lo.n[0] = N; a.lo.de[1] = 0; a.lo.n[1] = 0;
-    } else if (periodic) {
-        a.lo.c = 2; a.lo.de[0] = 0; a.lo.n[0] = 0; a.lo.de[1] = nel - 1; a.lo.n[1] = N;
-    } else {
-        a.lo.c = 1; a.lo.de[0] = a.lo.de[1] = 0; a.lo.n[0] = a.lo.n[1] = 0; a.lo.masked = lo_bit != 0;
-    }
-    if (c < nel - 1) {
-        a.hi.c = 2; a.hi.de[0] = 0; a.hi.n[0] = N; a.hi.de[1] = 1; a.hi.n[1] = 0;
-    } else if (periodic) {
-        a.hi.c = 2; a.hi.de[0] = -(nel - 1); a.hi.n[0] = 0; a.hi.de[1] = 0; a.hi.n[1] = N;
-    } else {
-        a.hi.c = 1; a.hi.de[0] = a.hi.de[1] = 0; a.hi.n[0] = a.hi.n[1] = N; a.hi.masked = hi_bit != 0;
-    }
-    return a;
-}
-
-// This lane's copies along one axis (GLL index n): count, and per copy the
-// offset from the lane's own value (element offset x element stride + GLL
-// index change x index stride), in 32 bits (the caller keeps the E-vector
-// below 2^31 values).
-struct LaneAxis {
-    int c;
-    int d[2];
-    bool masked;
-};
-template <int N>
-__device__ inline LaneAxis lane_axis(const ElemAxis &a, int n, int estride, int nstride)
-{
-    LaneAxis l;
-    const AxisSide &sd = n == 0 ? a.lo : a.hi;
-    const bool face = n == 0 || n == N;
-    l.c = face ? sd.c : 1;
-    l.masked = face && sd.masked;
-#pragma unroll
-    for (int q = 0; q < 2; ++q) l.d[q] = face ? sd.de[q] * estride + (sd.n[q] - n) * nstride : 0;
-    return l;
-}
-
 // The element-wise update with the gather-scatter of w folded in (lattice
 // meshes, Jacobi iteration): a node on an element face sums its copies of w
 // itself -- from 0, in ascending local index, as the gather-scatter would --

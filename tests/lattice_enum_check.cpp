@@ -4,7 +4,8 @@
 // lattice, all of them are met, and the
 // copies of each node are exactly the local indices at its position, in
 // ascending order, with every element-face local index met once, and the
-// element layers in z come one after another.  Prints
+// element layers in z come one after another; and that the fused CG
+// update's per-element copy rule agrees with the lattice rule node by node.  Prints
 // "OK <cases>" or the first failure.
 #include <cstdio>
 #include <cstdlib>
@@ -90,6 +91,67 @@ static int check(int N, const int nel[3], const int per[3], int faces)
     return 0;
 }
 
+// The fused CG update's per-element copy rule (elem_axis, lane_axis) against
+// the lattice rule: for every element-face node, the same mask, the same
+// number of copies and the same offsets in the same order.
+template <int N>
+static int check_update_rule(const int nel[3], const int per[3], int faces)
+{
+    GsLattice L{};
+    if (!gs_lattice_make(N, nel, per, faces, L)) return 0;
+    constexpr int P = N + 1, P2 = P * P, P3 = P2 * P;
+    const int sy = nel[0] * P3, sz = nel[0] * nel[1] * P3;
+    long ext[3];
+    for (int a = 0; a < 3; ++a) ext[a] = (long)nel[a] * N + (per[a] ? 0 : 1);
+    for (int ez = 0; ez < nel[2]; ++ez)
+        for (int ey = 0; ey < nel[1]; ++ey)
+            for (int ex = 0; ex < nel[0]; ++ex) {
+                const ElemAxis ax = elem_axis<N>(ex, nel[0], per[0], faces & 1, faces & 2);
+                const ElemAxis ay = elem_axis<N>(ey, nel[1], per[1], faces & 4, faces & 8);
+                const ElemAxis az = elem_axis<N>(ez, nel[2], per[2], faces & 16, faces & 32);
+                const long e = ex + (long)nel[0] * (ey + (long)nel[1] * ez);
+                for (int k = 0; k < P; ++k)
+                    for (int j = 0; j < P; ++j)
+                        for (int i = 0; i < P; ++i) {
+                            if (!(i == 0 || i == N || j == 0 || j == N || k == 0 || k == N)) continue;
+                            const long o = e * P3 + i + (long)P * j + (long)P2 * k;
+                            const LaneAxis cx = lane_axis<N>(ax, i, P3, 1);
+                            const LaneAxis cy = lane_axis<N>(ay, j, sy, P);
+                            const LaneAxis cz = lane_axis<N>(az, k, sz, P2);
+                            unsigned pos[3] = {(unsigned)(ex * N + i), (unsigned)(ey * N + j), (unsigned)(ez * N + k)};
+                            for (int a = 0; a < 3; ++a)
+                                if (per[a]) pos[a] %= (unsigned)ext[a];
+                            const LatticeCopies c = gs_lattice_copies(L, pos[0], pos[1], pos[2]);
+                            const bool masked = cx.masked || cy.masked || cz.masked;
+                            const int cnt = cx.c * cy.c * cz.c;
+                            if (masked != c.masked || cnt != c.cnt)
+                                return fail_case("update rule: mask or count", N, nel, per, o);
+                            for (int q = 0; q < 8; ++q) {
+                                const int qz = q >> 2, qy = (q >> 1) & 1, qx = q & 1;
+                                if (!(qz < cz.c && qy < cy.c && qx < cx.c)) continue;
+                                const long a = o + (cz.d[qz] + cy.d[qy] + cx.d[qx]);
+                                if (a != c.a[q]) return fail_case("update rule: copy offset", N, nel, per, o);
+                            }
+                        }
+            }
+    return 0;
+}
+
+template <int N>
+static int check_update_rules(int &cases)
+{
+    const int sizes[][3] = {{1, 1, 1}, {2, 1, 3}, {3, 2, 2}, {2, 3, 4}};
+    for (const auto &nel : sizes)
+        for (int pm = 0; pm < 8; ++pm) {
+            const int per[3] = {pm & 1, (pm >> 1) & 1, (pm >> 2) & 1};
+            for (int faces : {0, 63, 0b010110, 0b101001}) {
+                if (check_update_rule<N>(nel, per, faces)) return 1;
+                ++cases;
+            }
+        }
+    return 0;
+}
+
 int main()
 {
     int cases = 0;
@@ -108,6 +170,9 @@ int main()
     const int big9[3] = {12, 12, 8};
     if (check(9, big9, pipe_per, 0b001111)) return 1;
     cases += 2;
+    if (check_update_rules<3>(cases) || check_update_rules<4>(cases) || check_update_rules<5>(cases) ||
+        check_update_rules<7>(cases) || check_update_rules<9>(cases) || check_update_rules<12>(cases))
+        return 1;
     std::printf("OK %d\n", cases);
     return 0;
 }
