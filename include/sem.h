@@ -164,7 +164,9 @@ sem_status sem_get_operator_config(const sem_mesh *mesh, int *epw, int *grid);
  * sem_mass, every solve and the mesh's batched slots (the kind at admission):
  *   SEM_GS_AUTO (default): on the element lattice -- a global node's copies
  *     follow from its lattice position, so no plan is read -- whenever every
- *     periodic axis has at least two elements; else the plan.
+ *     periodic axis has at least two elements; else the plan.  On a single
+ *     mesh of order 2..7 the nodes off the z-planes go through a kernel that
+ *     streams whole element rows (same sums, same bits).
  *   SEM_GS_PLAN: the CSR plan sorted by global id.
  * Both sum a node's copies in ascending local index, from 0, and set
  * Dirichlet nodes to 0 at every copy: results are bit-identical.  Changing

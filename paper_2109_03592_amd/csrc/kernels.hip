@@ -720,9 +720,177 @@ template hipError_t launch_gs<double>(const GsPlan &, const int32_t *, const int
 template hipError_t launch_gs<float>(const GsPlan &, const int32_t *, const int32_t *, float *, bool,
                                      const PcgState *, hipStream_t);
 
+// Row-streaming gather-scatter of the nodes off the z-planes (orders 2..7,
+// (N+1)^2 <= 64 lanes).  One wavefront per (element row yg in y, interior
+// plane k, element layer ez) walks the row along x.  Its lanes hold the N+1
+// rows of the lattice lines Y = yg N .. yg N + N - 1 at plane k of the
+// current element: slot 0 the row j = N of element row yg - 1 (the other
+// copy of the line Y = yg N), slots 1..N the rows j = 0..N-1 of element row
+// yg; lane (slot, i) holds GLL index i.  Rows are loaded and stored whole
+// (coalesced).  Every lane that holds a copy of a shared node forms the
+// node's sum itself from the copies' values (cross-lane shuffles), from 0 in
+// ascending local index -- y copies outer, x copies inner, as the lattice
+// rule orders them -- so all copies get the same bits as the per-node
+// kernel writes.  The x-face X = ex N is formed at step ex from the
+// previous element's i = N and the current element's i = 0; the previous
+// element's rows are then final and stored.  On a periodic x axis the face
+// X = 0 waits for the last element.  For a non-periodic y axis the group
+// yg = nel[1] holds only slot 0 (the top boundary line).
+template <typename T, int N>
+__device__ inline void gs_stream_wave(const GsLattice &L, int64_t wv, T *__restrict__ v)
+{
+    constexpr int P = N + 1, P2 = P * P, P3 = P2 * P;
+    const int nx = L.nel[0], ny = L.nel[1];
+    const bool px = L.periodic[0] != 0, py = L.periodic[1] != 0;
+    const int ngy = py ? ny : ny + 1;
+    const int yg = (int)(wv % ngy);
+    const int64_t rest = wv / ngy;
+    const int k = 1 + (int)(rest % (N - 1));
+    const int ez = (int)(rest / (N - 1));
+    const int lane = threadIdx.x & 63;
+    const int sl = lane / P, i = lane - sl * P;
+    bool act = lane < P2;
+    int eys = 0, js = 0;
+    if (sl == 0) {
+        js = N;
+        if (yg > 0) eys = yg - 1;
+        else if (py) eys = ny - 1;
+        else act = false;
+    } else {
+        js = sl - 1;
+        if (yg < ny) eys = yg;
+        else act = false;
+    }
+    if (!act) { eys = 0; js = 0; }
+    // the y copies of this lane's line, in ascending element order
+    int cy = 1, ys0 = sl, ys1 = sl;
+    bool ymask = false;
+    if (sl <= 1) {
+        const bool has0 = yg > 0 || py, has1 = yg < ny;
+        if (has0 && has1) {
+            cy = 2;
+            if (py && yg == 0) { ys0 = 1; ys1 = 0; }  // element row 0 before the wrapped last one
+            else { ys0 = 0; ys1 = 1; }
+        } else {
+            cy = 1; ys0 = ys1 = has1 ? 1 : 0;
+            ymask = has1 ? (L.faces & 4) != 0 : (L.faces & 8) != 0;
+        }
+    }
+    const bool yline = sl <= 1;
+    const int64_t rowoff = (int64_t)k * P2 + (int64_t)js * P + i;
+    const int64_t rowbase = ((int64_t)ez * ny + eys) * nx;  // element index of ex = 0 in this lane's row
+    auto addr = [&](int ex) { return (rowbase + ex) * P3 + rowoff; };
+    // sum over y copies (outer) and x copies (inner) of values drawn from
+    // lanes: x copy q takes register a (q = 0) or b (q = 1) at GLL index xi[q]
+    auto node_sum = [&](T a, T b, int cx, int xi0, int xi1) {
+        T s = T(0);
+#pragma unroll
+        for (int qy = 0; qy < 2; ++qy) {
+            const int ysl = qy == 0 ? ys0 : ys1;
+#pragma unroll
+            for (int qx = 0; qx < 2; ++qx) {
+                const int src = ysl * P + (qx == 0 ? xi0 : xi1);
+                const T va = __shfl(a, src, 64), vb = __shfl(b, src, 64);
+                if (qy < cy && qx < cx) s = s + (qx == 0 ? va : vb);
+            }
+        }
+        return s;
+    };
+    T first = T(0), prev = T(0);
+    T n1 = act ? v[addr(0)] : T(0);
+    T n2 = (act && nx > 1) ? v[addr(1)] : T(0);
+    for (int ex = 0; ex < nx; ++ex) {
+        T cur = n1;
+        n1 = n2;
+        if (act && ex + 2 < nx) n2 = v[addr(ex + 2)];
+        // the line nodes off the x-faces (1 <= i <= N-1): y copies only
+        T curn = cur;
+        {
+            const T sy = node_sum(cur, cur, 1, i, i);
+            if (yline && i >= 1 && i <= N - 1) {
+                if (ymask) curn = T(0);
+                else if (cy == 2) curn = sy;
+            }
+        }
+        if (ex > 0) {
+            // x-face X = ex N: copies (ex - 1, N) in prev, (ex, 0) in cur
+            const T sf = node_sum(prev, cur, 2, N, 0);
+            const T f = (yline && ymask) ? T(0) : sf;
+            if (i == 0) curn = f;
+            T prevn = prev;
+            if (i == N) prevn = f;
+            if (act) v[addr(ex - 1)] = prevn;
+        } else {
+            // X = 0: a boundary face, or on a periodic axis the wrap with the last element
+            const T sb = node_sum(cur, cur, 1, 0, 0);
+            if (!px && i == 0) {
+                if ((L.faces & 1) || (yline && ymask)) curn = T(0);
+                else if (yline && cy == 2) curn = sb;
+            }
+            first = cur;
+        }
+        prev = curn;
+    }
+    // the last face X = nx N
+    if (px) {
+        // copies (0, 0) in first (its raw value), (nx - 1, N) in prev
+        const T sw = node_sum(first, prev, 2, 0, N);
+        const T f = (yline && ymask) ? T(0) : sw;
+        if (i == N) prev = f;
+        if (act && i == 0) v[addr(0)] = f;
+    } else {
+        const T sb = node_sum(prev, prev, 1, N, N);
+        if (i == N) {
+            if ((L.faces & 2) || (yline && ymask)) prev = T(0);
+            else if (yline && cy == 2) prev = sb;
+        }
+    }
+    if (act) v[addr(nx - 1)] = prev;
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(256) void gs_stream_kernel(GsLattice L, GsLattice Lz, T *__restrict__ v,
+                                                        const PcgState *__restrict__ st, int64_t nwaves,
+                                                        unsigned sblocks)
+{
+    if (st && st->done) return;
+    const unsigned b = blockIdx.x;
+    if (b < sblocks) {
+        const int64_t wv = (int64_t)b * 4 + (threadIdx.x >> 6);
+        if (wv < nwaves) gs_stream_wave<T, N>(L, wv, v);
+        return;
+    }
+    // the z-planes: one lane per node, XCD-contiguous (sblocks is a multiple of 8)
+    const unsigned nb = gridDim.x - sblocks, bb = b - sblocks;
+    const unsigned per = nb / 8, rem = nb % 8, xcd = bb % 8, kb = bb / 8;
+    const unsigned lb = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + kb;
+    const int64_t t = (int64_t)lb * blockDim.x + threadIdx.x;
+    if (t < Lz.n_nodes) gs_lattice_node<T>(Lz, t, v);
+}
+
 template <typename T>
 hipError_t launch_gs_lattice(const GsLattice &L, T *v, const PcgState *st, hipStream_t s)
 {
+    if (L.N >= 2 && L.N <= 7) {
+        GsLattice Lz{};
+        if (!gs_lattice_make(L.N, L.nel, L.periodic, L.faces, Lz, true)) return hipErrorInvalidValue;
+        const int64_t ngy = L.periodic[1] ? L.nel[1] : L.nel[1] + 1;
+        const int64_t nwaves = ngy * (L.N - 1) * L.nel[2];
+        const int64_t sblocks = ((nwaves + 3) / 4 + 7) / 8 * 8;
+        const int64_t zblocks = (Lz.n_nodes + 255) / 256;
+        const dim3 grid((unsigned)(sblocks + zblocks));
+        switch (L.N) {
+#define SEM_GSS_CASE(n)                                                                                      \
+    case n:                                                                                                  \
+        hipLaunchKernelGGL((gs_stream_kernel<T, n>), grid, dim3(256), 0, s, L, Lz, v, st, nwaves,           \
+                           (unsigned)sblocks);                                                               \
+        break;
+            SEM_GSS_CASE(2) SEM_GSS_CASE(3) SEM_GSS_CASE(4) SEM_GSS_CASE(5) SEM_GSS_CASE(6) SEM_GSS_CASE(7)
+#undef SEM_GSS_CASE
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     const int64_t n = L.n_nodes;
     if (n <= 0) return hipSuccess;
     const int64_t blocks = (n + 255) / 256;

@@ -79,7 +79,10 @@ struct GsLattice {
     int64_t stride_e[3];  // offset of one element step along x, y, z
 };
 
-inline bool gs_lattice_make(int N, const int nel[3], const int periodic[3], int faces, GsLattice &L)
+// zplanes_only: enumerate the z-planes alone (the nodes with Z mod N == 0);
+// the rest is left to the row-streaming kernel.
+inline bool gs_lattice_make(int N, const int nel[3], const int periodic[3], int faces, GsLattice &L,
+                            bool zplanes_only = false)
 {
     if (N < 1) return false;
     L.N = N;
@@ -95,8 +98,8 @@ inline bool gs_lattice_make(int N, const int nel[3], const int periodic[3], int 
         L.ext[a] = (int)ext[a];
     }
     const int64_t c_zplane = ext[0] * ext[1];
-    const int64_t c_yrows = (int64_t)(N - 1) * ext[0];
-    const int64_t c_unit = c_yrows + np[0] * (N - 1) * (N - 1);
+    const int64_t c_yrows = zplanes_only ? 0 : (int64_t)(N - 1) * ext[0];
+    const int64_t c_unit = zplanes_only ? 0 : c_yrows + np[0] * (N - 1) * (N - 1);
     const int64_t c_layer = c_zplane + nel[1] * c_unit + (periodic[1] ? 0 : c_yrows);
     const int64_t n = (int64_t)nel[2] * c_layer + (periodic[2] ? 0 : c_zplane);
     // lanes decode positions with 32-bit arithmetic

@@ -8,7 +8,10 @@ copy is left untouched by both); FP64 results must equal the oracle's
 assembled sum on inputs without negative zeros.  Meshes span every
 periodicity pattern, Dirichlet face subsets (none, some, all), one element
 along a non-periodic axis, orders 1 to 12, and the pipe map; a periodic axis
-of one element takes the plan (the lattice kernel declines it).
+of one element takes the plan (the lattice kernel declines it).  At orders
+2 to 7 the single-mesh lattice kind runs the row-streaming kernel for the
+nodes off the z-planes, so these cases check it against the plan and the
+oracle too.
 """
 import numpy as np
 import pytest
