@@ -165,15 +165,20 @@ sem_status sem_get_operator_config(const sem_mesh *mesh, int *epw, int *grid);
  *   SEM_GS_AUTO (default): on the element lattice -- a global node's copies
  *     follow from its lattice position, so no plan is read -- whenever every
  *     periodic axis has at least two elements; else the plan.  On a single
- *     mesh of order 2..7 the nodes off the z-planes go through a kernel that
- *     streams whole element rows (same sums, same bits).
+ *     mesh of order 7 with at least 2048 element-row walks (the number of
+ *     element rows along x times N - 1 interior planes per element layer) the
+ *     nodes off the z-planes go through a kernel that streams whole element
+ *     rows (same sums, same bits).
  *   SEM_GS_PLAN: the CSR plan sorted by global id.
+ *   SEM_GS_STREAM: as SEM_GS_AUTO, with the row-streaming kernel at every
+ *     order 2..7 whatever the mesh size (for checking it; it is slower than
+ *     the per-node kernel on small meshes and at low orders).
  * Both sum a node's copies in ascending local index, from 0, and set
  * Dirichlet nodes to 0 at every copy: results are bit-identical.  Changing
  * the kind drops the captured CG iterations (re-captured on the next solve).
  * sem_get_gs_config returns the kind and whether the lattice kernel runs.
  * Errors: SEM_EINVAL (null mesh, unknown kind). */
-enum { SEM_GS_AUTO = 0, SEM_GS_PLAN = 1 };
+enum { SEM_GS_AUTO = 0, SEM_GS_PLAN = 1, SEM_GS_STREAM = 2 };
 sem_status sem_set_gs_config(sem_mesh *mesh, int kind);
 sem_status sem_get_gs_config(const sem_mesh *mesh, int *kind, int *lattice_in_use);
 

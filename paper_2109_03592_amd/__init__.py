@@ -155,8 +155,9 @@ class Mesh:
 
     def set_gs_kind(self, kind: str = "auto"):
         """Gather-scatter kernel: "auto" (the lattice kernel where the mesh
-        allows it) or "plan" (the CSR plan); both give the same bits."""
-        k = {"auto": 0, "plan": 1}.get(kind)
+        allows it), "plan" (the CSR plan) or "stream" (auto with the
+        row-streaming kernel at every order 2..7); all give the same bits."""
+        k = {"auto": 0, "plan": 1, "stream": 2}.get(kind)
         if k is None:
             raise ValueError(f"unknown gather-scatter kind {kind!r}")
         L.check(self._lib.sem_set_gs_config(self._h, k), "sem_set_gs_config")
@@ -165,7 +166,7 @@ class Mesh:
         """(kind, lattice kernel in use)."""
         k, on = C.c_int(), C.c_int()
         L.check(self._lib.sem_get_gs_config(self._h, C.byref(k), C.byref(on)), "sem_get_gs_config")
-        return ("auto", "plan")[k.value], bool(on.value)
+        return ("auto", "plan", "stream")[k.value], bool(on.value)
 
     def set_axgs_config(self, enable: bool = True, epw: int = 0, lines_per_wg: int = 0):
         """Fused operator and gather-scatter: on/off, elements per tile and

@@ -305,8 +305,8 @@ static int64_t enqueue_ax(sem_mesh *m, int mode, const T *in, T *out, hipStream_
 template <typename T>
 static void enqueue_gs(sem_mesh *m, T *v, const PcgState *st, hipStream_t s)
 {
-    if (m->gs_lattice_ok && m->gs_kind == SEM_GS_AUTO)
-        SEM_HIP(launch_gs_lattice<T>(m->gsl, v, st, s));
+    if (m->gs_lattice_ok && m->gs_kind != SEM_GS_PLAN)
+        SEM_HIP(launch_gs_lattice<T>(m->gsl, v, st, s, m->gs_kind == SEM_GS_STREAM));
     else
         SEM_HIP(launch_gs<T>(m->gsplan, m->gs_off, m->gs_idx, v, false, st, s));
 }
@@ -541,7 +541,7 @@ static void enqueue_iterations(sem_mesh *m, int k, hipStream_t s, Profiler *prof
     AxgsShape *fused = mode == 2 ? axgs_shape<T>(m) : nullptr;
     // Jacobi on a lattice mesh: the update sums w's copies itself
     const bool update_gs = mode == 2 && !fused && !coarse && !schwarz && m->h.N >= 3 && m->gs_lattice_ok &&
-                           m->gs_kind == SEM_GS_AUTO && m->h.nL < INT32_MAX;
+                           m->gs_kind != SEM_GS_PLAN && m->h.nL < INT32_MAX;
     for (int it = 0; it < k; ++it) {
         if (prof) prof->mark(s);
         int64_t axb = 0;
@@ -1214,7 +1214,8 @@ sem_status sem_set_gs_config(sem_mesh *m, int kind)
 {
     return guarded([&]() -> sem_status {
         if (!m) fail(SEM_EINVAL, "sem_set_gs_config: null mesh");
-        if (kind != SEM_GS_AUTO && kind != SEM_GS_PLAN) fail(SEM_EINVAL, "sem_set_gs_config: unknown kind");
+        if (kind != SEM_GS_AUTO && kind != SEM_GS_PLAN && kind != SEM_GS_STREAM)
+            fail(SEM_EINVAL, "sem_set_gs_config: unknown kind");
         if (kind != m->gs_kind) {
             drop_graphs(m, nullptr);  // captured iterations hold the old kernel
             m->gs_kind = kind;
@@ -1228,7 +1229,7 @@ sem_status sem_get_gs_config(const sem_mesh *m, int *kind, int *lattice_in_use)
     return guarded([&]() -> sem_status {
         if (!m) fail(SEM_EINVAL, "sem_get_gs_config: null mesh");
         if (kind) *kind = m->gs_kind;
-        if (lattice_in_use) *lattice_in_use = m->gs_lattice_ok && m->gs_kind == SEM_GS_AUTO;
+        if (lattice_in_use) *lattice_in_use = m->gs_lattice_ok && m->gs_kind != SEM_GS_PLAN;
         return SEM_OK;
     });
 }

@@ -670,7 +670,7 @@ static int admit_slot(sem_batch *B, sem_mesh *m, const double *b, double *x, con
     d.gs_n_ids = hm.gs_n_ids;
     // the mesh's gather-scatter kind: the lattice kernel (same bits as the plan) where it runs
     d.gsl = m->gsl;
-    d.gs_lattice = m->gs_lattice_ok && m->gs_kind == SEM_GS_AUTO ? 1 : 0;
+    d.gs_lattice = m->gs_lattice_ok && m->gs_kind != SEM_GS_PLAN ? 1 : 0;
     d.b = b;
     d.x64 = x;
     size_t off[7];

@@ -869,13 +869,17 @@ __global__ __launch_bounds__(256) void gs_stream_kernel(GsLattice L, GsLattice L
 }
 
 template <typename T>
-hipError_t launch_gs_lattice(const GsLattice &L, T *v, const PcgState *st, hipStream_t s)
+hipError_t launch_gs_lattice(const GsLattice &L, T *v, const PcgState *st, hipStream_t s, bool force_stream)
 {
-    if (L.N >= 2 && L.N <= 7) {
+    const int64_t ngy = L.periodic[1] ? L.nel[1] : L.nel[1] + 1;
+    const int64_t nwaves = ngy * (L.N - 1) * L.nel[2];
+    // measured: the row walks win at N = 7 once there are enough of them to
+    // fill the device; at lower orders most lanes of a wave are idle and on
+    // small meshes the walks are too few, and the per-node kernel is faster
+    const bool stream = L.N >= 2 && L.N <= 7 && (force_stream || (L.N == 7 && nwaves >= 2048));
+    if (stream) {
         GsLattice Lz{};
         if (!gs_lattice_make(L.N, L.nel, L.periodic, L.faces, Lz, true)) return hipErrorInvalidValue;
-        const int64_t ngy = L.periodic[1] ? L.nel[1] : L.nel[1] + 1;
-        const int64_t nwaves = ngy * (L.N - 1) * L.nel[2];
         const int64_t sblocks = ((nwaves + 3) / 4 + 7) / 8 * 8;
         const int64_t zblocks = (Lz.n_nodes + 255) / 256;
         const dim3 grid((unsigned)(sblocks + zblocks));
@@ -897,8 +901,8 @@ hipError_t launch_gs_lattice(const GsLattice &L, T *v, const PcgState *st, hipSt
     hipLaunchKernelGGL((gs_lattice_kernel<T>), dim3((unsigned)blocks), dim3(256), 0, s, L, v, st);
     return hipGetLastError();
 }
-template hipError_t launch_gs_lattice<double>(const GsLattice &, double *, const PcgState *, hipStream_t);
-template hipError_t launch_gs_lattice<float>(const GsLattice &, float *, const PcgState *, hipStream_t);
+template hipError_t launch_gs_lattice<double>(const GsLattice &, double *, const PcgState *, hipStream_t, bool);
+template hipError_t launch_gs_lattice<float>(const GsLattice &, float *, const PcgState *, hipStream_t, bool);
 
 int vec_blocks(int64_t n) { return grid_for(n, 256, 8192); }
 

@@ -58,7 +58,9 @@ template <typename T>
 hipError_t launch_ax(int N, int mode, const AxParams<T> &a, hipStream_t s, int64_t *grid = nullptr);
 // false when the mesh has a periodic axis of one element or the counts do not fit
 template <typename T>
-hipError_t launch_gs_lattice(const GsLattice &L, T *v, const PcgState *st, hipStream_t s);
+// force_stream: the row-streaming kernel at every order 2..7 (by default only
+// at N = 7 with at least 2048 row walks, where it is the faster one)
+hipError_t launch_gs_lattice(const GsLattice &L, T *v, const PcgState *st, hipStream_t s, bool force_stream = false);
 
 template <typename T>
 hipError_t launch_gs(const GsPlan &plan, const int32_t *off, const int32_t *idx, T *v, bool zero_only,

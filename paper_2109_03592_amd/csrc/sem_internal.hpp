@@ -106,7 +106,7 @@ struct sem_mesh {
     int32_t *gs_idx = nullptr;
     sem::GsPlan gsplan{};
     // lattice gather-scatter (no plan read), used in place of the plan when
-    // gs_lattice_ok and gs_kind == SEM_GS_AUTO
+    // gs_lattice_ok and gs_kind != SEM_GS_PLAN
     sem::GsLattice gsl{};
     int gs_lattice_ok = 0;
     int gs_kind = 0;

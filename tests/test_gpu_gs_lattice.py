@@ -8,10 +8,11 @@ copy is left untouched by both); FP64 results must equal the oracle's
 assembled sum on inputs without negative zeros.  Meshes span every
 periodicity pattern, Dirichlet face subsets (none, some, all), one element
 along a non-periodic axis, orders 1 to 12, and the pipe map; a periodic axis
-of one element takes the plan (the lattice kernel declines it).  At orders
-2 to 7 the single-mesh lattice kind runs the row-streaming kernel for the
-nodes off the z-planes, so these cases check it against the plan and the
-oracle too.
+of one element takes the plan (the lattice kernel declines it).  The
+"stream" kind runs the row-streaming kernel for the nodes off the z-planes
+at every order 2 to 7 (the default kind only on large order-7 meshes), so
+these cases check it against the plan, bit for bit, on every periodicity
+and Dirichlet set.
 """
 import numpy as np
 import pytest
@@ -62,9 +63,11 @@ def _check_against_plan(m, v):
         src = torch.from_numpy(v).to(device="cuda", dtype=dt)
         m.set_gs_kind("plan")
         ref = _bits(m.gs(src.clone()))
+        for kind in ("auto", "stream"):
+            m.set_gs_kind(kind)
+            got = _bits(m.gs(src.clone()))
+            assert np.array_equal(got, ref), (dt, kind, int(np.count_nonzero(got != ref)))
         m.set_gs_kind("auto")
-        got = _bits(m.gs(src.clone()))
-        assert np.array_equal(got, ref), (dt, int(np.count_nonzero(got != ref)))
 
 
 @pytest.mark.parametrize("N,nel,per,faces", CASES)
@@ -104,15 +107,17 @@ def test_lattice_gs_pipe_and_solve(semlib, oracle_mod):
         b[om.local_mask() == 1] = 0.0
         bd = torch.from_numpy(b).cuda()
         out = {}
-        for kind in ("plan", "auto"):
+        for kind in ("plan", "auto", "stream"):
             m.set_gs_kind(kind)
             for prec in ("fp64", "mixed"):
                 x, res = m.solve(bd, tol=1e-10, max_iter=5000, precision=prec)
                 assert res.ok
                 out[kind, prec] = (_bits(x), res.iterations)
-        for prec in ("fp64", "mixed"):
-            assert out["plan", prec][1] == out["auto", prec][1]
-            assert np.array_equal(out["plan", prec][0], out["auto", prec][0]), prec
+        m.set_gs_kind("auto")
+        for kind in ("auto", "stream"):
+            for prec in ("fp64", "mixed"):
+                assert out["plan", prec][1] == out[kind, prec][1]
+                assert np.array_equal(out["plan", prec][0], out[kind, prec][0]), (kind, prec)
         assert om.true_residual(b, out["auto", "fp64"][0].view(np.float64)) <= 1e-10
     finally:
         m.close()
@@ -137,6 +142,8 @@ def test_gs_kind_validation(semlib):
             m.set_gs_kind("atomic")
         m.set_gs_kind("plan")
         assert m.gs_kind() == ("plan", False)
+        m.set_gs_kind("stream")
+        assert m.gs_kind() == ("stream", True)
         m.set_gs_kind("auto")
         assert m.gs_kind() == ("auto", True)
     finally:
