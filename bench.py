@@ -249,6 +249,13 @@ def axgs_timing(mesh, info, N, torch, SI, stream, applies: int):
              "wall_s": wall, "timing": "median of per-apply events"}
         r["gs_kernel"] = "lattice" if mesh.gs_kind()[1] else "plan"
         if r["gs_kernel"] == "lattice":
+            # the library streams whole element rows off the z-planes at N = 7
+            # once there are 2048 row walks (element rows in y x interior planes)
+            nel, per = list(mesh.desc.nel), list(mesh.desc.periodic)
+            walks = (nel[1] if per[1] else nel[1] + 1) * (N - 1) * nel[2]
+            if N == 7 and walks >= 2048:
+                r["gs_kernel"] = "lattice, row-streaming off the z-planes"
+        if r["gs_kernel"] == "lattice":
             # the CSR plan's gather-scatter on the same vector, for comparison
             mesh.set_gs_kind("plan")
             for _ in range(3):
